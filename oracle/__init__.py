@@ -1,0 +1,307 @@
+"""FP64 CPU oracle for batched prox-linear SCP + CTCS + customized PIPG (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow reference implementation that the
+GPU library is checked against.  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import it; the GPU library never does, and the oracle never
+imports the GPU library.  The C source (``scp_oracle.c``) is compiled with gcc, without
+fast-math and without FMA contraction, into ``_scp_oracle.so`` next to it.
+
+Layouts (row-major float64 numpy arrays):
+  x0[B,15], xf[B,13], params[B,22], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+NX, NU, NP, NXF = 15, 4, 22, 13
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "scp_oracle.c")
+_SO = os.path.join(_HERE, "_scp_oracle.so")
+
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-D_POSIX_C_SOURCE=200809L", "-pthread"]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (idempotent unless ``force``)."""
+    if (not force and os.path.exists(_SO)
+            and os.path.getmtime(_SO) >= os.path.getmtime(_SRC)):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [
+        ("scp_iters_max", ctypes.c_int32), ("pipg_iters_max", ctypes.c_int32),
+        ("pipg_check_every", ctypes.c_int32), ("rk4_substeps", ctypes.c_int32),
+        ("power_iters_max", ctypes.c_int32), ("early_exit", ctypes.c_int32),
+        ("node_projections", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
+        ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
+        ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
+        ("power_buff", ctypes.c_double),
+        ("w_cost", ctypes.c_double), ("w_prox", ctypes.c_double), ("w_ep", ctypes.c_double),
+        ("omega", ctypes.c_double), ("rho", ctypes.c_double),
+        ("px", ctypes.c_double * NX), ("pu", ctypes.c_double * NU),
+    ]
+
+
+def make_settings(cfg):
+    """Build the oracle's settings struct from a plain dict of solver settings."""
+    s = Settings()
+    for name, _ in Settings._fields_:
+        if name in ("px", "pu", "pad"):
+            continue
+        setattr(s, name, cfg[name])
+    for i, v in enumerate(cfg["px"]):
+        s.px[i] = float(v)
+    for i, v in enumerate(cfg["pu"]):
+        s.pu[i] = float(v)
+    return s
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        S = ctypes.POINTER(Settings)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        sig = {
+            "orc_dynamics": [_D, _D, _D, _D],
+            "orc_jacobians": [_D, _D, _D, _D, _D],
+            "orc_constraints": [_D, _D, _D, _D],
+            "orc_discretize_interval": [_D, _D, _D, _D, _D, _D, c_double, c_int, _D, _D, _D, _D],
+            "orc_discretize": [c_int, _D, _D, _D, c_int, _D, _D, _D, _D],
+            "orc_init_guess": [c_int, _D, _D, _D, _D, _D],
+            "orc_build_qp": [S, _D, c_int, _D, _D, _D, _D, _D, _D, _D, _D,
+                             _D, _D, _D, _D, _D, _D, _D, _D, _D],
+            "orc_power": [S, c_int, _D, _D, _D, _I],
+            "orc_pipg": [S, c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, c_double,
+                         c_int, c_int, _D, _D, _D, _D, _D, _D],
+            "orc_solve_batch": [S, c_int, c_int, _D, _D, _D, _I, c_int, _D, _D, _D, _D, _I, _I,
+                                _I, _D, _D, _D],
+            "orc_solve_trace": [S, c_int, _D, _D, _D, _D, _D, _D, _I, c_int, _D],
+            "orc_lastiter_state": [S, c_int, _D, _D, _D, _D, _D, _D, _D],
+            "orc_iter_len": [c_int],
+            "orc_truncated_map": [S, c_int, _D, _D, _D, _D, _D, _D, _D, c_double, c_int, _D],
+            "orc_stopping": [c_int] + [_D] * 12 + [c_double, c_double],
+            "orc_project_node": [_D, _D, _D],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+        L.orc_power.restype = c_double
+        L.orc_pipg.restype = c_int
+        L.orc_solve_batch.restype = c_int
+        L.orc_iter_len.restype = c_int
+        L.orc_lastiter_state.restype = c_int
+        L.orc_stopping.restype = c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_D)
+
+
+def _p(a):
+    return a.ctypes.data_as(_D) if a is not None else ctypes.cast(None, _D)
+
+
+# ----------------------------------------------------------------------------- model ----
+def dynamics(x, u, p):
+    x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
+    f = np.zeros(NX)
+    lib().orc_dynamics(xp, up, pp, _p(f))
+    return f
+
+
+def jacobians(x, u, p):
+    x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
+    A = np.zeros((NX, NX)); B = np.zeros((NX, NU))
+    lib().orc_jacobians(xp, up, pp, _p(A), _p(B))
+    return A, B
+
+
+def constraints(x, u, p):
+    x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
+    g = np.zeros(7)
+    lib().orc_constraints(xp, up, pp, _p(g))
+    return g
+
+
+# ---------------------------------------------------------------------- discretization ----
+def discretize_interval(xk, uk, uk1, p, dtau, nsub, A0=None, B0=None):
+    """One interval; with A0/B0 given, the linear test model f = A0 x + B0 u is used."""
+    xk, a = _d(xk); uk, b = _d(uk); uk1, c = _d(uk1)
+    p = np.zeros(NP) if p is None else p
+    p, pp = _d(p)
+    A0c = None if A0 is None else np.ascontiguousarray(A0, dtype=np.float64)
+    B0c = None if B0 is None else np.ascontiguousarray(B0, dtype=np.float64)
+    xe = np.zeros(NX); A = np.zeros((NX, NX)); Bm = np.zeros((NX, NU)); Bp = np.zeros((NX, NU))
+    lib().orc_discretize_interval(a, b, c, pp, _p(A0c), _p(B0c), float(dtau), int(nsub),
+                                  _p(xe), _p(A), _p(Bm), _p(Bp))
+    return xe, A, Bm, Bp
+
+
+def discretize(K, xbar, ubar, p, nsub):
+    xbar, xp = _d(xbar); ubar, up = _d(ubar); p, pp = _d(p)
+    M = K - 1
+    xe = np.zeros((M, NX)); A = np.zeros((M, NX, NX))
+    Bm = np.zeros((M, NX, NU)); Bp = np.zeros((M, NX, NU))
+    lib().orc_discretize(K, xp, up, pp, int(nsub), _p(xe), _p(A), _p(Bm), _p(Bp))
+    return xe, A, Bm, Bp
+
+
+def init_guess(K, x0, xf, p):
+    x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
+    xb = np.zeros((K, NX)); ub = np.zeros((K, NU))
+    lib().orc_init_guess(K, a, b, c, _p(xb), _p(ub))
+    return xb, ub
+
+
+# ------------------------------------------------------------------------------ QP -------
+def build_qp(cfg, p, K, x0, xf, xbar, ubar, xend, A, Bm, Bp):
+    st = make_settings(cfg)
+    args = [_d(v) for v in (p, x0, xf, xbar, ubar, xend, A, Bm, Bp)]
+    M = K - 1
+    out = dict(Am=np.zeros((M, NX, NX)), Bm=np.zeros((M, NX, NU)), Bp=np.zeros((M, NX, NU)),
+               w=np.zeros((M, NX)), eps=np.zeros(M), umin=np.zeros((K, NU)),
+               umax=np.zeros((K, NU)), zi=np.zeros(NX), zf=np.zeros(NXF))
+    a = [x[1] for x in args]
+    lib().orc_build_qp(ctypes.byref(st), a[0], K, a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8],
+                       *[_p(out[k]) for k in ("Am", "Bm", "Bp", "w", "eps", "umin", "umax",
+                                              "zi", "zf")])
+    return out
+
+
+def power(cfg, qp):
+    st = make_settings(cfg)
+    K = qp["umin"].shape[0] if "umin" in qp else qp["Am"].shape[0] + 1
+    Am, a = _d(qp["Am"]); Bm, b = _d(qp["Bm"]); Bp, c = _d(qp["Bp"])
+    it = ctypes.c_int32(0)
+    sigma = lib().orc_power(ctypes.byref(st), K, a, b, c, ctypes.byref(it))
+    return sigma, it.value
+
+
+def zero_warm_start(K):
+    M = K - 1
+    return dict(x=np.zeros((K, NX)), u=np.zeros((K, NU)), mup=np.zeros((M, NX)),
+                mum=np.zeros((M, NX)), phi=np.zeros((M, NX)), th=np.zeros(M))
+
+
+def pipg(cfg, qp, sigma, jmax, check, ws=None, ref=None):
+    """Run PIPG_custom on scaled QP data; returns (solution dict, iterations).
+
+    ``ref`` = (xbar, ubar, params) is needed only when node projections are enabled."""
+    st = make_settings(cfg)
+    K = qp["umin"].shape[0]
+    ws = zero_warm_start(K) if ws is None else ws
+    out = {k: np.array(v, dtype=np.float64, copy=True) for k, v in ws.items()}
+    q = {k: np.ascontiguousarray(qp[k], dtype=np.float64)
+         for k in ("Am", "Bm", "Bp", "w", "eps", "umin", "umax", "zi", "zf")}
+    refs = [None, None, None] if ref is None else [np.ascontiguousarray(r, dtype=np.float64)
+                                                   for r in ref]
+    n = lib().orc_pipg(ctypes.byref(st), K, *[_p(q[k]) for k in ("Am", "Bm", "Bp", "w", "eps",
+                                                                 "umin", "umax", "zi", "zf")],
+                       *[_p(r) for r in refs], float(sigma), int(jmax), int(check),
+                       *[_p(out[k]) for k in ("x", "u", "mup", "mum", "phi", "th")])
+    if n < 0:
+        raise ValueError("oracle: node projections need the reference and parameters")
+    return out, n
+
+
+# ----------------------------------------------------------------------------- SCP -------
+def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
+    """Solve a batch; returns a dict of numpy arrays (same names as the GPU library)."""
+    st = make_settings(cfg)
+    x0, a = _d(x0); xf, b = _d(xf); params, c = _d(params)
+    K = np.ascontiguousarray(K, dtype=np.int32)
+    B = x0.shape[0]
+    kmax = int(K.max()) if kmax is None else int(kmax)
+    nthreads = os.cpu_count() if nthreads is None else int(nthreads)
+    out = dict(x=np.zeros((B, kmax, NX)), u=np.zeros((B, kmax, NU)), t_f=np.zeros(B),
+               m_f=np.zeros(B), status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
+               pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B), ctcs_viol=np.zeros(B),
+               objective=np.zeros(B))
+    rc = lib().orc_solve_batch(
+        ctypes.byref(st), B, kmax, a, b, c, K.ctypes.data_as(_I), nthreads,
+        _p(out["x"]), _p(out["u"]), _p(out["t_f"]), _p(out["m_f"]),
+        out["status"].ctypes.data_as(_I), out["scp_iters"].ctypes.data_as(_I),
+        out["pipg_iters"].ctypes.data_as(_I), _p(out["defect_inf"]), _p(out["ctcs_viol"]),
+        _p(out["objective"]))
+    if rc != 0:
+        raise ValueError("oracle: invalid node count")
+    return out
+
+
+def solve_trace(cfg, x0, xf, p, K, trace_n=64):
+    st = make_settings(cfg)
+    x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
+    xb = np.zeros((K, NX)); ub = np.zeros((K, NU))
+    sc = np.zeros(6); ints = np.zeros(3, np.int32); tr = np.zeros((trace_n, 4))
+    lib().orc_solve_trace(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(sc),
+                          ints.ctypes.data_as(_I), int(trace_n), _p(tr))
+    n = int(ints[1])
+    return dict(x=xb, u=ub, t_f=sc[0], m_f=sc[1], defect_inf=sc[2], ctcs_viol=sc[3],
+                objective=sc[4], step=sc[5], status=int(ints[0]), scp_iters=n,
+                pipg_iters=int(ints[2]), trace=tr[:n])
+
+
+def lastiter_state(cfg, x0, xf, p, K):
+    """Reference, warm start and sigma of the last SCP iteration of a fixed-work solve."""
+    st = make_settings(cfg)
+    x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
+    n = lib().orc_iter_len(int(K))
+    xb = np.zeros((K, NX)); ub = np.zeros((K, NU)); ws = np.zeros(n); sg = ctypes.c_double(0)
+    rc = lib().orc_lastiter_state(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(ws),
+                                  ctypes.byref(sg))
+    if rc != 0:
+        raise RuntimeError("oracle: no last iteration recorded")
+    return dict(xbar=xb, ubar=ub, ws=ws, sigma=sg.value)
+
+
+def truncated_map(cfg, x0, xf, p, K, theta, last, n_steps):
+    """(m_f, t_f) of the last SCP iteration as a function of theta (18 values)."""
+    st = make_settings(cfg)
+    x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p); th, t = _d(theta)
+    out = np.zeros(2)
+    xb, xbp = _d(last["xbar"]); ub, ubp = _d(last["ubar"]); ws, wsp = _d(last["ws"])
+    lib().orc_truncated_map(ctypes.byref(st), int(K), a, b, c, t, xbp, ubp, wsp,
+                            float(last["sigma"]), int(n_steps), _p(out))
+    return out
+
+
+def theta_of(x0, p):
+    """The 18 differentiated inputs: x0 (15), m_wet, alpha_mdot, T_max."""
+    return np.concatenate([np.asarray(x0, np.float64), [p[0], p[2], p[13]]])
+
+
+def stopping(new, old, eabs, erel):
+    """The customized stopping test on two iterate dicts (keys x, u, mup, mum, phi, th)."""
+    K = new["x"].shape[0]
+    keys = ("x", "u", "mup", "mum", "phi", "th")
+    a = [np.ascontiguousarray(new[k], dtype=np.float64) for k in keys]
+    b = [np.ascontiguousarray(old[k], dtype=np.float64) for k in keys]
+    return bool(lib().orc_stopping(K, *[_p(v) for v in a], *[_p(v) for v in b], float(eabs),
+                                   float(erel)))
+
+
+def project_node(p, x, u):
+    """Node-wise convex-set projection of a state (15) and control (4), original units."""
+    p, pp = _d(p)
+    x = np.array(x, dtype=np.float64, copy=True); u = np.array(u, dtype=np.float64, copy=True)
+    lib().orc_project_node(pp, _p(x), _p(u))
+    return x, u
