@@ -1,0 +1,138 @@
+"""Benchmark: converged 6-DoF SCP solves per second on one MI355X.
+
+Workload: the 1,024-instance Monte Carlo (K = 20 nodes, FP32, fixed 15 SCP iterations x
+1,000 PIPG iterations, seeded dispersions), inputs resident in HBM before timing.  A step
+is one complete batched solve (initial guess, every discretization, power iteration, PIPG
+and reference update).  Prints one JSON line.
+
+Roofline: the dominant kernel is the subproblem kernel (power iteration + PIPG).  Its
+achieved rate is the algorithmic FP32 work of the PIPG iterations it ran divided by its
+launch durations, measured with HIP events recorded on the stream the library launches
+on.  The CPU baseline is the FP64 oracle on a bounded sample of the same workload, run on
+the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed issue)
+WORKLOAD = "C1"
+
+
+def pipg_flops_per_iter(K):
+    """Algorithmic flops of one PIPG_custom iteration of one instance with K nodes: the
+    block products A^-_k, B^-_k, B^+_k and their transposes (A^-_k has 196 free entries: its
+    mass row and y column are fixed), plus the vector updates of the primal/dual steps and
+    the extrapolation."""
+    M = K - 1
+    return M * (4 * 316 + 428) + 171 * K
+
+
+def cpu_baseline(cfg, inst, n_sample, threads):
+    import oracle
+    ids = np.arange(n_sample)
+    sub = {k: v[ids] for k, v in inst.items()}
+    oracle.build()
+    t = time.perf_counter()
+    r = oracle.solve(cfg, sub["x0"], sub["xf"], sub["params"], sub["K"], nthreads=threads)
+    dt = time.perf_counter() - t
+    conv = int(np.sum(r["status"] == 0))
+    return dict(value=round(conv / dt, 3), unit="converged solves/s", cores=threads,
+                kind="oracle",
+                sample="first %d of the %d instances (same settings), %d threads, %.1f s wall, "
+                       "%d converged" % (n_sample, inst["K"].shape[0], threads, dt, conv))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (instances are independent; a multi-GPU run would "
+              "shard the batch with no exchange). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_18034_amd import api
+    from paper_2404_18034_amd import instances as I
+
+    cfgd = I.CONFIGS[WORKLOAD]
+    cfg = I.solver_settings(WORKLOAD)
+    inst = I.make_instances(WORKLOAD)
+    B, K = cfgd["B"], cfgd["K"][0]
+    solver = api.BatchSolver(cfg, dtype=args.dtype, k_max=K, max_batch=B, device=0)
+    prob = solver.to_device(inst)
+    sol = solver.alloc_solution(B)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        solver.solve_into(prob, sol)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` solves, no profiling events inside
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve_into(prob, sol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    status = sol["status"].cpu().numpy()
+    pipg_iters = sol["pipg_iters"].cpu().numpy()
+    converged = int(np.sum(status == 0))
+    ms_per_step = dt * 1e3 / args.steps
+
+    # per-kernel launch durations (HIP events on the library's stream), separate solves
+    solver.profile(True)
+    per = {"discretize": [0.0, 0], "subproblem": [0.0, 0], "init": [0.0, 0]}
+    nprof = max(1, min(args.steps, 5))
+    for _ in range(nprof):
+        solver.solve_into(prob, sol)
+        for k, (ms, n) in solver.profile_read().items():
+            per[k][0] += ms
+            per[k][1] += n
+    solver.profile(False)
+    sub_ms = per["subproblem"][0] / nprof            # per solve
+    sub_launches = per["subproblem"][1] / nprof
+    flops_per_solve = float(np.sum(pipg_iters)) * pipg_flops_per_iter(K)
+    achieved = flops_per_solve / (sub_ms * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    traffic=None, kernel="subproblem_kernel",
+                    avg_launch_ms=round(sub_ms / max(sub_launches, 1), 4),
+                    kernel_ms_per_step={k: round(v[0] / nprof, 3) for k, v in per.items()})
+
+    out = {
+        "metric": "converged 6-DoF SCP solves/sec, 1k-64k-run Monte Carlo, FP32 vs FP64 plain",
+        "value": round(converged / (ms_per_step * 1e-3), 2),
+        "unit": "converged solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "Monte Carlo 1,024 x K=20, 15 SCP x 1,000 PIPG iterations, "
+                               "seeded dispersions (seed 1)",
+                   "batch": B, "K": K, "scp_iters": cfg["scp_iters_max"],
+                   "pipg_iters": cfg["pipg_iters_max"], "parallelism": "single GPU"},
+        "converged": converged, "solves_per_s_all": round(B / (ms_per_step * 1e-3), 2),
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(cfg, inst, args.cpu_sample, threads)
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * scp_batch.h -- C ABI of the batched 6-DoF SCP solver for AMD MI355X (gfx950).
+ *
+ * The library solves many independent free-final-time 6-DoF powered-descent guidance
+ * problems at once with the prox-linear sequential convex programming method, the
+ * continuous-time constraint satisfaction (CTCS) reformulation and the customized PIPG
+ * solver of Chari, Kamath, Elango and Acikmese, "Fast Monte Carlo Analysis for 6-DoF
+ * Powered-Descent Guidance via GPU-Accelerated Sequential Convex Programming"
+ * (sections "Problem Formulation", "Sequential Convex Programming", "Convex Optimization
+ * Solver", "6-DoF Powered Descent Guidance").
+ *
+ * Conventions
+ *   state   x = (m, r[3], v[3], q[4], w[3], y)  n_x = 15, q a Hamilton quaternion, scalar
+ *           first, body to inertial; y the CTCS constraint-violation integrator.
+ *   control u = (T[3], s)                         n_u = 4, T body-frame thrust, s dilation.
+ *   "real"  is float when scp_settings.dtype == SCP_F32 and double when SCP_F64.
+ *   All arrays are dense, row-major, device-resident (allocated by the caller on the
+ *   device the handle was created for), and 16-byte aligned.
+ *
+ * Threading and ordering
+ *   Every call that takes device memory only enqueues work on the handle's HIP stream and
+ *   returns; outputs are valid after the stream is synchronized.  A handle is not
+ *   thread-safe: use one handle per stream.  Nothing throws across this interface; every
+ *   entry point returns an scp_status and, on failure, scp_batch_last_error() describes it.
+ *
+ * Ownership
+ *   The caller owns every problem, solution and workspace buffer.  The library allocates no
+ *   device memory in scp_batch_solve; its workspace is the caller's buffer handed to
+ *   scp_batch_create.  The handle owns host-side state only.
+ */
+#ifndef SCP_BATCH_H
+#define SCP_BATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct scp_batch_s *scp_batch;
+
+typedef enum {
+    SCP_OK = 0,
+    SCP_ERR_ARG = 1,          /* a null pointer or an out-of-range setting                */
+    SCP_ERR_SHAPE = 2,        /* batch larger than max_batch, node count out of range     */
+    SCP_ERR_DTYPE = 3,        /* unknown dtype                                            */
+    SCP_ERR_DEVICE = 4,       /* no such device, or not a gfx950 device                   */
+    SCP_ERR_HIP = 5,          /* a HIP runtime call failed (message has the HIP error)    */
+    SCP_ERR_WORKSPACE = 6,    /* workspace missing, misaligned or smaller than required   */
+    SCP_ERR_STATE = 7,        /* the call needs state the handle does not have            */
+    SCP_ERR_UNSUPPORTED = 8   /* a setting the library does not implement                 */
+} scp_status;
+
+typedef enum { SCP_F32 = 0, SCP_F64 = 1 } scp_dtype;
+
+/* Solver settings; copied at scp_batch_create.  The weights, scalings and tolerances are the
+ * quantities the paper leaves as inputs: w_cost, w_prox and w_ep weigh the terminal cost,
+ * the proximal term and the exact l1 penalty of the subproblem (eq. cvx-subproblem-custom);
+ * px, pu are the diagonal prescaling P_x, P_u; omega, rho, pipg_eps_* and pipg_check_every
+ * are the PIPG step-size ratio, extrapolation, tolerances and check period (Algorithms
+ * "PIPG_custom" and "Customized stopping criterion"); power_* are those of the customized
+ * power iteration. */
+typedef struct {
+    int32_t dtype;              /* scp_dtype of the bulk arithmetic and of "real" arrays   */
+    int32_t k_max;              /* largest node count K of any instance (2..50)            */
+    int32_t max_batch;          /* largest batch passed to scp_batch_solve                 */
+    int32_t scp_iters_max;      /* maximum convex subproblems per instance                 */
+    int32_t pipg_iters_max;     /* PIPG iterations per subproblem (j_max)                  */
+    int32_t pipg_check_every;   /* j_check                                                 */
+    int32_t rk4_substeps;       /* RK4 steps per discretization interval                   */
+    int32_t power_iters_max;    /* power-iteration limit                                   */
+    int32_t early_exit;         /* 1: SCP and PIPG stop on their tolerances; 0: fixed work */
+    int32_t node_projections;   /* bitmask of node-wise convex path-constraint sets the
+                                   PIPG projection also enforces: 1 dry mass, 2 glide slope,
+                                   4 tilt, 8 rate, 16 thrust (gimbal cone and T_max);
+                                   0 = the paper's set only (boundary values, s box)       */
+    int32_t mode;               /* 0: one launch per solver phase (the only mode so far)   */
+    int32_t reserved;
+    double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
+    double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
+    double pipg_eps_abs, pipg_eps_rel;
+    double power_eps_abs, power_eps_rel, power_buff;
+    double w_cost, w_prox, w_ep, omega, rho;
+    double px[15], pu[4];
+} scp_settings;
+
+/* A batch of B problems.  params columns: m_wet, m_dry, alpha_mdot, g[3], J_diag[3],
+ * r_T[3], T_min, T_max, delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs,
+ * s_init (angles in radians).  x0 is the initial state (its y entry is ignored: y(0) = 0);
+ * xf = (r, v, q, w) is the landing condition, of which r, v, the tilt part (q2, q3) of q and
+ * w are imposed.  An instance whose K is outside [2, k_max] is not solved (status 3). */
+typedef struct {
+    int32_t batch;              /* B >= 0                                                  */
+    const void *x0;             /* real [B][15]                                            */
+    const void *xf;             /* real [B][13]                                            */
+    const void *params;         /* real [B][22]                                            */
+    const int32_t *K;           /* int32 [B] node counts                                   */
+} scp_problem;
+
+/* Per-instance results.  x, u hold the trajectory on the K nodes (rows >= K are zero).
+ * status: 0 converged, 1 iteration limit reached, 2 non-finite value met (the instance is
+ * frozen, the others are unaffected), 3 invalid instance (K out of range). */
+typedef struct {
+    void *x;                    /* real [B][k_max][15]                                     */
+    void *u;                    /* real [B][k_max][4]                                      */
+    void *t_f;                  /* real [B] time of flight = integral of s                 */
+    void *m_f;                  /* real [B] final mass                                     */
+    int32_t *status;            /* int32 [B]                                               */
+    int32_t *scp_iters;         /* int32 [B] convex subproblems solved                     */
+    int32_t *pipg_iters;        /* int32 [B] PIPG iterations summed over subproblems       */
+    double *defect_inf;         /* f64 [B] scaled dynamics defect (inf-norm) at the end    */
+    double *ctcs_viol;          /* f64 [B] largest per-interval CTCS increment y_k+1 - y_k */
+    double *objective;          /* f64 [B] -m_f + w_ep * sum |scaled defect|               */
+} scp_solution;
+
+/* Bytes of device workspace a handle with these settings needs (0 on invalid settings). */
+size_t scp_batch_workspace_bytes(const scp_settings *settings);
+
+/* Create a handle on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t, NULL
+ * for the default stream).  `workspace` is caller-owned device memory of at least
+ * scp_batch_workspace_bytes() bytes, 256-byte aligned, that must outlive the handle. */
+scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_stream,
+                            void *workspace, size_t workspace_bytes, scp_batch *out);
+
+/* Solve every instance of `problem`, writing `solution` (prox-linear SCP, section
+ * "Sequential Convex Programming"; each subproblem is discretized by RK4 on the state and
+ * variational equations, scaled as in "Convex Subproblem with Prescaling and
+ * Preconditioning", and solved by the customized power iteration and PIPG).  Enqueued on the
+ * handle's stream.  Inputs are validated before anything is enqueued. */
+scp_status scp_batch_solve(scp_batch h, const scp_problem *problem, scp_solution *solution);
+
+/* Change the stream later calls enqueue on. */
+scp_status scp_batch_set_stream(scp_batch h, void *hip_stream);
+
+/* Message for the last failed call on this handle ("" if none); valid until the next call. */
+const char *scp_batch_last_error(scp_batch h);
+
+/* Message for the last failed scp_batch_create in this process. */
+const char *scp_batch_create_error(void);
+
+/* Launch timing, for measurement tools.  With profiling enabled, every kernel launch of a
+ * solve is bracketed by two HIP events recorded on the handle's stream (created here, once;
+ * no device memory is allocated).  scp_batch_profile_read() waits for the last solve and
+ * returns, per kernel class (0 initial guess, 1 discretization, 2 subproblem), the summed
+ * launch durations in milliseconds (ms[3]) and the number of launches (launches[3]).
+ * Reading without profiling enabled is SCP_ERR_STATE. */
+scp_status scp_batch_profile(scp_batch h, int enable);
+scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
+
+/* Release the handle (not the caller's workspace).  Synchronizes its stream first. */
+scp_status scp_batch_destroy(scp_batch h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCP_BATCH_H */

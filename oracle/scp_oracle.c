@@ -50,7 +50,8 @@ typedef struct {
     int32_t rk4_substeps;      /* RK4 steps per discretization interval                  */
     int32_t power_iters_max;   /* j_max of the power iteration                           */
     int32_t early_exit;        /* 1: SCP and PIPG stop on their tolerances; 0: fixed work */
-    int32_t node_projections;  /* 1: also project nodes onto the convex path-constraint sets */
+    int32_t node_projections;  /* bitmask of node-wise convex sets: 1 dry mass, 2 glide slope,
+                                  4 tilt, 8 rate, 16 thrust (gimbal cone and T_max); 0 none */
     int32_t pad;
     double scp_tol, feas_tol;
     double pipg_eps_abs, pipg_eps_rel;
@@ -704,16 +705,18 @@ static void proj_ball(double *z, int n, double rad)
         for (i = 0; i < n; i++) z[i] *= rad / nz;
 }
 
-/* State sets: m >= m_dry, glide-slope cone on r, tilt disk on (q2, q3), rate ball on w. */
-static void project_state(double *xh, const double *xb, const double *px, const double *p)
+/* State sets (mask bits 1, 2, 4, 8): m >= m_dry, glide-slope cone on r, tilt disk on
+ * (q2, q3), rate ball on w. */
+static void project_state(double *xh, const double *xb, const double *px, const double *p,
+                          int mask)
 {
     double x[NX];
     int i;
     for (i = 0; i < NX; i++) x[i] = xb[i] + px[i] * xh[i];
-    if (x[0] < p[P_MDRY]) x[0] = p[P_MDRY];
-    proj_soc(&x[1], &x[2], 2, 1.0 / tan(p[P_GAMMA]));
-    proj_ball(&x[9], 2, sqrt(0.5 * (1.0 - cos(p[P_THETA]))));
-    proj_ball(&x[11], 3, p[P_OMEGA]);
+    if ((mask & 1) && x[0] < p[P_MDRY]) x[0] = p[P_MDRY];
+    if (mask & 2) proj_soc(&x[1], &x[2], 2, 1.0 / tan(p[P_GAMMA]));
+    if (mask & 4) proj_ball(&x[9], 2, sqrt(0.5 * (1.0 - cos(p[P_THETA]))));
+    if (mask & 8) proj_ball(&x[11], 3, p[P_OMEGA]);
     for (i = 0; i < NX; i++) xh[i] = (x[i] - xb[i]) / px[i];
 }
 
@@ -768,8 +771,9 @@ static int pipg_custom(const orc_settings *st, const qp_t *qp, double sigma, int
                 if (k == K - 1) gr += st->w_cost * ecost[j];
                 hat.x[k * NX + j] = tl.x[k * NX + j] - alpha * gr;
             }
-            if (st->node_projections)
-                project_state(hat.x + k * NX, qp->xbar + k * NX, st->px, qp->p);
+            if (st->node_projections & 15)
+                project_state(hat.x + k * NX, qp->xbar + k * NX, st->px, qp->p,
+                              st->node_projections);
             if (k == 0)
                 for (j = 0; j < NX; j++) hat.x[j] = qp->zi[j];
             if (k == K - 1)
@@ -785,7 +789,7 @@ static int pipg_custom(const orc_settings *st, const qp_t *qp, double sigma, int
                 hat.u[k * NU + j] =
                     clampd(tl.u[k * NU + j] - alpha * gr, qp->umin[k * NU + j], qp->umax[k * NU + j]);
             }
-            if (st->node_projections)
+            if (st->node_projections & 16)
                 project_thrust(hat.u + k * NU, qp->ubar + k * NU, st->pu, qp->p);
         }
         for (i = 0; i < M * NX; i++) {
@@ -1215,6 +1219,6 @@ void orc_project_node(const double *p, double *x, double *u)
     for (i = 0; i < NX; i++) one_x[i] = 1.0;
     for (i = 0; i < NU; i++) one_u[i] = 1.0;
     /* with a zero reference and unit scales the scaled projection is the plain one */
-    project_state(x, zx, one_x, p);
+    project_state(x, zx, one_x, p, 15);
     project_thrust(u, zu, one_u, p);
 }

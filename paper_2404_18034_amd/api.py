@@ -1,0 +1,240 @@
+"""Python binding of the batched 6-DoF SCP library (argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libscp_batch.so``; this module only
+allocates device tensors with PyTorch, hands their pointers and the current stream to the
+C ABI declared in ``include/scp_batch.h``, and wraps the results.  There is no CPU
+fallback: if the library or a GPU is missing, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+NX, NU, NP, NXF = 15, 4, 22, 13
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscp_batch.so")
+
+SCP_F32, SCP_F64 = 0, 1
+STATUS = {0: "SCP_OK", 1: "SCP_ERR_ARG", 2: "SCP_ERR_SHAPE", 3: "SCP_ERR_DTYPE",
+          4: "SCP_ERR_DEVICE", 5: "SCP_ERR_HIP", 6: "SCP_ERR_WORKSPACE", 7: "SCP_ERR_STATE",
+          8: "SCP_ERR_UNSUPPORTED"}
+
+# Symbols the header declares (checked by the test-suite without a GPU).
+EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
+           "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
+           "scp_batch_profile", "scp_batch_profile_read", "scp_batch_destroy"]
+KERNEL_CLASSES = ("init", "discretize", "subproblem")
+
+
+class ScpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("k_max", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+        ("scp_iters_max", ctypes.c_int32), ("pipg_iters_max", ctypes.c_int32),
+        ("pipg_check_every", ctypes.c_int32), ("rk4_substeps", ctypes.c_int32),
+        ("power_iters_max", ctypes.c_int32), ("early_exit", ctypes.c_int32),
+        ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
+        ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
+        ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
+        ("power_buff", ctypes.c_double), ("w_cost", ctypes.c_double),
+        ("w_prox", ctypes.c_double), ("w_ep", ctypes.c_double), ("omega", ctypes.c_double),
+        ("rho", ctypes.c_double), ("px", ctypes.c_double * NX), ("pu", ctypes.c_double * NU),
+    ]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("x0", ctypes.c_void_p), ("xf", ctypes.c_void_p),
+                ("params", ctypes.c_void_p), ("K", ctypes.c_void_p)]
+
+
+class Solution(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("x", "u", "t_f", "m_f", "status", "scp_iters",
+                                               "pipg_iters", "defect_inf", "ctcs_viol",
+                                               "objective")]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libscp_batch.so is not built; run __graft_entry__.build() or "
+                               "python paper_2404_18034_amd/build_lib.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.scp_batch_workspace_bytes.argtypes = [ctypes.POINTER(Settings)]
+        L.scp_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.scp_batch_create.argtypes = [ctypes.POINTER(Settings), ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.scp_batch_create.restype = ctypes.c_int
+        L.scp_batch_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                      ctypes.POINTER(Solution)]
+        L.scp_batch_solve.restype = ctypes.c_int
+        L.scp_batch_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.scp_batch_set_stream.restype = ctypes.c_int
+        L.scp_batch_last_error.argtypes = [ctypes.c_void_p]
+        L.scp_batch_last_error.restype = ctypes.c_char_p
+        L.scp_batch_create_error.argtypes = []
+        L.scp_batch_create_error.restype = ctypes.c_char_p
+        L.scp_batch_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.scp_batch_profile.restype = ctypes.c_int
+        L.scp_batch_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int32)]
+        L.scp_batch_profile_read.restype = ctypes.c_int
+        L.scp_batch_destroy.argtypes = [ctypes.c_void_p]
+        L.scp_batch_destroy.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
+    """C settings struct from a dict of solver settings (see instances.solver_settings)."""
+    s = Settings()
+    s.dtype = SCP_F64 if dtype in ("f64", "float64", SCP_F64) else SCP_F32
+    s.k_max = int(k_max)
+    s.max_batch = int(max_batch)
+    for name in ("scp_iters_max", "pipg_iters_max", "pipg_check_every", "rk4_substeps",
+                 "power_iters_max", "early_exit", "node_projections"):
+        setattr(s, name, int(cfg[name]))
+    s.mode = int(cfg.get("mode", 0))
+    for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",
+                 "power_eps_rel", "power_buff", "w_cost", "w_prox", "w_ep", "omega", "rho"):
+        setattr(s, name, float(cfg[name]))
+    for i, v in enumerate(cfg["px"]):
+        s.px[i] = float(v)
+    for i, v in enumerate(cfg["pu"]):
+        s.pu[i] = float(v)
+    return s
+
+
+def workspace_bytes(settings):
+    return int(load().scp_batch_workspace_bytes(ctypes.byref(settings)))
+
+
+class BatchSolver:
+    """A library handle with its caller-owned workspace (a torch uint8 device tensor)."""
+
+    def __init__(self, cfg, dtype="f32", k_max=30, max_batch=1024, device=0, stream=None):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("BatchSolver needs a HIP GPU; none is visible")
+        L = load()
+        self.settings = make_settings(cfg, dtype, k_max, max_batch)
+        self.dtype = torch.float64 if self.settings.dtype == SCP_F64 else torch.float32
+        self.k_max, self.max_batch, self.device = int(k_max), int(max_batch), int(device)
+        nbytes = workspace_bytes(self.settings)
+        if nbytes == 0:
+            raise ScpError(1, "invalid settings")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                     device="cuda:%d" % self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = L.scp_batch_create(ctypes.byref(self.settings), self.device,
+                                ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(aligned),
+                                ctypes.c_size_t(nbytes), ctypes.byref(h))
+        if rc != 0:
+            raise ScpError(rc, L.scp_batch_create_error().decode())
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().scp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise ScpError(rc, load().scp_batch_last_error(self.handle).decode())
+
+    def alloc_solution(self, B):
+        t = self.torch
+        dev = "cuda:%d" % self.device
+        return dict(
+            x=t.empty((B, self.k_max, NX), dtype=self.dtype, device=dev),
+            u=t.empty((B, self.k_max, NU), dtype=self.dtype, device=dev),
+            t_f=t.empty(B, dtype=self.dtype, device=dev),
+            m_f=t.empty(B, dtype=self.dtype, device=dev),
+            status=t.empty(B, dtype=t.int32, device=dev),
+            scp_iters=t.empty(B, dtype=t.int32, device=dev),
+            pipg_iters=t.empty(B, dtype=t.int32, device=dev),
+            defect_inf=t.empty(B, dtype=t.float64, device=dev),
+            ctcs_viol=t.empty(B, dtype=t.float64, device=dev),
+            objective=t.empty(B, dtype=t.float64, device=dev))
+
+    def to_device(self, inst):
+        """Problem dict of numpy arrays -> device tensors of the handle's dtype."""
+        t = self.torch
+        dev = "cuda:%d" % self.device
+        return dict(x0=t.as_tensor(np.ascontiguousarray(inst["x0"]), dtype=self.dtype).to(dev),
+                    xf=t.as_tensor(np.ascontiguousarray(inst["xf"]), dtype=self.dtype).to(dev),
+                    params=t.as_tensor(np.ascontiguousarray(inst["params"]),
+                                       dtype=self.dtype).to(dev),
+                    K=t.as_tensor(np.ascontiguousarray(inst["K"]), dtype=t.int32).to(dev))
+
+    def solve_into(self, prob, sol):
+        """Enqueue a solve of device problem tensors into preallocated solution tensors."""
+        B = int(prob["x0"].shape[0])
+        for k, shape in (("x0", (B, NX)), ("xf", (B, NXF)), ("params", (B, NP))):
+            v = prob[k]
+            if tuple(v.shape) != shape or v.dtype != self.dtype or not v.is_contiguous():
+                raise ScpError(2, "%s must be a contiguous %s tensor of shape %s" %
+                               (k, self.dtype, shape))
+        if tuple(prob["K"].shape) != (B,) or prob["K"].dtype != self.torch.int32:
+            raise ScpError(2, "K must be an int32 tensor of shape (B,)")
+        p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
+                    prob["K"].data_ptr())
+        s = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status",
+                                                    "scp_iters", "pipg_iters", "defect_inf",
+                                                    "ctcs_viol", "objective")])
+        self._check(load().scp_batch_solve(self.handle, ctypes.byref(p), ctypes.byref(s)))
+        return sol
+
+    def profile(self, enable=True):
+        """Turn per-launch HIP-event timing on or off (see scp_batch_profile)."""
+        self._check(load().scp_batch_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        """{kernel class: (summed ms, launches)} of the last solve."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int32 * 3)()
+        self._check(load().scp_batch_profile_read(self.handle, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def solve(self, prob):
+        B = int(prob["x0"].shape[0])
+        sol = self.alloc_solution(B)
+        return self.solve_into(prob, sol)
+
+
+def solve(cfg, inst, dtype="f32", k_max=None, device=0):
+    """One-shot convenience: numpy problem dict in, dict of numpy arrays out."""
+    import torch
+    K = np.asarray(inst["K"])
+    k_max = int(K.max()) if k_max is None else int(k_max)
+    B = int(K.shape[0])
+    s = BatchSolver(cfg, dtype=dtype, k_max=k_max, max_batch=max(B, 1), device=device)
+    try:
+        sol = s.solve(s.to_device(inst))
+        torch.cuda.synchronize(device)
+        return {k: v.cpu().numpy() for k, v in sol.items()}
+    finally:
+        s.close()

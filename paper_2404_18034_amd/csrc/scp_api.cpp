@@ -1,0 +1,318 @@
+// scp_api.cpp -- C ABI of the batched SCP solver: argument validation, workspace carving,
+// handle state and error reporting.  All numerical work is in scp_kernels.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/scp_batch.h"
+#include "scp_kernels.hpp"
+
+namespace {
+
+constexpr int KMAX_LIMIT = 50;  // 19 * k_max threads per subproblem workgroup must fit 1024
+constexpr size_t ALIGN = 256;
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, total;
+};
+
+bool settings_ok(const scp_settings *s, std::string &why)
+{
+    if (!s) { why = "settings is NULL"; return false; }
+    if (s->dtype != SCP_F32 && s->dtype != SCP_F64) { why = "dtype must be SCP_F32 or SCP_F64"; return false; }
+    if (s->k_max < 2 || s->k_max > KMAX_LIMIT) { why = "k_max must be in [2, 50]"; return false; }
+    if (s->max_batch < 0) { why = "max_batch must be >= 0"; return false; }
+    if (s->scp_iters_max < 1 || s->pipg_iters_max < 1 || s->rk4_substeps < 1 ||
+        s->power_iters_max < 1) {
+        why = "iteration counts and rk4_substeps must be >= 1";
+        return false;
+    }
+    if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
+    if (s->mode != 0) { why = "mode must be 0"; return false; }
+    if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
+        !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
+        why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
+        return false;
+    }
+    for (int i = 0; i < 15; ++i)
+        if (!(s->px[i] > 0.0) || !isfinite(s->px[i])) { why = "px entries must be > 0"; return false; }
+    for (int i = 0; i < 4; ++i)
+        if (!(s->pu[i] > 0.0) || !isfinite(s->pu[i])) { why = "pu entries must be > 0"; return false; }
+    if (s->node_projections < 0 || s->node_projections > 31) {
+        why = "node_projections is a bitmask in [0, 31]";
+        return false;
+    }
+    if (s->node_projections &&
+        (s->px[1] != s->px[2] || s->px[1] != s->px[3] || s->px[9] != s->px[10] ||
+         s->px[11] != s->px[12] || s->px[11] != s->px[13] || s->pu[0] != s->pu[1] ||
+         s->pu[0] != s->pu[2])) {
+        why = "node projections need equal scales within r, (q2,q3), w and T";
+        return false;
+    }
+    return true;
+}
+
+Layout layout_of(const scp_settings *s)
+{
+    const size_t rs = s->dtype == SCP_F64 ? 8 : 4;
+    const size_t B = (size_t)s->max_batch, M = (size_t)(s->k_max - 1), K = (size_t)s->k_max;
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.blocks = take(B * M * 23 * 16 * rs);
+    L.what = take(B * M * 16 * rs);
+    L.dy = take(B * M * 8);
+    L.mup = take(B * M * 16 * rs);
+    L.mum = take(B * M * 16 * rs);
+    L.phi = take(B * M * 16 * rs);
+    L.th = take(B * K * rs);
+    L.step = take(B * 8);
+    L.pipg_total = take(B * 4);
+    L.total = off == 0 ? ALIGN : off;
+    return L;
+}
+
+}  // namespace
+
+struct scp_batch_s {
+    scp_settings st;
+    int device;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Layout L;
+    std::string err;
+    // launch timing (scp_batch_profile)
+    std::vector<hipEvent_t> events;
+    std::vector<int> kinds;
+    scp::LaunchTimer timer{nullptr, nullptr, 0, 0};
+    bool profiling = false;
+};
+
+static void drop_events(scp_batch h)
+{
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    h->kinds.clear();
+    h->timer = scp::LaunchTimer{nullptr, nullptr, 0, 0};
+    h->profiling = false;
+}
+
+static scp_status fail(scp_batch h, scp_status s, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return s;
+}
+
+extern "C" {
+
+size_t scp_batch_workspace_bytes(const scp_settings *settings)
+{
+    std::string why;
+    if (!settings_ok(settings, why)) return 0;
+    return layout_of(settings).total;
+}
+
+const char *scp_batch_create_error(void) { return g_create_error.c_str(); }
+
+scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_stream,
+                            void *workspace, size_t workspace_bytes, scp_batch *out)
+{
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return SCP_ERR_ARG; }
+    *out = nullptr;
+    std::string why;
+    if (!settings_ok(settings, why)) { g_create_error = why; return SCP_ERR_ARG; }
+    const Layout L = layout_of(settings);
+    if (!workspace || workspace_bytes < L.total) {
+        g_create_error = "workspace missing or smaller than scp_batch_workspace_bytes()";
+        return SCP_ERR_WORKSPACE;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN != 0) {
+        g_create_error = "workspace must be 256-byte aligned";
+        return SCP_ERR_WORKSPACE;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) { g_create_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(e); return SCP_ERR_HIP; }
+    if (device < 0 || device >= ndev) { g_create_error = "no such device"; return SCP_ERR_DEVICE; }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { g_create_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e); return SCP_ERR_HIP; }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950";
+        return SCP_ERR_DEVICE;
+    }
+    hipPointerAttribute_t attr;
+    e = hipPointerGetAttributes(&attr, workspace);
+    if (e != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != device) {
+        (void)hipGetLastError();
+        g_create_error = "workspace is not device memory of the requested device";
+        return SCP_ERR_WORKSPACE;
+    }
+    scp_batch h = new (std::nothrow) scp_batch_s();
+    if (!h) { g_create_error = "out of host memory"; return SCP_ERR_ARG; }
+    h->st = *settings;
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->ws = static_cast<char *>(workspace);
+    h->ws_bytes = workspace_bytes;
+    h->L = L;
+    *out = h;
+    return SCP_OK;
+}
+
+scp_status scp_batch_set_stream(scp_batch h, void *hip_stream)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return SCP_OK;
+}
+
+const char *scp_batch_last_error(scp_batch h) { return h ? h->err.c_str() : "null handle"; }
+
+scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *sol)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (!prob || !sol) return fail(h, SCP_ERR_ARG, "problem or solution is NULL");
+    if (prob->batch < 0 || prob->batch > h->st.max_batch)
+        return fail(h, SCP_ERR_SHAPE, "batch must be in [0, max_batch]");
+    if (prob->batch == 0) return SCP_OK;
+    const void *in_ptrs[] = {prob->x0, prob->xf, prob->params, prob->K};
+    for (const void *p : in_ptrs)
+        if (!p) return fail(h, SCP_ERR_ARG, "a problem array is NULL");
+    const void *out_ptrs[] = {sol->x, sol->u, sol->t_f, sol->m_f, sol->status,
+                              sol->scp_iters, sol->pipg_iters, sol->defect_inf,
+                              sol->ctcs_viol, sol->objective};
+    for (const void *p : out_ptrs)
+        if (!p) return fail(h, SCP_ERR_ARG, "a solution array is NULL");
+    for (const void *p : in_ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    for (const void *p : out_ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != h->device) {
+        e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+
+    scp::Config cfg;
+    const scp_settings &s = h->st;
+    cfg.dtype = s.dtype == SCP_F64 ? 1 : 0;
+    cfg.B = prob->batch;
+    cfg.kmax = s.k_max;
+    cfg.scp_iters_max = s.scp_iters_max;
+    cfg.pipg_iters_max = s.pipg_iters_max;
+    cfg.pipg_check_every = s.pipg_check_every;
+    cfg.rk4_substeps = s.rk4_substeps;
+    cfg.power_iters_max = s.power_iters_max;
+    cfg.early_exit = s.early_exit;
+    cfg.node_projections = s.node_projections;
+    cfg.scp_tol = s.scp_tol;
+    cfg.feas_tol = s.feas_tol;
+    cfg.pipg_eps_abs = s.pipg_eps_abs;
+    cfg.pipg_eps_rel = s.pipg_eps_rel;
+    cfg.power_eps_abs = s.power_eps_abs;
+    cfg.power_eps_rel = s.power_eps_rel;
+    cfg.power_buff = s.power_buff;
+    cfg.w_cost = s.w_cost;
+    cfg.w_prox = s.w_prox;
+    cfg.w_ep = s.w_ep;
+    cfg.omega = s.omega;
+    cfg.rho = s.rho;
+    memcpy(cfg.px, s.px, sizeof(cfg.px));
+    memcpy(cfg.pu, s.pu, sizeof(cfg.pu));
+
+    scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+    scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
+                    sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
+    scp::Workspace W;
+    W.blocks = h->ws + h->L.blocks;
+    W.what = h->ws + h->L.what;
+    W.dy = reinterpret_cast<double *>(h->ws + h->L.dy);
+    W.mup = h->ws + h->L.mup;
+    W.mum = h->ws + h->L.mum;
+    W.phi = h->ws + h->L.phi;
+    W.th = h->ws + h->L.th;
+    W.step = reinterpret_cast<double *>(h->ws + h->L.step);
+    W.pipg_total = reinterpret_cast<int32_t *>(h->ws + h->L.pipg_total);
+    e = scp::launch_solve(cfg, P, S, W, h->stream, h->profiling ? &h->timer : nullptr);
+    if (cur != h->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SCP_OK;
+}
+
+scp_status scp_batch_profile(scp_batch h, int enable)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (!enable) {
+        (void)hipStreamSynchronize(h->stream);
+        drop_events(h);
+        return SCP_OK;
+    }
+    if (h->profiling) return SCP_OK;
+    const int cap = 1 + 2 * (h->st.scp_iters_max + 1);
+    h->events.assign(2 * cap, nullptr);
+    h->kinds.assign(cap, -1);
+    for (auto &ev : h->events) {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            drop_events(h);
+            return fail(h, SCP_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+        }
+    }
+    h->timer = scp::LaunchTimer{h->events.data(), h->kinds.data(), cap, 0};
+    h->profiling = true;
+    return SCP_OK;
+}
+
+scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches)
+{
+    if (!h || !ms || !launches) return SCP_ERR_ARG;
+    h->err.clear();
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (!h->profiling) return fail(h, SCP_ERR_STATE, "profiling is not enabled");
+    const int n = h->timer.n_launches;
+    if (n == 0) return SCP_OK;
+    hipError_t e = hipEventSynchronize(h->events[2 * n - 1]);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, h->events[2 * i], h->events[2 * i + 1]);
+        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+        const int k = h->kinds[i];
+        if (k >= 0 && k < 3) {
+            ms[k] += t;
+            launches[k] += 1;
+        }
+    }
+    return SCP_OK;
+}
+
+scp_status scp_batch_destroy(scp_batch h)
+{
+    if (!h) return SCP_ERR_ARG;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    drop_events(h);
+    delete h;
+    return e == hipSuccess ? SCP_OK : SCP_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// scp_kernels.hpp -- launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scp {
+
+// Device workspace carved by the host (all pointers device-resident).  R-typed regions are
+// allocated for the dtype of the handle; the blocks of one interval are stored column by
+// column, 23 columns [A^- | B^- | B^+] of 16 entries (15 rows + 1 pad).
+struct Workspace {
+    void *blocks;       // R  [B][kmax-1][23][16]  scaled A^-_k, B^-_k, B^+_k
+    void *what;         // R  [B][kmax-1][16]      scaled defect w^_k
+    double *dy;         // f64 [B][kmax-1]          CTCS increment y^k(tau_k+1) - y_k
+    void *mup;          // R  [B][kmax-1][16]      warm start mu+
+    void *mum;          // R  [B][kmax-1][16]      warm start mu-
+    void *phi;          // R  [B][kmax-1][16]      warm start dual of the dynamics
+    void *th;           // R  [B][kmax]            warm start dual of the CTCS rows
+    double *step;       // f64 [B]                  scaled step of the last subproblem
+    int32_t *pipg_total;// i32 [B]
+};
+
+struct Config {
+    int dtype;          // 0 float, 1 double
+    int B, kmax;
+    int scp_iters_max, pipg_iters_max, pipg_check_every, rk4_substeps, power_iters_max;
+    int early_exit, node_projections;
+    double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
+    double power_eps_abs, power_eps_rel, power_buff;
+    double w_cost, w_prox, w_ep, omega, rho;
+    double px[15], pu[4];
+};
+
+struct Problem {
+    const void *x0, *xf, *params;
+    const int32_t *K;
+};
+
+struct Solution {
+    void *x, *u, *t_f, *m_f;
+    int32_t *status, *scp_iters, *pipg_iters;
+    double *defect_inf, *ctcs_viol, *objective;
+};
+
+// Optional per-launch timing: when `events` is non-null, launch i is bracketed by
+// events[2i] and events[2i+1] (recorded on `stream`) and kinds[i] receives its kernel class
+// (0 init, 1 discretize, 2 subproblem); *n_launches receives the number of launches.
+struct LaunchTimer {
+    hipEvent_t *events;
+    int *kinds;
+    int capacity;
+    int n_launches;
+};
+
+// Enqueue one whole solve on `stream`; returns the first HIP error met while launching.
+hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &sol,
+                        const Workspace &ws, hipStream_t stream, LaunchTimer *timer);
+
+// Largest workgroup the subproblem kernel uses for node count kmax.
+int qp_block_threads(int kmax);
+
+}  // namespace scp

@@ -1,0 +1,74 @@
+"""The C ABI library loads, exports every declared symbol and validates its arguments before
+touching a GPU (runs without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_18034_amd import api
+from paper_2404_18034_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "scp_batch.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(scp_batch_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(api.LIB_PATH):
+        pytest.skip("libscp_batch.so not built")
+    return api.load()
+
+
+def test_exports_match_header(lib):
+    decl = declared_functions()
+    assert decl == sorted(api.EXPORTS)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_and_validation(lib):
+    cfg = I.solver_settings("C1")
+    s = api.make_settings(cfg, "f32", 20, 1024)
+    n1 = api.workspace_bytes(s)
+    s2 = api.make_settings(cfg, "f32", 20, 2048)
+    s3 = api.make_settings(cfg, "f64", 20, 1024)
+    assert n1 > 0 and api.workspace_bytes(s2) > n1 and api.workspace_bytes(s3) > n1
+    assert n1 % 256 == 0
+    for bad in (dict(k_max=1), dict(k_max=51), dict(w_prox=0.0), dict(rho=2.0),
+                dict(pipg_iters_max=0), dict(dtype=7)):
+        sb = api.make_settings(cfg, "f32", 20, 1024)
+        for k, v in bad.items():
+            setattr(sb, k, v)
+        assert api.workspace_bytes(sb) == 0
+    # node projections need block-uniform scales
+    sb = api.make_settings(dict(cfg, px=(1, 4, 4, 3, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 0.1)),
+                           "f32", 20, 1024)
+    assert api.workspace_bytes(sb) == 0
+
+
+def test_create_rejects_bad_workspace_before_any_hip_call(lib):
+    cfg = I.solver_settings("C1")
+    s = api.make_settings(cfg, "f32", 20, 16)
+    h = ctypes.c_void_p()
+    rc = lib.scp_batch_create(ctypes.byref(s), 0, None, None, 0, ctypes.byref(h))
+    assert rc == 6 and not h.value
+    assert b"workspace" in lib.scp_batch_create_error()
+    rc = lib.scp_batch_create(ctypes.byref(s), 0, None, ctypes.c_void_p(256 + 8),
+                              ctypes.c_size_t(1 << 30), ctypes.byref(h))
+    assert rc == 6 and b"aligned" in lib.scp_batch_create_error()
+    s.k_max = 0
+    rc = lib.scp_batch_create(ctypes.byref(s), 0, None, None, 0, ctypes.byref(h))
+    assert rc == 1
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.scp_batch_solve(None, None, None) == 1
+    assert lib.scp_batch_set_stream(None, None) == 1
+    assert lib.scp_batch_destroy(None) == 1
+    assert lib.scp_batch_last_error(None) == b"null handle"
