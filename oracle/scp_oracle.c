@@ -31,6 +31,13 @@
 #define NXF 13
 #define IY 14 /* index of the CTCS integrator state y */
 
+/* Below this norm a thrust vector (or the lateral position) is treated as zero when
+ * differentiating ||.||: the derivative of the norm is taken as 0 there.  The node-wise
+ * thrust projection can land exactly on T = 0, and a reference rebuilt from the scaled step
+ * then holds T at rounding level; the threshold keeps the linearization continuous across
+ * that rounding. */
+#define NORM_EPS 1e-4
+
 /* Final boundary condition E_f: r, v, the tilt part (q2, q3) of the attitude and w are fixed;
  * the roll part (q0, q1), the mass and y are free.  Reading of "land upright": with thrust as
  * the only input, roll about the body axis is not controllable, so it cannot be prescribed. */
@@ -115,7 +122,7 @@ static void constraints(const double *x, const double *u, const double *p, doubl
     g[6] = p[P_TMIN] - Tn;
 }
 
-/* Gradients of g w.r.t. x (7 x 15) and w.r.t. T (7 x 3).  d||v||/dv := 0 at v = 0. */
+/* Gradients of g w.r.t. x (7 x 15) and w.r.t. T (7 x 3).  d||v||/dv := 0 for ||v|| <= NORM_EPS. */
 static void constraint_grads(const double *x, const double *u, const double *p, double Gx[7][NX],
                              double Gt[7][3])
 {
@@ -127,11 +134,11 @@ static void constraint_grads(const double *x, const double *u, const double *p, 
     int i;
     memset(Gx, 0, sizeof(double) * 7 * NX);
     memset(Gt, 0, sizeof(double) * 7 * 3);
-    if (Tn > 0.0)
+    if (Tn > NORM_EPS)
         for (i = 0; i < 3; i++) dT[i] = u[i] / Tn;
     Gx[0][0] = -1.0;
     Gx[1][1] = -1.0;
-    if (lat > 0.0) {
+    if (lat > NORM_EPS) {
         Gx[1][2] = tg * r[1] / lat;
         Gx[1][3] = tg * r[2] / lat;
     }
@@ -259,7 +266,7 @@ void orc_jacobians(const double *x, const double *u, const double *p, double *A,
     for (i = 0; i < NX * NX; i++) A[i] *= s;
 
     /* dF/dT */
-    if (Tn > 0.0)
+    if (Tn > NORM_EPS)
         for (j = 0; j < 3; j++) B[0 * NU + j] = -p[P_ALPHA] * u[j] / Tn;
     for (i = 0; i < 3; i++)
         for (j = 0; j < 3; j++) B[(4 + i) * NU + j] = C[i][j] / m;

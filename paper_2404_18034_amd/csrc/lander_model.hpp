@@ -14,6 +14,7 @@ constexpr int NU = 4;
 constexpr int NP = 22;
 constexpr int NXF = 13;
 constexpr int IY = 14;
+constexpr double NORM_EPS = 1e-4;  // below this a norm's derivative is taken as 0
 
 // Vehicle data used inside the model, with the trigonometric constants folded once.
 template <typename R>
@@ -133,8 +134,9 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     const R da0 = dC00 * T0 + dC01 * T1 + dC02 * T2 + C00 * dT0 + C01 * dT1 + C02 * dT2;
     const R da1 = dC10 * T0 + dC11 * T1 + dC12 * T2 + C10 * dT0 + C11 * dT1 + C12 * dT2;
     const R da2 = dC20 * T0 + dC21 * T1 + dC22 * T2 + C20 * dT0 + C21 * dT1 + C22 * dT2;
-    // d||T|| := 0 at T = 0
-    const R dTn = Tn > R(0) ? (T0 * dT0 + T1 * dT1 + T2 * dT2) / Tn : R(0);
+    // the derivative of a norm is taken as 0 below NORM_EPS (the thrust projection can put T
+    // exactly at the apex of the gimbal cone; its reconstruction carries rounding noise)
+    const R dTn = Tn > R(NORM_EPS) ? (T0 * dT0 + T1 * dT1 + T2 * dT2) / Tn : R(0);
     const R dim = -dm * im * im;
 
     R dF[NX];
@@ -158,7 +160,7 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
                           (dw0 * Jw1 + w0 * dJw1 - dw1 * Jw0 - w1 * dJw0));
     R dg[7];
     dg[0] = -dm;
-    dg[1] = (lat > R(0) ? V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]) / lat : R(0)) - dx[1];
+    dg[1] = (lat > R(NORM_EPS) ? V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]) / lat : R(0)) - dx[1];
     dg[2] = R(4) * (q2 * dq2 + q3 * dq3);
     dg[3] = R(2) * (w0 * dw0 + w1 * dw1 + w2 * dw2);
     dg[4] = dTn - dT0 * V.sec_delta;

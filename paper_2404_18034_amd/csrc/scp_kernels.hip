@@ -7,14 +7,18 @@
 //                      column (subsection "Convex Subproblem with Prescaling and
 //                      Preconditioning"); lane 0 of each interval also writes the scaled
 //                      defect w^_k and the CTCS increment.
-//   subproblem_kernel  one workgroup per instance: convergence test of the current
-//                      reference, the customized power iteration (FP64), PIPG_custom with
-//                      its projections and stopping rule, and the reference update.  The
-//                      instance's blocks stay in registers for all PIPG iterations; the
-//                      iterates that neighbouring nodes exchange live in LDS.
+//   subproblem_kernel  one workgroup per instance, one 16-lane row per node: convergence
+//                      test of the current reference, the customized power iteration
+//                      (FP64), PIPG_custom with its projections and stopping rule, and the
+//                      reference update.  The instance's blocks stay in registers for all
+//                      PIPG iterations; products inside an interval use DPP row
+//                      broadcasts, and only values exchanged between neighbouring nodes
+//                      pass through LDS.
 // Per-instance results never depend on other instances, and every reduction has a fixed
 // order, so repeated runs are bitwise identical.
 #include <math.h>
+
+#include <utility>
 
 #include "lander_model.hpp"
 #include "scp_kernels.hpp"
@@ -235,24 +239,89 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
     }
 }
 
-// Node-wise convex sets (original units); component `j` of group member `which`.
-template <typename R>
-__device__ __forceinline__ R proj_soc_comp(R t, R z0, R z1, R a, int which)
+// ------------------------------------------------------------------------------------------
+// Cross-lane helpers.  A workgroup row is 16 lanes (one DPP row); row k of the workgroup
+// holds node k (state variable i on lane i) and interval k (dynamics row i on lane i).
+// ------------------------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ float rowb(float v)
 {
-    // second-order cone {(t, z) : ||z|| <= a t}; returns component 0 (t), 1 or 2 (z)
+    // row_newbcast: every lane of the 16-lane row receives lane L's value
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + L, 0xf, 0xf, true));
+}
+template <int L>
+__device__ __forceinline__ double rowb(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + L, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + L, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dppmov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppmov(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 16 lanes of a row, returned to every lane.  Partners are exchanged
+// symmetrically at every step (quad xor 1, quad xor 2, row mirror, row rotate by 8), so each
+// lane adds the same two operands and all 16 lanes end with bitwise identical sums.
+template <typename R>
+__device__ __forceinline__ R row_allreduce(R v)
+{
+    v = v + dppmov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = v + dppmov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = v + dppmov<0x140>(v);  // row_mirror
+    v = v + dppmov<0x128>(v);  // row_ror:8
+    return v;
+}
+// sum_j c[j] * (value of lane j of this row), j = 0..14, in a fixed order
+template <typename R, int... J>
+__device__ __forceinline__ R rowdot_impl(const R *c, R v, R acc, std::integer_sequence<int, J...>)
+{
+    ((acc = acc + c[J] * rowb<J>(v)), ...);
+    return acc;
+}
+template <typename R>
+__device__ __forceinline__ R rowdot15(const R *c, R v, R acc)
+{
+    return rowdot_impl<R>(c, v, acc, std::make_integer_sequence<int, NX>{});
+}
+
+// Node-wise convex sets, branch-free: project v = (t, z0, z1) onto the second-order cone
+// {||z|| <= a t} (when `cone`), then onto the ball of radius `rad` centred at the cone's apex
+// (rad = +inf for none); for a cone and a ball sharing that centre the composition is the
+// projection onto their intersection.  inv1a2 = 1 / (1 + a^2).
+template <typename R>
+__device__ __forceinline__ void proj_cone_ball(R &t, R &z0, R &z1, bool cone, R a, R inv1a2, R rad)
+{
     const R nz = sqrt(z0 * z0 + z1 * z1);
-    if (nz <= a * t) return which == 0 ? t : (which == 1 ? z0 : z1);
-    if (a * nz <= -t) return R(0);
-    const R tp = (t + a * nz) / (R(1) + a * a);
-    if (which == 0) return tp;
-    return a * tp * (which == 1 ? z0 : z1) / nz;
+    const bool inside = !cone || nz <= a * t;
+    const bool polar = a * nz <= -t;
+    const R tp = (t + a * nz) * inv1a2;
+    const R zs = nz > R(0) ? a * tp / nz : R(0);
+    const R t1 = inside ? t : (polar ? R(0) : tp);
+    const R s1 = inside ? R(1) : (polar ? R(0) : zs);
+    const R a0 = z0 * s1, a1 = z1 * s1;
+    const R n = sqrt(t1 * t1 + a0 * a0 + a1 * a1);
+    const R bs = n > rad ? rad / n : R(1);
+    t = t1 * bs;
+    z0 = a0 * bs;
+    z1 = a1 * bs;
 }
 
 // ------------------------------------------------------------------------------------------
-// Subproblem kernel.  Thread t of the workgroup of instance b:
-//   t < 15K:          state variable (k, i) = (t / 15, t % 15) of node k for the primal
-//                     step; for k < K-1 also dynamics row (k, i) for the dual step.
-//   15K <= t < 19K:   control variable (k, j) = ((t - 15K) / 4, (t - 15K) % 4).
+// Subproblem kernel: one workgroup per instance, 16 lanes (one DPP row) per node.
+//   lane i of row k:  state variable (k, i) for i < 15 (primal step), dynamics row (k, i)
+//                     of interval k for i < 15, k < K-1 (dual step); the four controls of
+//                     node k are held, bitwise identical, by all 16 lanes of the row.
+// The block products inside an interval use row broadcasts of register values (DPP);
+// only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
 template <typename R, int MAXT>
 __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
@@ -263,51 +332,45 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
     if (a.status[b] >= 0) return;  // uniform over the workgroup
     const int K = a.K[b], M = K - 1, kmax = a.kmax;
     const int t = threadIdx.x;
+    const int k = t >> 4, i = t & 15;
 
     // LDS carve (doubles first for alignment)
-    double *red = reinterpret_cast<double *>(smem_raw);           // [16 waves * 8]
-    double *dZ = red + 128;                                        // [kmax][VST]
-    double *dPhi = dZ + kmax * VST;                                // [kmax-1][DST]
-    double *dTh = dPhi + (kmax - 1) * DST;                         // [kmax]
-    R *sPhi = reinterpret_cast<R *>(dTh + kmax);                   // [kmax-1][DST]
-    R *sTh = sPhi + (kmax - 1) * DST;                              // [kmax]
-    R *sV = sTh + kmax;                                            // [kmax][VST]
-    R *sPre = sV + kmax * VST;                                     // [kmax][VST]
+    double *red = reinterpret_cast<double *>(smem_raw);          // [16 waves * 8]
+    double *dZ = red + 128;                                       // [kmax][VST]
+    double *dPhi = dZ + kmax * VST;                               // [kmax][DST]
+    double *dTh = dPhi + kmax * DST;                              // [kmax]
+    R *sPhi = reinterpret_cast<R *>(dTh + kmax);                  // [kmax][DST]
+    R *sTh = sPhi + kmax * DST;                                   // [kmax]
+    R *sVx = sTh + kmax;                                          // [kmax][DST]
+    R *sVu = sVx + kmax * DST;                                    // [kmax][4]
 
-    const bool isx = t < NX * K;
-    const bool isu = !isx && t < (NX + NU) * K;
-    const bool prim = isx || isu;
-    const int pk = isx ? t / NX : (isu ? (t - NX * K) / NU : 0);
-    const int pj = isx ? t % NX : (isu ? NX + (t - NX * K) % NU : 0);  // 0..18 within node
-    const bool dual = t < NX * M;
-    const int dk = t / NX, di = t % NX;
-    const long xoff = ((long)b * kmax + pk) * NX;
-    const long uoff = ((long)b * kmax + pk) * NU;
-    const double pscale = isx ? a.px[pj] : (isu ? a.pu[pj - NX] : 1.0);
+    const bool node = k < K;               // row holds a node
+    const bool isx = node && i < NX;       // lane holds a state variable
+    const bool dual = k < M && i < NX;     // lane holds a dynamics row
+    const long xoff = ((long)b * kmax + (node ? k : 0)) * NX;
+    const long uoff = ((long)b * kmax + (node ? k : 0)) * NU;
+    const R *p = a.params + (long)b * NP;
 
     // -------------------- convergence test of the current reference --------------------
-    // (scaled defect, CTCS increment, objective; status and outputs when the instance ends)
     {
         double mx[2] = {0.0, -INFINITY};
         double sm[2] = {0.0, 0.0};
         if (dual) {
-            const R w = a.what[((long)b * (kmax - 1) + dk) * DST + di];
+            const R w = a.what[((long)b * (kmax - 1) + k) * DST + i];
             const double e = fabs(double(w));
             mx[0] = isfinite(e) ? e : INFINITY;
             sm[0] = e;
-            if (di == 0) mx[1] = a.dy[(long)b * (kmax - 1) + dk];
+            if (i == 0) mx[1] = a.dy[(long)b * (kmax - 1) + k];
+            if (!isfinite(e)) sm[1] = 1.0;
         }
-        if (prim) {
-            const R v = isx ? a.x[xoff + pj] : a.u[uoff + pj - NX];
-            if (!isfinite(double(v))) sm[1] = 1.0;
-        }
-        if (dual && !isfinite(mx[0])) sm[1] = 1.0;
+        if (isx && !isfinite(double(a.x[xoff + i]))) sm[1] = 1.0;
+        if (node && i < NU && !isfinite(double(a.u[uoff + i]))) sm[1] = 1.0;
         block_reduce<2, true>(mx, red);
         block_reduce<2, false>(sm, red);
         const double d = mx[0], c = mx[1];
         const double step = a.step[b];
         const bool bad = sm[1] > 0.0 || !isfinite(d) || (a.j > 1 && !isfinite(step));
-        const double eps = double(a.params[(long)b * NP + 20]);
+        const double eps = double(p[20]);
         const bool conv = a.j > 1 && step <= a.scp_tol && d <= a.feas_tol &&
                           (c - eps) / a.px[IY] <= a.feas_tol;
         if (bad || a.j > a.scp_iters_max || (a.early_exit && conv)) {
@@ -321,10 +384,10 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
                 a.objective[b] = -mN + a.w_ep * sm[0];
                 double tf = 0.0;
                 const double dtau = 1.0 / M;
-                for (int k = 0; k < M; ++k)
+                for (int q = 0; q < M; ++q)
                     tf += dtau * 0.5 *
-                          (double(a.u[((long)b * kmax + k) * NU + 3]) +
-                           double(a.u[((long)b * kmax + k + 1) * NU + 3]));
+                          (double(a.u[((long)b * kmax + q) * NU + 3]) +
+                           double(a.u[((long)b * kmax + q + 1) * NU + 3]));
                 a.t_f[b] = R(tf);
                 a.m_f[b] = R(mN);
             }
@@ -334,96 +397,104 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
 
     // -------------------- load the subproblem into registers --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
-    R c1[NX], c2[NX], row[COLS];
-    // primal: c1 = column pj of A^-_k (state) or of B^-_k (control); c2 = column of B^+_{k-1}
-    for (int i = 0; i < NX; ++i) {
-        c1[i] = R(0);
-        c2[i] = R(0);
+    R colA[NX], rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
+    // (forward product); rowBq: row i of B^+_{k-1} (control gradient of node k)
+    for (int q = 0; q < NX; ++q) {
+        colA[q] = dual ? blk[(long)k * BLK + i * CST + q] : R(0);
+        rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
     }
-    if (prim && pk < M)
-        for (int i = 0; i < NX; ++i) c1[i] = blk[(long)pk * BLK + pj * CST + i];
-    if (isu && pk > 0)
-        for (int i = 0; i < NX; ++i) c2[i] = blk[(long)(pk - 1) * BLK + (pj + NU) * CST + i];
-    // dual: row di of [A^-_k | B^-_k | B^+_k]
-    for (int j = 0; j < COLS; ++j) row[j] = dual ? blk[(long)dk * BLK + j * CST + di] : R(0);
+    for (int q = 0; q < NU; ++q) {
+        rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
+        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
+        rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
+                                             : R(0);
+    }
 
-    const R *p = a.params + (long)b * NP;
-    // boundary values and bounds of this primal variable
+    // boundary values, bounds, reference values
+    const R xb = isx ? a.x[xoff + i] : R(0);
+    R ub[NU];
+    for (int q = 0; q < NU; ++q) ub[q] = node ? a.u[uoff + q] : R(0);
     bool fixed = false;
-    R fixv = R(0), lo = R(-INFINITY), hi = R(INFINITY), xb = R(0);
+    R fixv = R(0);
     if (isx) {
-        xb = a.x[xoff + pj];
-        if (pk == 0) {
+        if (k == 0) {
             fixed = true;
-            const double zi = pj < IY ? double(a.x0[(long)b * NX + pj]) : 0.0;
-            fixv = R((zi - double(xb)) / a.px[pj]);
-        } else if (pk == K - 1 && final_fixed(pj)) {
+            const double zi = i < IY ? double(a.x0[(long)b * NX + i]) : 0.0;
+            fixv = R((zi - double(xb)) / a.px[i]);
+        } else if (k == K - 1 && final_fixed(i)) {
             fixed = true;
-            fixv = R((double(a.xf[(long)b * NXF + pj - 1]) - double(xb)) / a.px[pj]);
-        }
-    } else if (isu) {
-        xb = a.u[uoff + pj - NX];
-        if (pj == NX + 3) {
-            lo = R((double(p[18]) - double(xb)) / a.pu[3]);
-            hi = R((double(p[19]) - double(xb)) / a.pu[3]);
+            fixv = R((double(a.xf[(long)b * NXF + i - 1]) - double(xb)) / a.px[i]);
         }
     }
+    const R slo = R((double(p[18]) - double(ub[3])) / a.pu[3]);
+    const R shi = R((double(p[19]) - double(ub[3])) / a.pu[3]);
     R wk = R(0), epsk = R(0);
     if (dual) {
-        wk = a.what[((long)b * (kmax - 1) + dk) * DST + di];
-        if (di == IY) {
-            const double y0 = double(a.x[((long)b * kmax + dk) * NX + IY]);
-            const double y1 = double(a.x[((long)b * kmax + dk + 1) * NX + IY]);
+        wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
+        if (i == IY) {
+            const double y0 = double(a.x[((long)b * kmax + k) * NX + IY]);
+            const double y1 = double(a.x[((long)b * kmax + k + 1) * NX + IY]);
             epsk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
         }
     }
 
     // -------------------- customized power iteration (FP64) --------------------
+    // z = (x, u, mu+, mu-) starts at all ones.  x on lane i of row k, u of node k on lanes
+    // 0..3 of row k, mu+- of row (k, i) on the dual lanes.
     double sigma;
     {
-        double z = 1.0, mp = 1.0, mm = 1.0;
-        double acc[1] = {(prim ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
+        const bool isu = node && i < NU;
+        double zx = 1.0, zu = 1.0, mp = 1.0, mm = 1.0;
+        double acc[1] = {(isx ? 1.0 : 0.0) + (isu ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
         block_reduce<1, false>(acc, red);
         sigma = sqrt(acc[0]);
         double sstar = sigma;
         for (int it = 1; it <= a.power_iters_max; ++it) {
-            if (prim) dZ[pk * VST + pj] = z;
+            if (isx) dZ[k * VST + i] = zx;
+            if (isu) dZ[k * VST + NX + i] = zu;
             __syncthreads();
             double ph = 0.0;
             if (dual) {
                 double r = 0.0;
-                for (int j = 0; j < NX; ++j) r += double(row[j]) * dZ[dk * VST + j];
-                r -= dZ[(dk + 1) * VST + di];
+                for (int j = 0; j < NX; ++j) r += double(rowA[j]) * dZ[k * VST + j];
+                r -= dZ[(k + 1) * VST + i];
                 for (int j = 0; j < NU; ++j) {
-                    r += double(row[NX + j]) * dZ[dk * VST + NX + j];
-                    r += double(row[NX + NU + j]) * dZ[(dk + 1) * VST + NX + j];
+                    r += double(rowBm[j]) * dZ[k * VST + NX + j];
+                    r += double(rowBp[j]) * dZ[(k + 1) * VST + NX + j];
                 }
                 r += mp - mm;
                 ph = r / sigma;
-                dPhi[dk * DST + di] = ph;
-                if (di == IY) dTh[dk] = (dZ[(dk + 1) * VST + IY] - dZ[dk * VST + IY]) / sigma;
+                dPhi[k * DST + i] = ph;
+                if (i == IY) dTh[k] = (dZ[(k + 1) * VST + IY] - dZ[k * VST + IY]) / sigma;
             }
             __syncthreads();
-            if (prim) {
+            if (isx) {
                 double r = 0.0;
-                if (pk < M)
-                    for (int i = 0; i < NX; ++i) r += double(c1[i]) * dPhi[pk * DST + i];
-                if (isx) {
-                    if (pk > 0) r -= dPhi[(pk - 1) * DST + pj];
-                    if (pj == IY) {
-                        if (pk < M) r -= dTh[pk];
-                        if (pk > 0) r += dTh[pk - 1];
-                    }
-                } else if (pk > 0) {
-                    for (int i = 0; i < NX; ++i) r += double(c2[i]) * dPhi[(pk - 1) * DST + i];
+                if (k < M)
+                    for (int q = 0; q < NX; ++q) r += double(colA[q]) * dPhi[k * DST + q];
+                if (k > 0) r -= dPhi[(k - 1) * DST + i];
+                if (i == IY) {
+                    if (k < M) r -= dTh[k];
+                    if (k > 0) r += dTh[k - 1];
                 }
-                z = r;
+                zx = r;
+            }
+            {
+                // control part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
+                const double phk = dual ? dPhi[k * DST + i] : 0.0;
+                const double phm = (k > 0 && k <= M && i < NX) ? dPhi[(k - 1) * DST + i] : 0.0;
+                double zq[NU];
+                for (int q = 0; q < NU; ++q)
+                    zq[q] = row_allreduce<double>(double(rowBm[q]) * phk + double(rowBq[q]) * phm);
+                zu = i == 0 ? zq[0] : (i == 1 ? zq[1] : (i == 2 ? zq[2] : zq[3]));
             }
             if (dual) {
                 mp = ph;
                 mm = -ph;
             }
-            double sq[1] = {(prim ? z * z : 0.0) + (dual ? mp * mp + mm * mm : 0.0)};
+            double sq[1] = {(isx ? zx * zx : 0.0) + (isu ? zu * zu : 0.0) +
+                            (dual ? mp * mp + mm * mm : 0.0)};
             block_reduce<1, false>(sq, red);
             sstar = sqrt(sq[0]);
             if (fabs(sstar - sigma) <= a.power_eps_abs + a.power_eps_rel * fmax(sstar, sigma))
@@ -437,189 +508,189 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
     const R alpha = R(alpha_d), beta = R(a.omega * alpha_d), rho = R(a.rho);
     const R omr = R(1) - rho;
     const R wprox = R(a.w_prox), wep = R(a.w_ep);
-    const R cost = (isx && pk == K - 1 && pj == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
+    const R cost = (isx && k == K - 1 && i == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
 
     // -------------------- PIPG_custom --------------------
     // warm start: x^, u^ = 0; mu+-, phi, theta from the previous subproblem
-    R xt = R(0), xh = R(0), xprev = R(0);
-    R vphi = R(0), ph = R(0), phprev = R(0);
-    R nup = R(0), num = R(0), mup = R(0), mum = R(0), mupprev = R(0), mumprev = R(0);
-    R vth = R(0), th = R(0), thprev = R(0);
-    const long doff = ((long)b * (kmax - 1) + dk) * DST + di;
+    // fresh iterates (x^, u^, mu, phi, theta) double as the previous iterate of the stopping
+    // test; the extrapolated ones are x~, u~, nu, varphi, vartheta
+    R xt = R(0), xh = R(0);
+    R ut[NU], uh[NU];
+    for (int q = 0; q < NU; ++q) ut[q] = uh[q] = R(0);
+    R vphi = R(0), ph = R(0);
+    R nup = R(0), num = R(0), mup = R(0), mum = R(0);
+    R vth = R(0), th = R(0);
+    const long doff = ((long)b * (kmax - 1) + (dual ? k : 0)) * DST + i;
     if (dual) {
-        mup = nup = mupprev = a.mup[doff];
-        mum = num = mumprev = a.mum[doff];
-        ph = vphi = phprev = a.phi[doff];
-        sPhi[dk * DST + di] = vphi;
-        if (di == IY) {
-            th = vth = thprev = a.th[(long)b * kmax + dk];
-            sTh[dk] = vth;
-        }
+        mup = nup = a.mup[doff];
+        mum = num = a.mum[doff];
+        ph = vphi = a.phi[doff];
+        if (i == IY) th = vth = a.th[(long)b * kmax + k];
+    }
+    if (k < kmax) {
+        sPhi[k * DST + i] = vphi;
+        if (i == IY) sTh[k] = vth;
     }
     __syncthreads();
 
     const int jmax = a.pipg_iters_max;
     const int check = a.early_exit ? a.pipg_check_every : 0;
-    const bool nodeproj = a.node_projections != 0;
-    // projection group of this primal variable: 0 none, 1 mass, 2 glide-slope cone on r,
-    // 3 tilt disk on (q2, q3), 4 rate ball on w, 5 thrust cone and ball on T
-    int grp = 0, gbase = 0;
     const int pmask = a.node_projections;
-    if (nodeproj && prim && !fixed) {
-        if (isx) {
-            if (pj == 0) grp = (pmask & 1) ? 1 : 0;
-            else if (pj <= 3) { grp = (pmask & 2) ? 2 : 0; gbase = 1; }
-            else if (pj == 9 || pj == 10) { grp = (pmask & 4) ? 3 : 0; gbase = 9; }
-            else if (pj >= 11 && pj <= 13) { grp = (pmask & 8) ? 4 : 0; gbase = 11; }
-        } else if (pj < NX + 3) {
-            grp = (pmask & 16) ? 5 : 0;
-            gbase = NX;
-        }
+    // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
+    // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
+    int grp = 0, gw = 0, gb = 0;
+    if (isx && !fixed) {
+        if (i == 0) grp = (pmask & 1) ? 1 : 0;
+        else if (i <= 3) { grp = (pmask & 2) ? 2 : 0; gb = 1; }
+        else if (i == 9 || i == 10) { grp = (pmask & 4) ? 3 : 0; gb = 9; }
+        else if (i >= 11 && i <= 13) { grp = (pmask & 8) ? 4 : 0; gb = 11; }
+        gw = i - gb;
     }
-    // reference values of the group (original units) and its scale
-    R gref[3] = {R(0), R(0), R(0)};
-    if (grp >= 2) {
-        const R *src = grp == 5 ? a.u + uoff : a.x + xoff + gbase;
-        gref[0] = src[0];
-        gref[1] = src[1];
-        gref[2] = grp == 3 ? R(0) : src[2];
-    }
-    const R gsc = R(pscale);
-    const R tan_g = R(tan(double(p[15]))), tan_d = R(tan(double(p[14])));
-    const R disk = R(sqrt(0.5 * (1.0 - cos(double(p[16]))))), wmax = p[17], Tmax = p[13];
+    const R INF = R(INFINITY);
+    const double tan_g = tan(double(p[15])), tan_d = tan(double(p[14]));
+    const R g_a = grp == 2 ? R(1.0 / tan_g) : R(0);
+    const R g_inv = grp == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g))) : R(1);
+    const R g_rad = grp == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16]))))) : (grp == 4 ? p[17] : INF);
+    const R T_a = R(tan_d), T_inv = R(1.0 / (1.0 + tan_d * tan_d)), Tmax = p[13];
     const R mdry = p[1];
+    const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
+    const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
+    // reference values of the group members (original units)
+    const R xbb1 = rowb<1>(xb), xbb2 = rowb<2>(xb), xbb3 = rowb<3>(xb);
+    const R xbb9 = rowb<9>(xb), xbb10 = rowb<10>(xb);
+    const R xbb11 = rowb<11>(xb), xbb12 = rowb<12>(xb), xbb13 = rowb<13>(xb);
+    const R gr0 = grp == 2 ? xbb1 : (grp == 3 ? xbb9 : xbb11);
+    const R gr1 = grp == 2 ? xbb2 : (grp == 3 ? xbb10 : xbb12);
+    const R gr2 = grp == 2 ? xbb3 : (grp == 3 ? R(0) : xbb13);
 
     int it = 1;
     for (; it <= jmax; ++it) {
         // ---- projected gradient step on the primal variables ----
-        R xn = R(0);
-        if (prim) {
-            R g = wprox * xt + cost;
-            if (pk < M)
-                for (int i = 0; i < NX; ++i) g += c1[i] * sPhi[pk * DST + i];
-            if (isx) {
-                if (pk > 0) g -= sPhi[(pk - 1) * DST + pj];
-                if (pj == IY) {
-                    if (pk < M) g -= sTh[pk];
-                    if (pk > 0) g += sTh[pk - 1];
-                }
-                xn = xt - alpha * g;
-            } else {
-                if (pk > 0)
-                    for (int i = 0; i < NX; ++i) g += c2[i] * sPhi[(pk - 1) * DST + i];
-                xn = fmin(fmax(xt - alpha * g, lo), hi);
-            }
+        const R phm1 = (k > 0 && k < kmax) ? sPhi[(k - 1) * DST + i] : R(0);  // phi_{k-1}[i]
+        const R thm1 = (k > 0 && k < kmax) ? sTh[k - 1] : R(0);               // theta_{k-1}
+        const R thk = rowb<IY>(vth);                                          // theta_k
+        R g = wprox * xt + cost;
+        g = rowdot15<R>(colA, vphi, g);  // (A^-_k)^T phi_k, column i
+        g -= (k > 0) ? phm1 : R(0);
+        if (i == IY) g += (k < M ? -thk : R(0)) + (k > 0 ? thm1 : R(0));
+        R xn = xt - alpha * g;
+        // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
+        R un[NU];
+        for (int q = 0; q < NU; ++q) {
+            R gq = rowBm[q] * vphi + rowBq[q] * phm1;
+            gq = row_allreduce<R>(gq);
+            gq = wprox * ut[q] + gq;
+            un[q] = ut[q] - alpha * gq;
         }
-        if (nodeproj) {
-            if (prim) sPre[pk * VST + pj] = xn;
-            __syncthreads();
+        un[3] = fmin(fmax(un[3], slo), shi);
+        if (pmask) {
+            // state sets: gather the pre-projection values of this lane's group
+            const R v1 = rowb<1>(xn), v2 = rowb<2>(xn), v3 = rowb<3>(xn);
+            const R v9 = rowb<9>(xn), v10 = rowb<10>(xn);
+            const R v11 = rowb<11>(xn), v12 = rowb<12>(xn), v13 = rowb<13>(xn);
+            R t0 = gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
+            R t1 = gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
+            R t2 = grp == 3 ? R(0) : gr2 + pxi * (grp == 2 ? v3 : v13);
+            proj_cone_ball<R>(t0, t1, t2, grp == 2, g_a, g_inv, g_rad);
+            const R o = gw == 0 ? t0 : (gw == 1 ? t1 : t2);
+            const R gref = gw == 0 ? gr0 : (gw == 1 ? gr1 : gr2);
+            if (grp >= 2) xn = (o - gref) * ipxi;
             if (grp == 1) {
-                R m = xb + gsc * xn;
-                m = m < mdry ? mdry : m;
-                xn = (m - xb) / gsc;
-            } else if (grp >= 2) {
-                const int w = pj - gbase;
-                R o0 = gref[0] + gsc * sPre[pk * VST + gbase];
-                R o1 = gref[1] + gsc * sPre[pk * VST + gbase + 1];
-                R o2 = grp == 3 ? R(0) : gref[2] + gsc * sPre[pk * VST + gbase + 2];
-                R o;
-                if (grp == 2) {
-                    o = proj_soc_comp<R>(o0, o1, o2, R(1) / tan_g, w);
-                } else if (grp == 5) {
-                    // cone {||(T1,T2)|| <= tan(delta) T0}, then the ball ||T|| <= T_max
-                    const R t0 = proj_soc_comp<R>(o0, o1, o2, tan_d, 0);
-                    const R t1 = proj_soc_comp<R>(o0, o1, o2, tan_d, 1);
-                    const R t2 = proj_soc_comp<R>(o0, o1, o2, tan_d, 2);
-                    const R n = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-                    const R sc = n > Tmax ? Tmax / n : R(1);
-                    o = (w == 0 ? t0 : (w == 1 ? t1 : t2)) * sc;
-                } else {
-                    const R n = grp == 3 ? sqrt(o0 * o0 + o1 * o1) : sqrt(o0 * o0 + o1 * o1 + o2 * o2);
-                    const R rad = grp == 3 ? disk : wmax;
-                    const R sc = n > rad ? rad / n : R(1);
-                    o = (w == 0 ? o0 : (w == 1 ? o1 : o2)) * sc;
-                }
-                const R gw = w == 0 ? gref[0] : (w == 1 ? gref[1] : gref[2]);
-                xn = (o - gw) / gsc;
+                const R m = xb + pxi * xn;
+                xn = m < mdry ? (mdry - xb) * ipxi : xn;
+            }
+            if (pmask & 16) {
+                // gimbal cone, then the ball ||T|| <= T_max centred at its apex
+                R T0 = ub[0] + pT * un[0], T1 = ub[1] + pT * un[1], T2 = ub[2] + pT * un[2];
+                proj_cone_ball<R>(T0, T1, T2, true, T_a, T_inv, Tmax);
+                un[0] = (T0 - ub[0]) * ipT;
+                un[1] = (T1 - ub[1]) * ipT;
+                un[2] = (T2 - ub[2]) * ipT;
             }
         }
         if (fixed) xn = fixv;
-        if (prim) {
-            sV[pk * VST + pj] = R(2) * xn - xt;
-            xt = omr * xt + rho * xn;
+        if (!isx) xn = R(0);
+        const R vx = R(2) * xn - xt;
+        xt = omr * xt + rho * xn;
+        R vu[NU];
+        for (int q = 0; q < NU; ++q) {
+            vu[q] = R(2) * un[q] - ut[q];
+            ut[q] = omr * ut[q] + rho * un[q];
+        }
+        if (node) {
+            sVx[k * DST + i] = vx;
+            if (i < NU) sVu[k * NU + i] = i == 0 ? vu[0] : (i == 1 ? vu[1] : (i == 2 ? vu[2] : vu[3]));
         }
         __syncthreads();
         // ---- dual (proportional-integral) step ----
-        R phn = R(0), thn = R(0), mupn = R(0), mumn = R(0);
-        if (dual) {
-            mupn = nup - alpha * (wep + vphi);
-            mumn = num - alpha * (wep - vphi);
-            mupn = mupn > R(0) ? mupn : R(0);
-            mumn = mumn > R(0) ? mumn : R(0);
-            R r = R(0);
-            for (int j = 0; j < NX; ++j) r += row[j] * sV[dk * VST + j];
-            r -= sV[(dk + 1) * VST + di];
-            for (int j = 0; j < NU; ++j) {
-                r += row[NX + j] * sV[dk * VST + NX + j];
-                r += row[NX + NU + j] * sV[(dk + 1) * VST + NX + j];
-            }
-            r += (R(2) * mupn - nup) - (R(2) * mumn - num);
-            r += wk;
-            phn = vphi + beta * r;
-            if (di == IY) {
-                const R tt = vth + beta * (sV[(dk + 1) * VST + IY] - sV[dk * VST + IY] - epsk);
-                thn = tt > R(0) ? tt : R(0);
-            }
-            vphi = omr * vphi + rho * phn;
-            nup = omr * nup + rho * mupn;
-            num = omr * num + rho * mumn;
-            sPhi[dk * DST + di] = vphi;
-            if (di == IY) {
-                vth = omr * vth + rho * thn;
-                sTh[dk] = vth;
-            }
+        R mupn = nup - alpha * (wep + vphi);
+        R mumn = num - alpha * (wep - vphi);
+        mupn = mupn > R(0) ? mupn : R(0);
+        mumn = mumn > R(0) ? mumn : R(0);
+        R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
+        const R vnext = (k + 1 < K) ? sVx[(k + 1) * DST + i] : R(0);
+        r -= vnext;
+        for (int q = 0; q < NU; ++q) {
+            const R vun = (k + 1 < K) ? sVu[(k + 1) * NU + q] : R(0);
+            r += rowBm[q] * vu[q];
+            r += rowBp[q] * vun;
+        }
+        r += (R(2) * mupn - nup) - (R(2) * mumn - num);
+        r += wk;
+        R phn = vphi + beta * r;
+        R thn = vth + beta * (vnext - vx - epsk);
+        thn = thn > R(0) ? thn : R(0);
+        if (!dual) {
+            phn = mupn = mumn = thn = R(0);
+        }
+        if (i != IY) thn = R(0);
+        vphi = omr * vphi + rho * phn;
+        nup = omr * nup + rho * mupn;
+        num = omr * num + rho * mumn;
+        vth = omr * vth + rho * thn;
+        if (k < kmax) {
+            sPhi[k * DST + i] = vphi;
+            if (i == IY) sTh[k] = vth;
         }
         bool done = false;
         if (check > 0 && it % check == 0) {
             // infinity norms of (x, u, mu+, mu-) and of (phi, theta) at j+1 and j
             double nz[6] = {0, 0, 0, 0, 0, 0};
-            if (prim) {
+            if (isx) {
                 nz[0] = fabs(double(xn));
-                nz[1] = fabs(double(xprev));
-                nz[2] = fabs(double(xn) - double(xprev));
+                nz[1] = fabs(double(xh));
+                nz[2] = fabs(double(xn) - double(xh));
             }
+            if (node && i == 0)
+                for (int q = 0; q < NU; ++q) {
+                    nz[0] = fmax(nz[0], fabs(double(un[q])));
+                    nz[1] = fmax(nz[1], fabs(double(uh[q])));
+                    nz[2] = fmax(nz[2], fabs(double(un[q]) - double(uh[q])));
+                }
             if (dual) {
                 nz[0] = fmax(nz[0], fmax(fabs(double(mupn)), fabs(double(mumn))));
-                nz[1] = fmax(nz[1], fmax(fabs(double(mupprev)), fabs(double(mumprev))));
-                nz[2] = fmax(nz[2], fmax(fabs(double(mupn) - double(mupprev)),
-                                         fabs(double(mumn) - double(mumprev))));
+                nz[1] = fmax(nz[1], fmax(fabs(double(mup)), fabs(double(mum))));
+                nz[2] = fmax(nz[2], fmax(fabs(double(mupn) - double(mup)),
+                                         fabs(double(mumn) - double(mum))));
                 nz[3] = fabs(double(phn));
-                nz[4] = fabs(double(phprev));
-                nz[5] = fabs(double(phn) - double(phprev));
-                if (di == IY) {
+                nz[4] = fabs(double(ph));
+                nz[5] = fabs(double(phn) - double(ph));
+                if (i == IY) {
                     nz[3] = fmax(nz[3], fabs(double(thn)));
-                    nz[4] = fmax(nz[4], fabs(double(thprev)));
-                    nz[5] = fmax(nz[5], fabs(double(thn) - double(thprev)));
+                    nz[4] = fmax(nz[4], fabs(double(th)));
+                    nz[5] = fmax(nz[5], fabs(double(thn) - double(th)));
                 }
             }
             block_reduce<6, true>(nz, red);
             done = nz[2] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(nz[0], nz[1]) &&
                    nz[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(nz[3], nz[4]);
         }
-        xprev = xn;
         xh = xn;
-        if (dual) {
-            mupprev = mupn;
-            mumprev = mumn;
-            phprev = phn;
-            mup = mupn;
-            mum = mumn;
-            ph = phn;
-            if (di == IY) {
-                thprev = thn;
-                th = thn;
-            }
-        }
+        for (int q = 0; q < NU; ++q) uh[q] = un[q];
+        mup = mupn;
+        mum = mumn;
+        ph = phn;
+        th = thn;
         __syncthreads();
         if (done) {
             ++it;
@@ -629,14 +700,22 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
     const int iters = it - 1;
 
     // -------------------- reference update and warm start --------------------
-    double st[1] = {prim ? fabs(double(xh)) : 0.0};
-    if (isx) a.x[xoff + pj] = R(double(xb) + a.px[pj] * double(xh));
-    if (isu) a.u[uoff + pj - NX] = R(double(xb) + a.pu[pj - NX] * double(xh));
+    double st[1] = {0.0};
+    if (isx) {
+        st[0] = fabs(double(xh));
+        a.x[xoff + i] = R(double(xb) + a.px[i] * double(xh));
+    }
+    if (node && i < NU) {
+        const R uq = i == 0 ? uh[0] : (i == 1 ? uh[1] : (i == 2 ? uh[2] : uh[3]));
+        const R ubq = i == 0 ? ub[0] : (i == 1 ? ub[1] : (i == 2 ? ub[2] : ub[3]));
+        st[0] = fmax(st[0], fabs(double(uq)));
+        a.u[uoff + i] = R(double(ubq) + a.pu[i] * double(uq));
+    }
     if (dual) {
         a.mup[doff] = mup;
         a.mum[doff] = mum;
         a.phi[doff] = ph;
-        if (di == IY) a.th[(long)b * kmax + dk] = th;
+        if (i == IY) a.th[(long)b * kmax + k] = th;
     }
     block_reduce<1, true>(st, red);
     if (t == 0) {
@@ -646,12 +725,12 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
 }
 
 // ------------------------------------------------------------------------------------------
-int qp_block_threads(int kmax) { return ((NX + NU) * kmax + 63) / 64 * 64; }
+int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
 static size_t qp_smem_bytes(int kmax, size_t rsize)
 {
-    return sizeof(double) * (128 + kmax * VST + (kmax - 1) * DST + kmax) +
-           rsize * ((kmax - 1) * DST + kmax + 2 * kmax * VST);
+    return sizeof(double) * (128 + kmax * VST + kmax * DST + kmax) +
+           rsize * (kmax * DST + kmax + kmax * DST + kmax * NU);
 }
 
 template <typename R>
