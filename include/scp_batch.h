@@ -75,7 +75,14 @@ typedef struct {
                                    PIPG projection also enforces: 1 dry mass, 2 glide slope,
                                    4 tilt, 8 rate, 16 thrust (gimbal cone and T_max);
                                    0 = the paper's set only (boundary values, s box)       */
-    int32_t mode;               /* 0: one launch per solver phase (the only mode so far)   */
+    int32_t mode;               /* 0: kernel launches per solve, workgroup b <-> instance b;
+                                   1: the launch sequence is captured once into a HIP graph
+                                   (per set of arguments) and replayed;
+                                   2: as 1, and subproblem workgroups take instances by node
+                                   count, descending (hardware dispatch as the work queue);
+                                   3: as 1, with a persistent subproblem grid (resident
+                                   workgroups pop instances from an atomic queue in that
+                                   order)                                                 */
     int32_t reserved;
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
@@ -147,6 +154,19 @@ const char *scp_batch_create_error(void);
  * Reading without profiling enabled is SCP_ERR_STATE. */
 scp_status scp_batch_profile(scp_batch h, int enable);
 scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
+
+/* Autotuner.  Times dispatch modes 1, 2 and 3 (see scp_settings.mode) with HIP events by
+ * solving `problem` into `solution` (whose contents are overwritten) and keeps the fastest
+ * mode for later solves on this handle; *mode_out receives it and ms_out[4] the measured
+ * milliseconds per mode (-1 where not timed).  With a non-NULL cache_path, a JSON-lines
+ * file keyed by (GPU arch, k_max, dtype, early_exit, node_projections, batch) is consulted
+ * first -- a hit skips the timing -- and the new result is appended.  Synchronizes the
+ * handle's stream. */
+scp_status scp_batch_autotune(scp_batch h, const scp_problem *problem, scp_solution *solution,
+                              const char *cache_path, int32_t *mode_out, double *ms_out);
+
+/* The dispatch mode the handle currently uses. */
+scp_status scp_batch_mode(scp_batch h, int32_t *mode_out);
 
 /* Release the handle (not the caller's workspace).  Synchronizes its stream first. */
 scp_status scp_batch_destroy(scp_batch h);

@@ -22,7 +22,8 @@ STATUS = {0: "SCP_OK", 1: "SCP_ERR_ARG", 2: "SCP_ERR_SHAPE", 3: "SCP_ERR_DTYPE",
 # Symbols the header declares (checked by the test-suite without a GPU).
 EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
            "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
-           "scp_batch_profile", "scp_batch_profile_read", "scp_batch_destroy"]
+           "scp_batch_profile", "scp_batch_profile_read", "scp_batch_autotune",
+           "scp_batch_mode", "scp_batch_destroy"]
 KERNEL_CLASSES = ("init", "discretize", "subproblem")
 
 
@@ -91,6 +92,13 @@ def load():
         L.scp_batch_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int32)]
         L.scp_batch_profile_read.restype = ctypes.c_int
+        L.scp_batch_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                         ctypes.POINTER(Solution), ctypes.c_char_p,
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.scp_batch_autotune.restype = ctypes.c_int
+        L.scp_batch_mode.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+        L.scp_batch_mode.restype = ctypes.c_int
         L.scp_batch_destroy.argtypes = [ctypes.c_void_p]
         L.scp_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -189,6 +197,31 @@ class BatchSolver:
                     params=t.as_tensor(np.ascontiguousarray(inst["params"]),
                                        dtype=self.dtype).to(dev),
                     K=t.as_tensor(np.ascontiguousarray(inst["K"]), dtype=t.int32).to(dev))
+
+    def _structs(self, prob, sol):
+        B = int(prob["x0"].shape[0])
+        p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
+                    prob["K"].data_ptr())
+        s = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status",
+                                                    "scp_iters", "pipg_iters", "defect_inf",
+                                                    "ctcs_viol", "objective")])
+        return p, s
+
+    def autotune(self, prob, sol, cache_path=None):
+        """Time the dispatch modes on this batch and keep the fastest (see
+        scp_batch_autotune); returns (mode, {mode: ms})."""
+        p, s = self._structs(prob, sol)
+        mode = ctypes.c_int32(-1)
+        ms = (ctypes.c_double * 4)()
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(load().scp_batch_autotune(self.handle, ctypes.byref(p), ctypes.byref(s),
+                                              path, ctypes.byref(mode), ms))
+        return mode.value, {m: ms[m] for m in range(1, 4) if ms[m] >= 0}
+
+    def mode(self):
+        m = ctypes.c_int32(-1)
+        self._check(load().scp_batch_mode(self.handle, ctypes.byref(m)))
+        return m.value
 
     def solve_into(self, prob, sol):
         """Enqueue a solve of device problem tensors into preallocated solution tensors."""

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <new>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -22,7 +24,7 @@ thread_local std::string g_create_error;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, total;
+    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, queue, bucket, order, total;
 };
 
 bool settings_ok(const scp_settings *s, std::string &why)
@@ -37,7 +39,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
         return false;
     }
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
-    if (s->mode != 0) { why = "mode must be 0"; return false; }
+    if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -77,6 +79,9 @@ Layout layout_of(const scp_settings *s)
     L.th = take(B * K * rs);
     L.step = take(B * 8);
     L.pipg_total = take(B * 4);
+    L.queue = take((size_t)(s->scp_iters_max + 2) * 4);
+    L.bucket = take((K + 1) * 4);
+    L.order = take(B * 4);
     L.total = off == 0 ? ALIGN : off;
     return L;
 }
@@ -96,7 +101,23 @@ struct scp_batch_s {
     std::vector<int> kinds;
     scp::LaunchTimer timer{nullptr, nullptr, 0, 0};
     bool profiling = false;
+    int persistent_grid = 0;  // workgroups of the persistent subproblem kernel (0: not set)
+    // graph replay (mode 1): the launch sequence of one solve, captured once per set of
+    // arguments on a private stream and replayed on the handle's stream
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_key[15] = {};
 };
+
+static void drop_graph(scp_batch h)
+{
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    for (auto &k : h->graph_key) k = nullptr;
+}
 
 static void drop_events(scp_batch h)
 {
@@ -221,6 +242,17 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
     cfg.power_iters_max = s.power_iters_max;
     cfg.early_exit = s.early_exit;
     cfg.node_projections = s.node_projections;
+    cfg.persistent_blocks = 0;
+    cfg.ordered = s.mode == 2 ? 1 : 0;
+    if (s.mode == 3) {
+        if (h->persistent_grid == 0) {
+            hipDeviceProp_t prop;
+            e = hipGetDeviceProperties(&prop, h->device);
+            if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+            h->persistent_grid = prop.multiProcessorCount * scp::qp_blocks_per_cu(cfg.dtype, s.k_max);
+        }
+        cfg.persistent_blocks = h->persistent_grid;
+    }
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -249,7 +281,49 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
     W.th = h->ws + h->L.th;
     W.step = reinterpret_cast<double *>(h->ws + h->L.step);
     W.pipg_total = reinterpret_cast<int32_t *>(h->ws + h->L.pipg_total);
-    e = scp::launch_solve(cfg, P, S, W, h->stream, h->profiling ? &h->timer : nullptr);
+    W.queue = reinterpret_cast<int32_t *>(h->ws + h->L.queue);
+    W.bucket = reinterpret_cast<int32_t *>(h->ws + h->L.bucket);
+    W.order = reinterpret_cast<int32_t *>(h->ws + h->L.order);
+    if (h->st.mode >= 1 && !h->profiling) {
+        // replay a captured graph of the whole launch sequence when the arguments match
+        const void *key[15] = {reinterpret_cast<const void *>((intptr_t)prob->batch), prob->x0,
+                               prob->xf, prob->params, prob->K, sol->x, sol->u, sol->t_f,
+                               sol->m_f, sol->status, sol->scp_iters, sol->pipg_iters,
+                               sol->defect_inf, sol->ctcs_viol, sol->objective};
+        if (!h->graph_exec || memcmp(key, h->graph_key, sizeof(key)) != 0) {
+            drop_graph(h);
+            if (!h->cap_stream) {
+                e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    h->cap_stream = nullptr;
+                    if (cur != h->device) (void)hipSetDevice(cur);
+                    return fail(h, SCP_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+                }
+            }
+            e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t el = scp::launch_solve(cfg, P, S, W, h->cap_stream, nullptr);
+                hipGraph_t g = nullptr;
+                e = hipStreamEndCapture(h->cap_stream, &g);
+                if (el != hipSuccess) e = el;
+                if (e == hipSuccess) {
+                    h->graph = g;
+                    e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+                } else if (g) {
+                    (void)hipGraphDestroy(g);
+                }
+            }
+            if (e != hipSuccess) {
+                drop_graph(h);
+                if (cur != h->device) (void)hipSetDevice(cur);
+                return fail(h, SCP_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            }
+            memcpy(h->graph_key, key, sizeof(key));
+        }
+        e = hipGraphLaunch(h->graph_exec, h->stream);
+    } else {
+        e = scp::launch_solve(cfg, P, S, W, h->stream, h->profiling ? &h->timer : nullptr);
+    }
     if (cur != h->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SCP_OK;
@@ -306,11 +380,115 @@ scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches)
     return SCP_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// Autotuner: time the dispatch modes on the caller's batch and keep the fastest.
+// ------------------------------------------------------------------------------------------
+static std::string tune_key(scp_batch h, int batch)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << ":kmax=" << h->st.k_max << ":dtype=" << (h->st.dtype == SCP_F64 ? "f64" : "f32")
+      << ":early_exit=" << h->st.early_exit << ":proj=" << h->st.node_projections
+      << ":batch=" << batch;
+    return k.str();
+}
+
+static int cache_lookup(const char *path, const std::string &key)
+{
+    if (!path) return -1;
+    std::ifstream f(path);
+    std::string line;
+    int found = -1;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(pat) == std::string::npos) continue;
+        const size_t m = line.find("\"mode\": ");
+        if (m != std::string::npos) found = atoi(line.c_str() + m + 8);
+    }
+    return (found >= 0 && found <= 3) ? found : -1;
+}
+
+scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution *sol,
+                              const char *cache_path, int32_t *mode_out, double *ms_out)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (!prob || !sol || !mode_out || !ms_out) return fail(h, SCP_ERR_ARG, "null argument");
+    for (int m = 0; m < 4; ++m) ms_out[m] = -1.0;
+    const std::string key = tune_key(h, prob->batch);
+    const int cached = cache_lookup(cache_path, key);
+    if (cached >= 0) {
+        h->st.mode = cached;
+        drop_graph(h);
+        *mode_out = cached;
+        return SCP_OK;
+    }
+    if (h->profiling) return fail(h, SCP_ERR_STATE, "disable profiling before autotuning");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(h, SCP_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+    const int saved_mode = h->st.mode;
+    int best = -1;
+    double best_ms = 0.0;
+    for (int m = 1; m <= 3; ++m) {
+        h->st.mode = m;
+        drop_graph(h);
+        scp_status st = scp_batch_solve(h, prob, sol);  // capture + warm-up
+        if (st != SCP_OK) break;
+        float t = 0.0f;
+        e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess && scp_batch_solve(h, prob, sol) != SCP_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) break;
+        ms_out[m] = t;
+        if (best < 0 || t < best_ms) {
+            best = m;
+            best_ms = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) {
+        h->st.mode = saved_mode;
+        drop_graph(h);
+        if (h->err.empty()) h->err = std::string("autotune: ") + hipGetErrorString(e);
+        return SCP_ERR_HIP;
+    }
+    h->st.mode = best;
+    drop_graph(h);
+    *mode_out = best;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        f << "{\"key\": \"" << key << "\", \"mode\": " << best << ", \"ms\": [" << ms_out[1]
+          << ", " << ms_out[2] << ", " << ms_out[3] << "]}\n";
+    }
+    return SCP_OK;
+}
+
+scp_status scp_batch_mode(scp_batch h, int32_t *mode_out)
+{
+    if (!h || !mode_out) return SCP_ERR_ARG;
+    *mode_out = h->st.mode;
+    return SCP_OK;
+}
+
 scp_status scp_batch_destroy(scp_batch h)
 {
     if (!h) return SCP_ERR_ARG;
     hipError_t e = hipStreamSynchronize(h->stream);
     drop_events(h);
+    drop_graph(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return e == hipSuccess ? SCP_OK : SCP_ERR_HIP;
 }

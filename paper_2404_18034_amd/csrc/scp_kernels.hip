@@ -51,6 +51,10 @@ struct Args {
     R *blocks, *what, *mup, *mum, *phi, *th;
     double *dy, *step;
     int32_t *pipg_total;
+    int32_t *queue;   // [scp_iters_max + 2] work-queue heads (persistent form)
+    int32_t *bucket;  // [kmax + 1] counting-sort buckets
+    int32_t *order;   // [B] instances by node count, descending
+    int use_order;    // subproblem workgroup w solves instance order[w]
 };
 
 // ------------------------------------------------------------------------------------------
@@ -72,6 +76,10 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
         for (int i = 0; i < DST; ++i) a.mup[o + i] = a.mum[o + i] = a.phi[o + i] = R(0);
     }
     a.th[(long)b * a.kmax + k] = R(0);
+    if (b == 0) {
+        for (int q = k; q < a.scp_iters_max + 2; q += a.kmax) a.queue[q] = 0;
+        for (int q = k; q <= a.kmax; q += a.kmax) a.bucket[q] = 0;
+    }
     if (k == 0) {
         a.status[b] = valid ? -1 : 3;
         a.scp_iters[b] = 0;
@@ -323,16 +331,18 @@ __device__ __forceinline__ void proj_cone_ball(R &t, R &z0, R &z1, bool cone, R 
 // The block products inside an interval use row broadcasts of register values (DPP);
 // only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
-template <typename R, int MAXT>
-__global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
+template <typename R>
+__device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
+                                                unsigned char *smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int b = blockIdx.x;
     if (b >= a.B) return;
     if (a.status[b] >= 0) return;  // uniform over the workgroup
     const int K = a.K[b], M = K - 1, kmax = a.kmax;
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
+    // waves whose four rows all lie beyond the instance's last node skip the arithmetic
+    // (they only take part in the barriers and reductions)
+    const bool wact = ((t >> 6) << 2) < K;
 
     // LDS carve (doubles first for alignment)
     double *red = reinterpret_cast<double *>(smem_raw);          // [16 waves * 8]
@@ -455,7 +465,7 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
             if (isu) dZ[k * VST + NX + i] = zu;
             __syncthreads();
             double ph = 0.0;
-            if (dual) {
+            if (wact && dual) {
                 double r = 0.0;
                 for (int j = 0; j < NX; ++j) r += double(rowA[j]) * dZ[k * VST + j];
                 r -= dZ[(k + 1) * VST + i];
@@ -480,7 +490,7 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
                 }
                 zx = r;
             }
-            {
+            if (wact) {
                 // control part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
                 const double phk = dual ? dPhi[k * DST + i] : 0.0;
                 const double phm = (k > 0 && k <= M && i < NX) ? dPhi[(k - 1) * DST + i] : 0.0;
@@ -565,6 +575,10 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
 
     int it = 1;
     for (; it <= jmax; ++it) {
+        R xn = R(0), un[NU] = {R(0), R(0), R(0), R(0)};
+        R vx = R(0), vu[NU] = {R(0), R(0), R(0), R(0)};
+        R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
+        if (wact) {
         // ---- projected gradient step on the primal variables ----
         const R phm1 = (k > 0 && k < kmax) ? sPhi[(k - 1) * DST + i] : R(0);  // phi_{k-1}[i]
         const R thm1 = (k > 0 && k < kmax) ? sTh[k - 1] : R(0);               // theta_{k-1}
@@ -573,9 +587,8 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
         g = rowdot15<R>(colA, vphi, g);  // (A^-_k)^T phi_k, column i
         g -= (k > 0) ? phm1 : R(0);
         if (i == IY) g += (k < M ? -thk : R(0)) + (k > 0 ? thm1 : R(0));
-        R xn = xt - alpha * g;
+        xn = xt - alpha * g;
         // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
-        R un[NU];
         for (int q = 0; q < NU; ++q) {
             R gq = rowBm[q] * vphi + rowBq[q] * phm1;
             gq = row_allreduce<R>(gq);
@@ -610,9 +623,8 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
         }
         if (fixed) xn = fixv;
         if (!isx) xn = R(0);
-        const R vx = R(2) * xn - xt;
+        vx = R(2) * xn - xt;
         xt = omr * xt + rho * xn;
-        R vu[NU];
         for (int q = 0; q < NU; ++q) {
             vu[q] = R(2) * un[q] - ut[q];
             ut[q] = omr * ut[q] + rho * un[q];
@@ -621,10 +633,12 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
             sVx[k * DST + i] = vx;
             if (i < NU) sVu[k * NU + i] = i == 0 ? vu[0] : (i == 1 ? vu[1] : (i == 2 ? vu[2] : vu[3]));
         }
+        }  // wact
         __syncthreads();
+        if (wact) {
         // ---- dual (proportional-integral) step ----
-        R mupn = nup - alpha * (wep + vphi);
-        R mumn = num - alpha * (wep - vphi);
+        mupn = nup - alpha * (wep + vphi);
+        mumn = num - alpha * (wep - vphi);
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
         R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
@@ -637,8 +651,8 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
         }
         r += (R(2) * mupn - nup) - (R(2) * mumn - num);
         r += wk;
-        R phn = vphi + beta * r;
-        R thn = vth + beta * (vnext - vx - epsk);
+        phn = vphi + beta * r;
+        thn = vth + beta * (vnext - vx - epsk);
         thn = thn > R(0) ? thn : R(0);
         if (!dual) {
             phn = mupn = mumn = thn = R(0);
@@ -652,6 +666,7 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
             sPhi[k * DST + i] = vphi;
             if (i == IY) sTh[k] = vth;
         }
+        }  // wact
         bool done = false;
         if (check > 0 && it % check == 0) {
             // infinity norms of (x, u, mu+, mu-) and of (phi, theta) at j+1 and j
@@ -725,6 +740,71 @@ __global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
 }
 
 // ------------------------------------------------------------------------------------------
+
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // with ordered dispatch, workgroup w takes the w-th instance by node count (descending):
+    // the hardware issues workgroups as earlier ones retire, so the longest instances start
+    // first and the short ones fill in behind them
+    const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]) : blockIdx.x;
+    subproblem_body<R>(a, b, smem_raw);
+}
+
+// Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
+// counter per SCP iteration, the only atomic) in the order of `order` (node count
+// descending, so the longest instances start first).  Which workgroup solves which instance
+// does not change any result.
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) subproblem_persistent(Args<R> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_next;
+    if (threadIdx.x == 0) s_next = atomicAdd(&a.queue[a.j], 1);
+    __syncthreads();
+    int idx = s_next;
+    while (idx < a.B) {
+        subproblem_body<R>(a, __builtin_amdgcn_readfirstlane(a.order[idx]), smem_raw);
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = atomicAdd(&a.queue[a.j], 1);
+        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(s_next);
+    }
+}
+
+// Order instances by node count, descending (counting sort; equal counts in any order).
+template <typename R>
+__global__ void order_histogram(Args<R> a)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B) return;
+    const int K = a.K[b];
+    const int key = (K >= 2 && K <= a.kmax) ? a.kmax - K : a.kmax;  // invalid last
+    atomicAdd(&a.bucket[key], 1);
+}
+template <typename R>
+__global__ void order_scan(Args<R> a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    for (int q = 0; q <= a.kmax; ++q) {
+        const int c = a.bucket[q];
+        a.bucket[q] = acc;
+        acc += c;
+    }
+}
+template <typename R>
+__global__ void order_scatter(Args<R> a)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B) return;
+    const int K = a.K[b];
+    const int key = (K >= 2 && K <= a.kmax) ? a.kmax - K : a.kmax;
+    a.order[atomicAdd(&a.bucket[key], 1)] = b;
+}
+
+// ------------------------------------------------------------------------------------------
 int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
 static size_t qp_smem_bytes(int kmax, size_t rsize)
@@ -785,6 +865,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.dy = ws.dy;
     a.step = ws.step;
     a.pipg_total = ws.pipg_total;
+    a.queue = ws.queue;
+    a.bucket = ws.bucket;
+    a.order = ws.order;
 
     if (cfg.B == 0) return hipSuccess;
     int nl = 0;
@@ -807,6 +890,16 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
     const int qthreads = qp_block_threads(cfg.kmax);
     const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
+    const bool persistent = cfg.persistent_blocks > 0;
+    a.use_order = cfg.ordered ? 1 : 0;
+    if (persistent || cfg.ordered) {
+        const unsigned nb = (unsigned)((cfg.B + 255) / 256);
+        order_histogram<R><<<dim3(nb), dim3(256), 0, stream>>>(a);
+        order_scan<R><<<dim3(1), dim3(64), 0, stream>>>(a);
+        order_scatter<R><<<dim3(nb), dim3(256), 0, stream>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const unsigned pgrid = (unsigned)(cfg.persistent_blocks < cfg.B ? cfg.persistent_blocks : cfg.B);
     for (int j = 1; j <= cfg.scp_iters_max + 1; ++j) {
         a.j = j;
         const int need_blocks = j <= cfg.scp_iters_max ? 1 : 0;
@@ -816,10 +909,16 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(1, false)) != hipSuccess) return e;
         if ((e = mark(2, true)) != hipSuccess) return e;
-        if (qthreads <= 640)
+        if (persistent) {
+            if (qthreads <= 640)
+                subproblem_persistent<R, 640><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+            else
+                subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+        } else if (qthreads <= 640) {
             subproblem_kernel<R, 640><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
-        else
+        } else {
             subproblem_kernel<R, 1024><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(2, false)) != hipSuccess) return e;
     }
@@ -833,4 +932,26 @@ hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &
     return launch_typed<float>(cfg, prob, sol, ws, stream, timer);
 }
 
+}  // namespace scp
+
+namespace scp {
+int qp_blocks_per_cu(int dtype, int kmax)
+{
+    const int threads = qp_block_threads(kmax);
+    int n = 0;
+    hipError_t e;
+    if (dtype == 1)
+        e = threads <= 640
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<double, 640>,
+                                                               threads, qp_smem_bytes(kmax, 8))
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<double, 1024>,
+                                                               threads, qp_smem_bytes(kmax, 8));
+    else
+        e = threads <= 640
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<float, 640>,
+                                                               threads, qp_smem_bytes(kmax, 4))
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<float, 1024>,
+                                                               threads, qp_smem_bytes(kmax, 4));
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
 }  // namespace scp

@@ -18,6 +18,9 @@ struct Workspace {
     void *th;           // R  [B][kmax]            warm start dual of the CTCS rows
     double *step;       // f64 [B]                  scaled step of the last subproblem
     int32_t *pipg_total;// i32 [B]
+    int32_t *queue;     // i32 [scp_iters_max + 2]  work-queue heads (persistent form)
+    int32_t *bucket;    // i32 [kmax + 1]           node-count buckets
+    int32_t *order;     // i32 [B]                  instances by node count, descending
 };
 
 struct Config {
@@ -25,6 +28,8 @@ struct Config {
     int B, kmax;
     int scp_iters_max, pipg_iters_max, pipg_check_every, rk4_substeps, power_iters_max;
     int early_exit, node_projections;
+    int persistent_blocks;  // 0: one workgroup per instance; > 0: persistent grid size
+    int ordered;            // 1: workgroups take instances by node count, descending
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
@@ -56,7 +61,10 @@ struct LaunchTimer {
 hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &sol,
                         const Workspace &ws, hipStream_t stream, LaunchTimer *timer);
 
-// Largest workgroup the subproblem kernel uses for node count kmax.
+// Workgroup size of the subproblem kernel for node count kmax.
 int qp_block_threads(int kmax);
+
+// Resident workgroups per compute unit of the persistent subproblem kernel (occupancy query).
+int qp_blocks_per_cu(int dtype, int kmax);
 
 }  // namespace scp

@@ -233,3 +233,52 @@ def test_invalid_arguments_raise():
     with pytest.raises(api.ScpError):
         s.solve(bad)
     s.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_dispatch_modes_match_plain_launches(mode):
+    # graph replay, K-ordered dispatch and the persistent work queue compute the same thing as
+    # plain launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
+    import torch
+    cfg = I.solver_settings("C2")
+    inst = I.make_instances("C2", B=40)
+    ref = _gpu(cfg, inst, "f32", k_max=30)
+    s = api.BatchSolver(dict(cfg, mode=mode), dtype="f32", k_max=30, max_batch=64)
+    prob = s.to_device(inst)
+    sol = s.alloc_solution(40)
+    for rep in range(3):
+        for v in sol.values():
+            v.zero_()
+        s.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        for k in ref:
+            np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k], err_msg="%s rep %d" % (k, rep))
+    # a smaller batch on the same handle re-captures
+    small = s.to_device(I.make_instances("C2", B=7))
+    sol7 = s.solve(small)
+    torch.cuda.synchronize()
+    for k in ref:
+        np.testing.assert_array_equal(sol7[k].cpu().numpy(), ref[k][:7])
+    s.close()
+
+
+def test_autotune_picks_a_mode_and_keeps_results(tmp_path):
+    import torch
+    cfg = I.solver_settings("C1", scp_iters_max=3, pipg_iters_max=200)
+    inst = I.make_instances("C1", B=64)
+    ref = _gpu(cfg, inst, "f32")
+    s = api.BatchSolver(cfg, dtype="f32", k_max=20, max_batch=64)
+    prob = s.to_device(inst)
+    sol = s.alloc_solution(64)
+    cache = tmp_path / "tune.jsonl"
+    mode, ms = s.autotune(prob, sol, cache_path=cache)
+    print("autotune", mode, ms)
+    assert mode in (1, 2, 3) and s.mode() == mode and len(ms) == 3
+    assert cache.read_text().count("\n") == 1
+    mode2, ms2 = s.autotune(prob, sol, cache_path=cache)     # cache hit: no timing
+    assert mode2 == mode and ms2 == {}
+    s.solve_into(prob, sol)
+    torch.cuda.synchronize()
+    for k in ref:
+        np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k])
+    s.close()
