@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (instances are independent; a multi-GPU run would "
@@ -67,6 +70,15 @@ def main():
     import torch
     from paper_2404_18034_amd import api
     from paper_2404_18034_amd import instances as I
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfgd = I.CONFIGS[WORKLOAD]
     cfg = I.solver_settings(WORKLOAD)

@@ -83,6 +83,9 @@ typedef struct {
                                    3: as 1, with a persistent subproblem grid (resident
                                    workgroups pop instances from an atomic queue in that
                                    order)                                                 */
+    int32_t grad_pipg_steps;    /* PIPG steps of the differentiated last iteration (0: the
+                                   handle computes no gradients and carves no scratch)     */
+    int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */
     int32_t reserved;
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
@@ -167,6 +170,44 @@ scp_status scp_batch_autotune(scp_batch h, const scp_problem *problem, scp_solut
 
 /* The dispatch mode the handle currently uses. */
 scp_status scp_batch_mode(scp_batch h, int32_t *mode_out);
+
+/* Starting point of the last convex subproblem an instance solved: the reference trajectory
+ * it linearized about, the warm-start duals (mu+, mu-, the dynamics dual phi and the CTCS
+ * dual theta; x^ and u^ start at zero) and the buffered power-iteration estimate sigma.
+ * Caller-owned device arrays; rows beyond an instance's K are not written.  Real arrays have
+ * the handle's dtype. */
+typedef struct {
+    void *xbar;                 /* real [B][k_max][15]                                     */
+    void *ubar;                 /* real [B][k_max][4]                                      */
+    void *mup, *mum, *phi;      /* real [B][k_max-1][15]                                   */
+    void *th;                   /* real [B][k_max-1]                                       */
+    double *sigma;              /* f64  [B]                                                */
+} scp_lastiter;
+
+/* As scp_batch_solve, and every subproblem also writes its starting point into `last`, so
+ * that after the solve `last` holds each instance's last subproblem (the input of
+ * scp_batch_grad).  Asynchronous on the handle's stream. */
+scp_status scp_batch_solve_record(scp_batch h, const scp_problem *problem,
+                                  scp_solution *solution, const scp_lastiter *last);
+
+/* Vector-Jacobian product of the last SCP iteration.  The differentiated map, an extension
+ * (the paper does not differentiate its solver), takes
+ *     theta = (x0[15], m_wet, alpha_mdot, T_max)
+ * to (m_f, t_f) through one SCP iteration started from `last`: the discretization at
+ * last->xbar/ubar (section "Discretization" with the variational equations of "Gradient of
+ * Discretized Dynamics"), the prescaled subproblem ("Convex Subproblem with Prescaling and
+ * Preconditioning"), settings.grad_pipg_steps steps of PIPG_custom (Algorithm "PIPG_custom",
+ * no early exit) from last's warm start with step sizes from last->sigma, and the reference
+ * update; m_f = m at the last node, t_f the integral of s.  m_wet is the initial-mass
+ * boundary value, so a change of m_wet moves x0[0] with it.
+ *   cotangent  real [B][2]  (c_m, c_t)
+ *   grad       real [B][18] c_m dm_f/dtheta + c_t dt_f/dtheta (zero for invalid instances)
+ *   value      real [B][2]  (m_f, t_f) of the map, or NULL
+ * The reverse sweep recomputes the PIPG steps from checkpoints every grad_ckpt_every steps.
+ * Needs a handle created with grad_pipg_steps > 0 (SCP_ERR_STATE otherwise).  Uses the
+ * handle's workspace: do not overlap with a solve on the same handle.  Asynchronous. */
+scp_status scp_batch_grad(scp_batch h, const scp_problem *problem, const scp_lastiter *last,
+                          const void *cotangent, void *grad, void *value);
 
 /* Release the handle (not the caller's workspace).  Synchronizes its stream first. */
 scp_status scp_batch_destroy(scp_batch h);

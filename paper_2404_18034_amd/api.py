@@ -23,7 +23,7 @@ STATUS = {0: "SCP_OK", 1: "SCP_ERR_ARG", 2: "SCP_ERR_SHAPE", 3: "SCP_ERR_DTYPE",
 EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
            "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
            "scp_batch_profile", "scp_batch_profile_read", "scp_batch_autotune",
-           "scp_batch_mode", "scp_batch_destroy"]
+           "scp_batch_mode", "scp_batch_solve_record", "scp_batch_grad", "scp_batch_destroy"]
 KERNEL_CLASSES = ("init", "discretize", "subproblem")
 
 
@@ -40,6 +40,7 @@ class Settings(ctypes.Structure):
         ("pipg_check_every", ctypes.c_int32), ("rk4_substeps", ctypes.c_int32),
         ("power_iters_max", ctypes.c_int32), ("early_exit", ctypes.c_int32),
         ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("grad_pipg_steps", ctypes.c_int32), ("grad_ckpt_every", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
@@ -59,6 +60,13 @@ class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("x", "u", "t_f", "m_f", "status", "scp_iters",
                                                "pipg_iters", "defect_inf", "ctcs_viol",
                                                "objective")]
+
+
+LASTITER_FIELDS = ("xbar", "ubar", "mup", "mum", "phi", "th", "sigma")
+
+
+class LastIter(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in LASTITER_FIELDS]
 
 
 _lib = None
@@ -99,6 +107,13 @@ def load():
         L.scp_batch_autotune.restype = ctypes.c_int
         L.scp_batch_mode.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
         L.scp_batch_mode.restype = ctypes.c_int
+        L.scp_batch_solve_record.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                             ctypes.POINTER(Solution), ctypes.POINTER(LastIter)]
+        L.scp_batch_solve_record.restype = ctypes.c_int
+        L.scp_batch_grad.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                     ctypes.POINTER(LastIter), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        L.scp_batch_grad.restype = ctypes.c_int
         L.scp_batch_destroy.argtypes = [ctypes.c_void_p]
         L.scp_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -115,6 +130,8 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
                  "power_iters_max", "early_exit", "node_projections"):
         setattr(s, name, int(cfg[name]))
     s.mode = int(cfg.get("mode", 0))
+    s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
+    s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",
                  "power_eps_rel", "power_buff", "w_cost", "w_prox", "w_ep", "omega", "rho"):
         setattr(s, name, float(cfg[name]))
@@ -202,6 +219,8 @@ class BatchSolver:
         B = int(prob["x0"].shape[0])
         p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
                     prob["K"].data_ptr())
+        if sol is None:
+            return p, None
         s = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status",
                                                     "scp_iters", "pipg_iters", "defect_inf",
                                                     "ctcs_viol", "objective")])
@@ -223,8 +242,7 @@ class BatchSolver:
         self._check(load().scp_batch_mode(self.handle, ctypes.byref(m)))
         return m.value
 
-    def solve_into(self, prob, sol):
-        """Enqueue a solve of device problem tensors into preallocated solution tensors."""
+    def _check_problem(self, prob):
         B = int(prob["x0"].shape[0])
         for k, shape in (("x0", (B, NX)), ("xf", (B, NXF)), ("params", (B, NP))):
             v = prob[k]
@@ -233,13 +251,68 @@ class BatchSolver:
                                (k, self.dtype, shape))
         if tuple(prob["K"].shape) != (B,) or prob["K"].dtype != self.torch.int32:
             raise ScpError(2, "K must be an int32 tensor of shape (B,)")
-        p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
-                    prob["K"].data_ptr())
-        s = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status",
-                                                    "scp_iters", "pipg_iters", "defect_inf",
-                                                    "ctcs_viol", "objective")])
+        return B
+
+    def _check_real(self, name, v, shape, dtype=None):
+        dtype = self.dtype if dtype is None else dtype
+        if tuple(v.shape) != tuple(shape) or v.dtype != dtype or not v.is_contiguous():
+            raise ScpError(2, "%s must be a contiguous %s tensor of shape %s" % (name, dtype, shape))
+
+    def solve_into(self, prob, sol):
+        """Enqueue a solve of device problem tensors into preallocated solution tensors."""
+        self._check_problem(prob)
+        p, s = self._structs(prob, sol)
         self._check(load().scp_batch_solve(self.handle, ctypes.byref(p), ctypes.byref(s)))
         return sol
+
+    def alloc_lastiter(self, B):
+        """Device buffers for the starting point of each instance's last subproblem."""
+        t = self.torch
+        dev = "cuda:%d" % self.device
+        km, M = self.k_max, self.k_max - 1
+        return dict(xbar=t.zeros((B, km, NX), dtype=self.dtype, device=dev),
+                    ubar=t.zeros((B, km, NU), dtype=self.dtype, device=dev),
+                    mup=t.zeros((B, M, NX), dtype=self.dtype, device=dev),
+                    mum=t.zeros((B, M, NX), dtype=self.dtype, device=dev),
+                    phi=t.zeros((B, M, NX), dtype=self.dtype, device=dev),
+                    th=t.zeros((B, M), dtype=self.dtype, device=dev),
+                    sigma=t.zeros(B, dtype=t.float64, device=dev))
+
+    def _lastiter_struct(self, last, B):
+        km, M = self.k_max, self.k_max - 1
+        shapes = dict(xbar=(B, km, NX), ubar=(B, km, NU), mup=(B, M, NX), mum=(B, M, NX),
+                      phi=(B, M, NX), th=(B, M), sigma=(B,))
+        for k, shp in shapes.items():
+            self._check_real(k, last[k], shp, self.torch.float64 if k == "sigma" else None)
+        return LastIter(*[last[n].data_ptr() for n in LASTITER_FIELDS])
+
+    def solve_record_into(self, prob, sol, last):
+        """Solve, and record into `last` the starting point of each instance's last
+        subproblem (scp_batch_solve_record)."""
+        B = self._check_problem(prob)
+        p, s = self._structs(prob, sol)
+        r = self._lastiter_struct(last, B)
+        self._check(load().scp_batch_solve_record(self.handle, ctypes.byref(p), ctypes.byref(s),
+                                                  ctypes.byref(r)))
+        return sol, last
+
+    def grad_into(self, prob, last, cot, grad, value=None):
+        """Vector-Jacobian product of the last SCP iteration (scp_batch_grad):
+        grad[B, 18] = cot[:, 0] dm_f/dtheta + cot[:, 1] dt_f/dtheta, theta = (x0, m_wet,
+        alpha_mdot, T_max); value[B, 2] (optional) receives (m_f, t_f) of that map."""
+        B = self._check_problem(prob)
+        p, _ = self._structs(prob, None)
+        r = self._lastiter_struct(last, B)
+        self._check_real("cot", cot, (B, 2))
+        self._check_real("grad", grad, (B, 18))
+        if value is not None:
+            self._check_real("value", value, (B, 2))
+        self._check(load().scp_batch_grad(self.handle, ctypes.byref(p), ctypes.byref(r),
+                                          ctypes.c_void_p(cot.data_ptr()),
+                                          ctypes.c_void_p(grad.data_ptr()),
+                                          None if value is None else
+                                          ctypes.c_void_p(value.data_ptr())))
+        return grad
 
     def profile(self, enable=True):
         """Turn per-launch HIP-event timing on or off (see scp_batch_profile)."""
@@ -271,3 +344,57 @@ def solve(cfg, inst, dtype="f32", k_max=None, device=0):
         return {k: v.cpu().numpy() for k, v in sol.items()}
     finally:
         s.close()
+
+
+_SOLVE_FN = None
+
+
+def _solve_fn():
+    global _SOLVE_FN
+    if _SOLVE_FN is None:
+        import torch
+
+        class ScpSolve(torch.autograd.Function):
+            """Forward: the batched solve, recording each instance's last subproblem; returns
+            (m_f, t_f).  Backward: the vector-Jacobian product of the last SCP iteration
+            (scp_batch_grad: the discretization, the subproblem and grad_pipg_steps PIPG steps
+            at the recorded starting point) with respect to x0 and to the params columns
+            alpha_mdot (2) and T_max (13).  The solve takes the initial mass from x0[0], so
+            params column 0 (m_wet) and the other columns receive no gradient."""
+
+            @staticmethod
+            def forward(ctx, x0, params, solver, xf, K):
+                prob = dict(x0=x0.detach().contiguous(), xf=xf.detach().contiguous(),
+                            params=params.detach().contiguous(), K=K)
+                B = int(x0.shape[0])
+                sol = solver.alloc_solution(B)
+                last = solver.alloc_lastiter(B)
+                solver.solve_record_into(prob, sol, last)
+                ctx.solver, ctx.prob, ctx.last = solver, prob, last
+                return sol["m_f"].clone(), sol["t_f"].clone()
+
+            @staticmethod
+            def backward(ctx, g_m, g_t):
+                solver, prob = ctx.solver, ctx.prob
+                B = int(prob["x0"].shape[0])
+                dev = prob["x0"].device
+                z = torch.zeros(B, dtype=solver.dtype, device=dev)
+                cot = torch.stack([z if g_m is None else g_m.to(solver.dtype),
+                                   z if g_t is None else g_t.to(solver.dtype)], dim=1).contiguous()
+                g = torch.empty((B, 18), dtype=solver.dtype, device=dev)
+                solver.grad_into(prob, ctx.last, cot, g)
+                g_x0 = g[:, :NX].clone()
+                g_p = torch.zeros_like(prob["params"])
+                g_p[:, 2] = g[:, 16]
+                g_p[:, 13] = g[:, 17]
+                return g_x0, g_p, None, None, None
+
+        _SOLVE_FN = ScpSolve
+    return _SOLVE_FN
+
+
+def solve_differentiable(solver, x0, params, xf, K):
+    """(m_f, t_f) of the batched solve as torch functions of x0 [B, 15] and params [B, 22]
+    (device tensors of the solver's dtype); gradients flow through the last SCP iteration.
+    The solver must have been created with grad_pipg_steps > 0."""
+    return _solve_fn().apply(x0, params, solver, xf, K)

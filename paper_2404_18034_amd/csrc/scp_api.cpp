@@ -24,7 +24,9 @@ thread_local std::string g_create_error;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, queue, bucket, order, total;
+    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, queue, bucket, order;
+    size_t dblk, dwhat, tape, gstat;  // gradient scratch (present when grad_pipg_steps > 0)
+    size_t total;
 };
 
 bool settings_ok(const scp_settings *s, std::string &why)
@@ -49,6 +51,12 @@ bool settings_ok(const scp_settings *s, std::string &why)
         if (!(s->px[i] > 0.0) || !isfinite(s->px[i])) { why = "px entries must be > 0"; return false; }
     for (int i = 0; i < 4; ++i)
         if (!(s->pu[i] > 0.0) || !isfinite(s->pu[i])) { why = "pu entries must be > 0"; return false; }
+    if (s->grad_pipg_steps < 0 ||
+        (s->grad_pipg_steps > 0 &&
+         (s->grad_ckpt_every < 1 || s->grad_ckpt_every > s->grad_pipg_steps))) {
+        why = "grad_pipg_steps must be >= 0 and, when > 0, 1 <= grad_ckpt_every <= grad_pipg_steps";
+        return false;
+    }
     if (s->node_projections < 0 || s->node_projections > 31) {
         why = "node_projections is a bitmask in [0, 31]";
         return false;
@@ -82,6 +90,14 @@ Layout layout_of(const scp_settings *s)
     L.queue = take((size_t)(s->scp_iters_max + 2) * 4);
     L.bucket = take((K + 1) * 4);
     L.order = take(B * 4);
+    L.dblk = L.dwhat = L.tape = L.gstat = 0;
+    if (s->grad_pipg_steps > 0) {
+        const size_t n_ckpt = (size_t)((s->grad_pipg_steps + s->grad_ckpt_every - 1) / s->grad_ckpt_every);
+        L.dblk = take(B * M * 2 * 23 * 16 * rs);
+        L.dwhat = take(B * M * 2 * 16 * rs);
+        L.tape = take(B * (n_ckpt + (size_t)s->grad_ckpt_every) * (size_t)scp::grad_state_len(s->k_max) * rs);
+        L.gstat = take(B * 4);
+    }
     L.total = off == 0 ? ALIGN : off;
     return L;
 }
@@ -107,7 +123,7 @@ struct scp_batch_s {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    const void *graph_key[15] = {};
+    const void *graph_key[22] = {};
 };
 
 static void drop_graph(scp_batch h)
@@ -153,6 +169,11 @@ scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_
     *out = nullptr;
     std::string why;
     if (!settings_ok(settings, why)) { g_create_error = why; return SCP_ERR_ARG; }
+    if (settings->grad_pipg_steps > 0 &&
+        scp::grad_smem_bytes(settings->dtype == SCP_F64 ? 1 : 0, settings->k_max) == 0) {
+        g_create_error = "gradient state of this k_max and dtype does not fit one workgroup's LDS";
+        return SCP_ERR_UNSUPPORTED;
+    }
     const Layout L = layout_of(settings);
     if (!workspace || workspace_bytes < L.total) {
         g_create_error = "workspace missing or smaller than scp_batch_workspace_bytes()";
@@ -202,38 +223,24 @@ scp_status scp_batch_set_stream(scp_batch h, void *hip_stream)
 
 const char *scp_batch_last_error(scp_batch h) { return h ? h->err.c_str() : "null handle"; }
 
-scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *sol)
-{
-    if (!h) return SCP_ERR_ARG;
-    h->err.clear();
-    if (!prob || !sol) return fail(h, SCP_ERR_ARG, "problem or solution is NULL");
-    if (prob->batch < 0 || prob->batch > h->st.max_batch)
-        return fail(h, SCP_ERR_SHAPE, "batch must be in [0, max_batch]");
-    if (prob->batch == 0) return SCP_OK;
-    const void *in_ptrs[] = {prob->x0, prob->xf, prob->params, prob->K};
-    for (const void *p : in_ptrs)
-        if (!p) return fail(h, SCP_ERR_ARG, "a problem array is NULL");
-    const void *out_ptrs[] = {sol->x, sol->u, sol->t_f, sol->m_f, sol->status,
-                              sol->scp_iters, sol->pipg_iters, sol->defect_inf,
-                              sol->ctcs_viol, sol->objective};
-    for (const void *p : out_ptrs)
-        if (!p) return fail(h, SCP_ERR_ARG, "a solution array is NULL");
-    for (const void *p : in_ptrs)
-        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
-    for (const void *p : out_ptrs)
-        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
-    if (cur != h->device) {
-        e = hipSetDevice(h->device);
-        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
-    }
+static bool aligned16(const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
 
-    scp::Config cfg;
+static bool lastiter_ok(scp_batch h, const scp_lastiter *rec)
+{
+    const void *ptrs[] = {rec->xbar, rec->ubar, rec->mup, rec->mum, rec->phi, rec->th, rec->sigma};
+    for (const void *p : ptrs)
+        if (!p || !aligned16(p)) {
+            h->err = "a last-iteration array is NULL or not 16-byte aligned";
+            return false;
+        }
+    return true;
+}
+
+static void fill_config(scp_batch h, int batch, scp::Config &cfg)
+{
     const scp_settings &s = h->st;
     cfg.dtype = s.dtype == SCP_F64 ? 1 : 0;
-    cfg.B = prob->batch;
+    cfg.B = batch;
     cfg.kmax = s.k_max;
     cfg.scp_iters_max = s.scp_iters_max;
     cfg.pipg_iters_max = s.pipg_iters_max;
@@ -244,15 +251,6 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
     cfg.node_projections = s.node_projections;
     cfg.persistent_blocks = 0;
     cfg.ordered = s.mode == 2 ? 1 : 0;
-    if (s.mode == 3) {
-        if (h->persistent_grid == 0) {
-            hipDeviceProp_t prop;
-            e = hipGetDeviceProperties(&prop, h->device);
-            if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
-            h->persistent_grid = prop.multiProcessorCount * scp::qp_blocks_per_cu(cfg.dtype, s.k_max);
-        }
-        cfg.persistent_blocks = h->persistent_grid;
-    }
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -267,10 +265,10 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
     cfg.rho = s.rho;
     memcpy(cfg.px, s.px, sizeof(cfg.px));
     memcpy(cfg.pu, s.pu, sizeof(cfg.pu));
+}
 
-    scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
-    scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
-                    sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
+static scp::Workspace workspace_of(scp_batch h)
+{
     scp::Workspace W;
     W.blocks = h->ws + h->L.blocks;
     W.what = h->ws + h->L.what;
@@ -284,12 +282,65 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
     W.queue = reinterpret_cast<int32_t *>(h->ws + h->L.queue);
     W.bucket = reinterpret_cast<int32_t *>(h->ws + h->L.bucket);
     W.order = reinterpret_cast<int32_t *>(h->ws + h->L.order);
+    return W;
+}
+
+static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution *sol,
+                             const scp_lastiter *rec)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (!prob || !sol) return fail(h, SCP_ERR_ARG, "problem or solution is NULL");
+    if (rec && !lastiter_ok(h, rec)) return SCP_ERR_ARG;
+    if (prob->batch < 0 || prob->batch > h->st.max_batch)
+        return fail(h, SCP_ERR_SHAPE, "batch must be in [0, max_batch]");
+    if (prob->batch == 0) return SCP_OK;
+    const void *in_ptrs[] = {prob->x0, prob->xf, prob->params, prob->K};
+    for (const void *p : in_ptrs)
+        if (!p) return fail(h, SCP_ERR_ARG, "a problem array is NULL");
+    const void *out_ptrs[] = {sol->x, sol->u, sol->t_f, sol->m_f, sol->status,
+                              sol->scp_iters, sol->pipg_iters, sol->defect_inf,
+                              sol->ctcs_viol, sol->objective};
+    for (const void *p : out_ptrs)
+        if (!p) return fail(h, SCP_ERR_ARG, "a solution array is NULL");
+    for (const void *p : in_ptrs)
+        if (!aligned16(p)) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    for (const void *p : out_ptrs)
+        if (!aligned16(p)) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != h->device) {
+        e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+
+    scp::Config cfg;
+    fill_config(h, prob->batch, cfg);
+    if (h->st.mode == 3) {
+        if (h->persistent_grid == 0) {
+            hipDeviceProp_t prop;
+            e = hipGetDeviceProperties(&prop, h->device);
+            if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+            h->persistent_grid = prop.multiProcessorCount * scp::qp_blocks_per_cu(cfg.dtype, h->st.k_max);
+        }
+        cfg.persistent_blocks = h->persistent_grid;
+    }
+
+    scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+    scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
+                    sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
+    const scp::Workspace W = workspace_of(h);
+    scp::Record Rc{};
+    if (rec) Rc = scp::Record{rec->xbar, rec->ubar, rec->mup, rec->mum, rec->phi, rec->th, rec->sigma};
+    const scp::Record *RP = rec ? &Rc : nullptr;
     if (h->st.mode >= 1 && !h->profiling) {
         // replay a captured graph of the whole launch sequence when the arguments match
-        const void *key[15] = {reinterpret_cast<const void *>((intptr_t)prob->batch), prob->x0,
+        const void *key[22] = {reinterpret_cast<const void *>((intptr_t)prob->batch), prob->x0,
                                prob->xf, prob->params, prob->K, sol->x, sol->u, sol->t_f,
                                sol->m_f, sol->status, sol->scp_iters, sol->pipg_iters,
-                               sol->defect_inf, sol->ctcs_viol, sol->objective};
+                               sol->defect_inf, sol->ctcs_viol, sol->objective,
+                               Rc.xbar, Rc.ubar, Rc.mup, Rc.mum, Rc.phi, Rc.th, Rc.sigma};
         if (!h->graph_exec || memcmp(key, h->graph_key, sizeof(key)) != 0) {
             drop_graph(h);
             if (!h->cap_stream) {
@@ -302,7 +353,7 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
             }
             e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t el = scp::launch_solve(cfg, P, S, W, h->cap_stream, nullptr);
+                hipError_t el = scp::launch_solve(cfg, P, S, W, RP, h->cap_stream, nullptr);
                 hipGraph_t g = nullptr;
                 e = hipStreamEndCapture(h->cap_stream, &g);
                 if (el != hipSuccess) e = el;
@@ -322,8 +373,66 @@ scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *s
         }
         e = hipGraphLaunch(h->graph_exec, h->stream);
     } else {
-        e = scp::launch_solve(cfg, P, S, W, h->stream, h->profiling ? &h->timer : nullptr);
+        e = scp::launch_solve(cfg, P, S, W, RP, h->stream, h->profiling ? &h->timer : nullptr);
     }
+    if (cur != h->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SCP_OK;
+}
+
+scp_status scp_batch_solve(scp_batch h, const scp_problem *prob, scp_solution *sol)
+{
+    return solve_impl(h, prob, sol, nullptr);
+}
+
+scp_status scp_batch_solve_record(scp_batch h, const scp_problem *prob, scp_solution *sol,
+                                  const scp_lastiter *last)
+{
+    if (!h) return SCP_ERR_ARG;
+    if (!last) {
+        h->err = "last is NULL";
+        return SCP_ERR_ARG;
+    }
+    return solve_impl(h, prob, sol, last);
+}
+
+scp_status scp_batch_grad(scp_batch h, const scp_problem *prob, const scp_lastiter *last,
+                          const void *cotangent, void *grad, void *value)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (h->st.grad_pipg_steps <= 0)
+        return fail(h, SCP_ERR_STATE, "the handle was created with grad_pipg_steps = 0");
+    if (!prob || !last || !cotangent || !grad)
+        return fail(h, SCP_ERR_ARG, "problem, last, cotangent or grad is NULL");
+    if (!lastiter_ok(h, last)) return SCP_ERR_ARG;
+    if (prob->batch < 0 || prob->batch > h->st.max_batch)
+        return fail(h, SCP_ERR_SHAPE, "batch must be in [0, max_batch]");
+    if (prob->batch == 0) return SCP_OK;
+    const void *ptrs[] = {prob->x0, prob->xf, prob->params, prob->K, cotangent, grad};
+    for (const void *p : ptrs)
+        if (!p || !aligned16(p)) return fail(h, SCP_ERR_ARG, "arrays must be non-NULL and 16-byte aligned");
+    if (value && !aligned16(value)) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != h->device) {
+        e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    scp::Config cfg;
+    fill_config(h, prob->batch, cfg);
+    const scp::Workspace W = workspace_of(h);
+    scp::GradWorkspace G;
+    G.dblk = h->ws + h->L.dblk;
+    G.dwhat = h->ws + h->L.dwhat;
+    G.tape = h->ws + h->L.tape;
+    G.gstat = reinterpret_cast<int32_t *>(h->ws + h->L.gstat);
+    const scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+    const scp::Record Rc{last->xbar, last->ubar, last->mup, last->mum, last->phi, last->th,
+                         last->sigma};
+    e = scp::launch_grad(cfg, h->st.grad_pipg_steps, h->st.grad_ckpt_every, P, Rc, cotangent,
+                         grad, value, W, G, h->stream);
     if (cur != h->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SCP_OK;

@@ -1,0 +1,43 @@
+// scp_common.hpp -- layout constants and workgroup helpers shared by the solve kernels and
+// the gradient kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lander_model.hpp"
+
+namespace scp {
+
+constexpr int COLS = 23;         // columns of [A^- | B^- | B^+]
+constexpr int CST = 16;          // stride of one column (15 rows + pad)
+constexpr int BLK = COLS * CST;  // entries per interval
+constexpr int VST = 20;          // node stride of (x, u) vectors in LDS (15 + 4 + pad)
+constexpr int DST = 16;          // interval stride of dual vectors
+
+// Final boundary condition: r, v, (q2, q3) and w are imposed; m, (q0, q1) and y are free.
+__device__ __forceinline__ bool final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8; }
+
+// ------------------------------------------------------------------------------------------
+// Workgroup reductions with a fixed combination order (deterministic).
+// ------------------------------------------------------------------------------------------
+template <int N, bool MAX>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        for (int q = 0; q < N; ++q) {
+            const double w = __shfl_xor(v[q], o, 64);
+            v[q] = MAX ? fmax(v[q], w) : v[q] + w;
+        }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < N; ++q) red[wave * N + q] = v[q];
+    __syncthreads();
+    for (int q = 0; q < N; ++q) {
+        double r = red[q];
+        for (int w = 1; w < nw; ++w) r = MAX ? fmax(r, red[w * N + q]) : r + red[w * N + q];
+        v[q] = r;
+    }
+}
+
+}  // namespace scp

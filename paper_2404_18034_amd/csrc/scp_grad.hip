@@ -1,0 +1,836 @@
+// scp_grad.hip -- derivative of the last SCP iteration with respect to the problem data.
+//
+// The differentiated map takes theta = (x0[15], m_wet, alpha_mdot, T_max) to (m_f, t_f) through
+// one SCP iteration with its starting point frozen: the discretization at the recorded
+// reference (section "Discretization", with the variational equations of "Gradient of
+// Discretized Dynamics"), the prescaled QP ("Convex Subproblem with Prescaling and
+// Preconditioning"), a fixed number of PIPG_custom steps (Algorithm "PIPG_custom") from the
+// recorded warm start with the recorded step sizes, and the reference update.  The paper
+// does not differentiate its solver; this is an extension.
+//
+//   tangent_kernel  one lane per (instance, interval, column of [A | B- | B+]): the RK4 of the
+//                   discretization run on two-direction dual numbers, giving the derivative of
+//                   the scaled blocks and of the scaled defect with respect to alpha_mdot and
+//                   T_max (the only entries of theta the discretization sees; x0 and m_wet
+//                   enter through the initial boundary value alone).
+//   grad_kernel     one workgroup per instance, one 16-lane row per node: the PIPG steps
+//                   forward with a checkpoint every `ckpt` steps, then the reverse (adjoint)
+//                   sweep segment by segment, each segment recomputed from its checkpoint.
+//                   The adjoint accumulates the derivative of the output with respect to
+//                   the scaled blocks, the defect and the initial boundary value; the
+//                   first two are contracted with the tangents at the end.
+// Every projection is differentiated on the branch the forward evaluation takes; a kink is
+// given the derivative of that branch (the derivative of max(0, .) at 0 is that of the
+// clamped side).
+#include <math.h>
+
+#include "dual2.hpp"
+#include "lander_model.hpp"
+#include "scp_common.hpp"
+#include "scp_kernels.hpp"
+
+namespace scp {
+
+// Offsets of one saved PIPG iterate (x~, u~, nu+, nu-, varphi, vartheta) in LDS and tape.
+struct StateLayout {
+    int X, U, MP, MM, PH, TH, len;
+};
+
+__host__ __device__ inline StateLayout state_layout(int kmax)
+{
+    StateLayout L;
+    const int M = kmax - 1;
+    L.X = 0;
+    L.U = kmax * 16;
+    L.MP = L.U + kmax * NU;
+    L.MM = L.MP + M * DST;
+    L.PH = L.MM + M * DST;
+    L.TH = L.PH + M * DST;
+    L.len = L.TH + kmax;
+    return L;
+}
+
+int grad_state_len(int kmax) { return state_layout(kmax).len; }
+
+template <typename R>
+struct GradArgs {
+    int B, kmax, nsteps, ckpt, n_ckpt, rk4_substeps, node_projections;
+    double w_cost, w_prox, w_ep, omega, rho;
+    double px[NX], pu[NU];
+    const R *x0, *xf, *params;
+    const int32_t *K;
+    const R *xbar, *ubar, *mup, *mum, *phi, *th;
+    const double *sigma;
+    const R *cot;
+    R *grad, *fval;
+    const R *blocks, *what;
+    R *dblk, *dwhat;
+    R *tape;
+    int32_t *gstat;
+};
+
+__global__ void grad_status_kernel(const int32_t *K, int B, int kmax, int32_t *gstat)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int k = K[b];
+    gstat[b] = (k >= 2 && k <= kmax) ? -1 : 3;
+}
+
+// ------------------------------------------------------------------------------------------
+// Tangents of the discretization with respect to (alpha_mdot, T_max), in double.
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
+{
+    using D = Dual2<double>;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per_b = (long)(a.kmax - 1) * COLS;
+    const int b = (int)(gid / per_b);
+    if (b >= a.B) return;
+    const int rem = (int)(gid % per_b), k = rem / COLS, c = rem % COLS;
+    if (a.gstat[b] >= 0) return;
+    const int K = a.K[b];
+    if (k >= K - 1) return;
+
+    double pd[NP];
+    for (int q = 0; q < NP; ++q) pd[q] = double(a.params[(long)b * NP + q]);
+    const Vehicle<double> W = load_vehicle<double>(pd);
+    Vehicle<D> V;
+    V.m_dry = D(W.m_dry);
+    V.alpha = D(W.alpha, 1.0, 0.0);
+    for (int q = 0; q < 3; ++q) {
+        V.g[q] = D(W.g[q]);
+        V.Jinv[q] = D(W.Jinv[q]);
+        V.J[q] = D(W.J[q]);
+        V.rT[q] = D(W.rT[q]);
+    }
+    V.T_min = D(W.T_min);
+    V.T_max = D(W.T_max, 0.0, 1.0);
+    V.sec_delta = D(W.sec_delta);
+    V.tan_gamma = D(W.tan_gamma);
+    V.tilt_c = D(W.tilt_c);
+    V.w_max2 = D(W.w_max2);
+
+    const R *xk = a.xbar + ((long)b * a.kmax + k) * NX;
+    const R *uk = a.ubar + ((long)b * a.kmax + k) * NU;
+    D x[NX], col[NX];
+    for (int i = 0; i < NX; ++i) {
+        x[i] = D(double(xk[i]));
+        col[i] = D((c < NX && i == c) ? 1.0 : 0.0);
+    }
+    double ua[NU], ub[NU];
+    for (int i = 0; i < NU; ++i) {
+        ua[i] = double(uk[i]);
+        ub[i] = double(uk[NU + i]);
+    }
+    const int uj = c < NX ? -1 : (c - NX) % NU;
+    const bool plus = c >= NX + NU;
+    const double dtau = 1.0 / double(K - 1);
+    const int nsub = a.rk4_substeps;
+    const double h = dtau / nsub, hh = 0.5 * h, h6 = h / 6.0;
+
+    D xs[NX], cs[NX], accx[NX], accc[NX], fx[NX], fc[NX], u[NU], du[NU];
+    double fy;
+    for (int n = 0; n < nsub; ++n) {
+        const double sig = n * h;
+        for (int st = 0; st < 4; ++st) {
+            const double sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
+            const double lp = sg / dtau, lm = 1.0 - lp;
+            for (int i = 0; i < NU; ++i) {
+                u[i] = D(lm * ua[i] + lp * ub[i]);
+                du[i] = D(i == uj ? (plus ? lp : lm) : 0.0);
+            }
+            f_jvp<D, true>(V, st == 0 ? x : xs, u, st == 0 ? col : cs, du, fx, fy, fc);
+            const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+            for (int i = 0; i < NX; ++i) {
+                if (st == 0) {
+                    accx[i] = fx[i];
+                    accc[i] = fc[i];
+                } else {
+                    accx[i] += D(wgt) * fx[i];
+                    accc[i] += D(wgt) * fc[i];
+                }
+            }
+            if (st < 3) {
+                const D hs = D(st == 2 ? h : hh);
+                for (int i = 0; i < NX; ++i) {
+                    xs[i] = x[i] + hs * fx[i];
+                    cs[i] = col[i] + hs * fc[i];
+                }
+            }
+        }
+        for (int i = 0; i < NX; ++i) {
+            x[i] += D(h6) * accx[i];
+            col[i] += D(h6) * accc[i];
+        }
+    }
+
+    const long ib = (long)b * (a.kmax - 1) + k;
+    const double pc = c < NX ? a.px[c] : a.pu[(c - NX) % NU];
+    R *d0 = a.dblk + (ib * 2) * BLK + c * CST;
+    R *d1 = d0 + BLK;
+    for (int i = 0; i < NX; ++i) {
+        d0[i] = R(col[i].d0 * pc / a.px[i]);
+        d1[i] = R(col[i].d1 * pc / a.px[i]);
+    }
+    d0[NX] = d1[NX] = R(0);
+    if (c == 0) {
+        R *w0 = a.dwhat + (ib * 2) * DST;
+        R *w1 = w0 + DST;
+        for (int i = 0; i < NX; ++i) {
+            w0[i] = R(x[i].d0 / a.px[i]);
+            w1[i] = R(x[i].d1 / a.px[i]);
+        }
+        w0[NX] = w1[NX] = R(0);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Projections and their vector-Jacobian products (recomputed from the projection's input).
+// ------------------------------------------------------------------------------------------
+// Second-order cone {(t, z) : ||z|| <= a t}, z in R^2.
+template <typename R>
+__device__ __forceinline__ void soc2_fwd(R &t, R &z0, R &z1, R a)
+{
+    const R nz = sqrt(z0 * z0 + z1 * z1);
+    if (nz <= a * t) return;
+    if (a * nz <= -t) {
+        t = z0 = z1 = R(0);
+        return;
+    }
+    const R tp = (t + a * nz) / (R(1) + a * a);
+    const R s = a * tp / nz;
+    z0 *= s;
+    z1 *= s;
+    t = tp;
+}
+
+// (tb, zb) holds the adjoint of the projection's output and receives that of its input
+// (t, z).
+template <typename R>
+__device__ __forceinline__ void soc2_vjp(R t, R z0, R z1, R a, R &tb, R &zb0, R &zb1)
+{
+    const R nz = sqrt(z0 * z0 + z1 * z1);
+    if (nz <= a * t) return;
+    if (a * nz <= -t) {
+        tb = zb0 = zb1 = R(0);
+        return;
+    }
+    const R den = R(1) + a * a;
+    const R tp = (t + a * nz) / den;
+    const R n0 = z0 / nz, n1 = z1 / nz;
+    const R tpb = tb + a * (n0 * zb0 + n1 * zb1);
+    const R nb0 = a * tp * zb0, nb1 = a * tp * zb1;
+    const R nn = n0 * nb0 + n1 * nb1;
+    const R c = a * tpb / den;
+    tb = tpb / den;
+    zb0 = c * n0 + (nb0 - n0 * nn) / nz;
+    zb1 = c * n1 + (nb1 - n1 * nn) / nz;
+}
+
+// Ball ||z|| <= rad in R^N.
+template <typename R, int N>
+__device__ __forceinline__ void ball_fwd(R *z, R rad)
+{
+    R s = R(0);
+    for (int q = 0; q < N; ++q) s += z[q] * z[q];
+    const R nz = sqrt(s);
+    if (nz > rad) {
+        const R f = rad / nz;
+        for (int q = 0; q < N; ++q) z[q] *= f;
+    }
+}
+
+// zb: adjoint of the output in, of the input z out; returns the adjoint of the radius.
+template <typename R, int N>
+__device__ __forceinline__ R ball_vjp(const R *z, R rad, R *zb)
+{
+    R s = R(0);
+    for (int q = 0; q < N; ++q) s += z[q] * z[q];
+    const R nz = sqrt(s);
+    if (!(nz > rad)) return R(0);
+    R nzb = R(0);
+    for (int q = 0; q < N; ++q) nzb += z[q] * zb[q];
+    nzb /= nz;
+    for (int q = 0; q < N; ++q) zb[q] = rad / nz * (zb[q] - z[q] / nz * nzb);
+    return nzb;
+}
+
+// Sets of the node-wise projection in original units, with what the kernel needs of them.
+template <typename R>
+struct NodeSets {
+    int mask;
+    R mdry, glide_a, tilt_rad, w_max, gimbal_a, T_max;
+};
+
+// State sets of node k (bits 1, 2, 4, 8): pre-projection x^ in XP (scaled), reference xb
+// (original units).  Writes the projected non-fixed group members into xh.
+template <typename R>
+__device__ __forceinline__ void xproj_fwd(const NodeSets<R> &S, const R *xp, const R *xb,
+                                          const R *px, const bool *fixed, R *xh)
+{
+    R xo[NX];
+    for (int q = 0; q < NX; ++q) xo[q] = xb[q] + px[q] * xp[q];
+    if (S.mask & 1)
+        if (!fixed[0] && xo[0] < S.mdry) xh[0] = (S.mdry - xb[0]) / px[0];
+    if (S.mask & 2) {
+        R t = xo[1], z0 = xo[2], z1 = xo[3];
+        soc2_fwd<R>(t, z0, z1, S.glide_a);
+        if (!fixed[1]) {
+            xh[1] = (t - xb[1]) / px[1];
+            xh[2] = (z0 - xb[2]) / px[2];
+            xh[3] = (z1 - xb[3]) / px[3];
+        }
+    }
+    if (S.mask & 4) {
+        R z[2] = {xo[9], xo[10]};
+        ball_fwd<R, 2>(z, S.tilt_rad);
+        if (!fixed[9]) {
+            xh[9] = (z[0] - xb[9]) / px[9];
+            xh[10] = (z[1] - xb[10]) / px[10];
+        }
+    }
+    if (S.mask & 8) {
+        R z[3] = {xo[11], xo[12], xo[13]};
+        ball_fwd<R, 3>(z, S.w_max);
+        if (!fixed[11])
+            for (int q = 0; q < 3; ++q) xh[11 + q] = (z[q] - xb[11 + q]) / px[11 + q];
+    }
+}
+
+// g: adjoint of the projected (scaled) state in, of the pre-projection state out.  Fixed
+// members already carry a zero adjoint.
+template <typename R>
+__device__ __forceinline__ void xproj_vjp(const NodeSets<R> &S, const R *xp, const R *xb,
+                                          const R *px, R *g)
+{
+    R xo[NX];
+    for (int q = 0; q < NX; ++q) xo[q] = xb[q] + px[q] * xp[q];
+    if ((S.mask & 1) && xo[0] < S.mdry) g[0] = R(0);
+    if (S.mask & 2) {
+        R tb = g[1] / px[1], zb0 = g[2] / px[2], zb1 = g[3] / px[3];
+        soc2_vjp<R>(xo[1], xo[2], xo[3], S.glide_a, tb, zb0, zb1);
+        g[1] = tb * px[1];
+        g[2] = zb0 * px[2];
+        g[3] = zb1 * px[3];
+    }
+    if (S.mask & 4) {
+        R zb[2] = {g[9] / px[9], g[10] / px[10]};
+        const R z[2] = {xo[9], xo[10]};
+        (void)ball_vjp<R, 2>(z, S.tilt_rad, zb);
+        g[9] = zb[0] * px[9];
+        g[10] = zb[1] * px[10];
+    }
+    if (S.mask & 8) {
+        R zb[3] = {g[11] / px[11], g[12] / px[12], g[13] / px[13]};
+        const R z[3] = {xo[11], xo[12], xo[13]};
+        (void)ball_vjp<R, 3>(z, S.w_max, zb);
+        for (int q = 0; q < 3; ++q) g[11 + q] = zb[q] * px[11 + q];
+    }
+}
+
+// Control of node k: the s box, then (bit 16) the gimbal cone and the T_max ball.
+template <typename R>
+__device__ __forceinline__ void uproj_fwd(const NodeSets<R> &S, const R *up, const R *ub,
+                                          const R *pu, R slo, R shi, R *uh)
+{
+    uh[3] = fmin(fmax(up[3], slo), shi);
+    if (S.mask & 16) {
+        R T[3];
+        for (int q = 0; q < 3; ++q) T[q] = ub[q] + pu[q] * up[q];
+        soc2_fwd<R>(T[0], T[1], T[2], S.gimbal_a);
+        ball_fwd<R, 3>(T, S.T_max);
+        for (int q = 0; q < 3; ++q) uh[q] = (T[q] - ub[q]) / pu[q];
+    } else {
+        for (int q = 0; q < 3; ++q) uh[q] = up[q];
+    }
+}
+
+// Returns the adjoint of T_max.
+template <typename R>
+__device__ __forceinline__ R uproj_vjp(const NodeSets<R> &S, const R *up, const R *ub,
+                                       const R *pu, R slo, R shi, R *g)
+{
+    if (!(up[3] >= slo && up[3] <= shi)) g[3] = R(0);
+    if (!(S.mask & 16)) return R(0);
+    R T[3], Tc[3], Tb[3];
+    for (int q = 0; q < 3; ++q) {
+        T[q] = Tc[q] = ub[q] + pu[q] * up[q];
+        Tb[q] = g[q] / pu[q];
+    }
+    soc2_fwd<R>(Tc[0], Tc[1], Tc[2], S.gimbal_a);
+    const R radb = ball_vjp<R, 3>(Tc, S.T_max, Tb);
+    soc2_vjp<R>(T[0], T[1], T[2], S.gimbal_a, Tb[0], Tb[1], Tb[2]);
+    for (int q = 0; q < 3; ++q) g[q] = Tb[q] * pu[q];
+    return radb;
+}
+
+// ------------------------------------------------------------------------------------------
+// Forward steps with checkpoints, then the reverse sweep.
+// ------------------------------------------------------------------------------------------
+size_t grad_smem_bytes_r(int kmax, size_t rs)
+{
+    const StateLayout L = state_layout(kmax);
+    return 128 * sizeof(double) +
+           rs * ((size_t)L.len + 4 * 16 * kmax + 4 * NU * kmax + 128 * (kmax - 1) +
+                 DST * (kmax - 1) + kmax);
+}
+
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    const int kmax = a.kmax, t = threadIdx.x;
+    const int k = t >> 4, i = t & 15;
+    R *gout = a.grad + (long)b * 18;
+    if (a.gstat[b] >= 0) {
+        if (t < 18) gout[t] = R(0);
+        if (a.fval && t < 2) a.fval[(long)b * 2 + t] = R(0);
+        return;
+    }
+    const int K = a.K[b], M = K - 1;
+    const StateLayout L = state_layout(kmax);
+
+    double *red = reinterpret_cast<double *>(smem_raw);  // [16 waves * 8]
+    R *S = reinterpret_cast<R *>(red + 128);             // current extrapolated iterate
+    R *XP = S + L.len;                                    // [kmax][16] x^ before projection
+    R *XH = XP + kmax * 16;                               // [kmax][16] fresh x^
+    R *XB = XH + kmax * 16;                               // [kmax][16] reference (original)
+    R *XHB = XB + kmax * 16;                              // [kmax][16] adjoint of x^
+    R *UP = XHB + kmax * 16;                              // [kmax][4]  u^ before projection
+    R *UH = UP + kmax * NU;                               // [kmax][4]  fresh u^
+    R *UB = UH + kmax * NU;                               // [kmax][4]  reference (original)
+    R *UHB = UB + kmax * NU;                              // [kmax][4]  adjoint of u^
+    R *BC = UHB + kmax * NU;                              // [kmax-1][8][16] B^-, B^+ columns
+    R *RB = BC + (kmax - 1) * 128;                        // [kmax-1][16] adjoint of r
+    R *PB = RB + (kmax - 1) * DST;                        // [kmax] adjoint of the theta step
+
+    const bool node = k < K;
+    const bool isx = node && i < NX;
+    const bool isu = node && i < NU;
+    const bool dual = k < M && i < NX;
+    const R *p = a.params + (long)b * NP;
+    const long ib = (long)b * (kmax - 1) + (dual ? k : 0);
+
+    // -------------------- load the recorded starting point and the QP --------------------
+    if (k < kmax) {
+        XB[k * 16 + i] = isx ? a.xbar[((long)b * kmax + k) * NX + i] : R(0);
+        if (i < NU) UB[k * NU + i] = isu ? a.ubar[((long)b * kmax + k) * NU + i] : R(0);
+        S[L.X + k * 16 + i] = R(0);
+        if (i < NU) S[L.U + k * NU + i] = R(0);
+        if (k < kmax - 1) {
+            const long ro = ((long)b * (kmax - 1) + k) * NX + i;
+            S[L.MP + k * DST + i] = dual ? a.mup[ro] : R(0);
+            S[L.MM + k * DST + i] = dual ? a.mum[ro] : R(0);
+            S[L.PH + k * DST + i] = dual ? a.phi[ro] : R(0);
+            for (int c = 0; c < 8; ++c)
+                BC[(k * 8 + c) * 16 + i] =
+                    dual ? a.blocks[ib * BLK + (NX + c) * CST + i] : R(0);
+        }
+        if (i == IY) S[L.TH + k] = k < M ? a.th[(long)b * (kmax - 1) + k] : R(0);
+    }
+    R colA[NX], rowA[NX], rowBm[NU], rowBp[NU];
+    for (int q = 0; q < NX; ++q) {
+        colA[q] = dual ? a.blocks[ib * BLK + i * CST + q] : R(0);
+        rowA[q] = dual ? a.blocks[ib * BLK + q * CST + i] : R(0);
+    }
+    for (int q = 0; q < NU; ++q) {
+        rowBm[q] = dual ? a.blocks[ib * BLK + (NX + q) * CST + i] : R(0);
+        rowBp[q] = dual ? a.blocks[ib * BLK + (NX + NU + q) * CST + i] : R(0);
+    }
+    const R wk = dual ? a.what[ib * DST + i] : R(0);
+    R epsk = R(0);
+    if (dual && i == IY) {
+        const double y0 = double(a.xbar[((long)b * kmax + k) * NX + IY]);
+        const double y1 = double(a.xbar[((long)b * kmax + k + 1) * NX + IY]);
+        epsk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
+    }
+    bool fixed = false;
+    R fixv = R(0);
+    if (isx) {
+        const double xb = double(a.xbar[((long)b * kmax + k) * NX + i]);
+        if (k == 0) {
+            fixed = true;
+            const double zi = i < IY ? double(a.x0[(long)b * NX + i]) : 0.0;
+            fixv = R((zi - xb) / a.px[i]);
+        } else if (k == K - 1 && final_fixed(i)) {
+            fixed = true;
+            fixv = R((double(a.xf[(long)b * NXF + i - 1]) - xb) / a.px[i]);
+        }
+    }
+    R slo = R(0), shi = R(0);
+    if (node) {
+        const double s0 = double(a.ubar[((long)b * kmax + k) * NU + 3]);
+        slo = R((double(p[18]) - s0) / a.pu[3]);
+        shi = R((double(p[19]) - s0) / a.pu[3]);
+    }
+    NodeSets<R> sets;
+    sets.mask = a.node_projections;
+    sets.mdry = p[1];
+    sets.glide_a = R(1.0 / tan(double(p[15])));
+    sets.tilt_rad = R(sqrt(0.5 * (1.0 - cos(double(p[16])))));
+    sets.w_max = p[17];
+    sets.gimbal_a = R(tan(double(p[14])));
+    sets.T_max = p[13];
+    R pxr[NX], pur[NU];
+    for (int q = 0; q < NX; ++q) pxr[q] = R(a.px[q]);
+    for (int q = 0; q < NU; ++q) pur[q] = R(a.pu[q]);
+    bool fixed_node[NX];
+    for (int q = 0; q < NX; ++q) fixed_node[q] = k == 0 || (k == K - 1 && final_fixed(q));
+
+    const double sig = a.sigma[b];
+    const double alpha_d = 2.0 / (a.w_prox + sqrt(a.w_prox * a.w_prox + 4.0 * a.omega * sig));
+    const R alpha = R(alpha_d), beta = R(a.omega * alpha_d), rho = R(a.rho), omr = R(1) - rho;
+    const R wprox = R(a.w_prox), wep = R(a.w_ep);
+    const R cost = (isx && k == K - 1 && i == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
+    __syncthreads();
+
+    // per-lane values of the step last evaluated
+    R a_mu = R(0), b_mu = R(0), mupn = R(0), mumn = R(0), phn = R(0), thp = R(0), thn = R(0);
+
+    // projected gradient step on the primal variables: XP/UP (pre-projection), XH/UH
+    auto primal = [&]() {
+        if (isx) {
+            R g = wprox * S[L.X + k * 16 + i] + cost;
+            if (k < M)
+                for (int q = 0; q < NX; ++q) g += colA[q] * S[L.PH + k * DST + q];
+            if (k > 0) g -= S[L.PH + (k - 1) * DST + i];
+            if (i == IY) {
+                if (k < M) g -= S[L.TH + k];
+                if (k > 0) g += S[L.TH + k - 1];
+            }
+            const R xp = S[L.X + k * 16 + i] - alpha * g;
+            XP[k * 16 + i] = xp;
+            XH[k * 16 + i] = fixed ? fixv : xp;
+        }
+        if (isu) {
+            R g = wprox * S[L.U + k * NU + i];
+            if (k < M)
+                for (int q = 0; q < NX; ++q) g += BC[(k * 8 + i) * 16 + q] * S[L.PH + k * DST + q];
+            if (k > 0)
+                for (int q = 0; q < NX; ++q)
+                    g += BC[((k - 1) * 8 + NU + i) * 16 + q] * S[L.PH + (k - 1) * DST + q];
+            UP[k * NU + i] = S[L.U + k * NU + i] - alpha * g;
+        }
+        __syncthreads();
+        if (node && i == 0 && (sets.mask & 15))
+            xproj_fwd<R>(sets, XP + k * 16, XB + k * 16, pxr, fixed_node, XH + k * 16);
+        if (node && i == 1) uproj_fwd<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UH + k * NU);
+        __syncthreads();
+    };
+
+    // dual step (needs XH, UH)
+    auto dual_step = [&]() {
+        if (!dual) return;
+        const R vph = S[L.PH + k * DST + i];
+        const R np = S[L.MP + k * DST + i], nm = S[L.MM + k * DST + i];
+        a_mu = np - alpha * (wep + vph);
+        b_mu = nm - alpha * (wep - vph);
+        mupn = a_mu > R(0) ? a_mu : R(0);
+        mumn = b_mu > R(0) ? b_mu : R(0);
+        R r = R(0);
+        for (int q = 0; q < NX; ++q) r += rowA[q] * (R(2) * XH[k * 16 + q] - S[L.X + k * 16 + q]);
+        r -= R(2) * XH[(k + 1) * 16 + i] - S[L.X + (k + 1) * 16 + i];
+        for (int q = 0; q < NU; ++q) {
+            r += rowBm[q] * (R(2) * UH[k * NU + q] - S[L.U + k * NU + q]);
+            r += rowBp[q] * (R(2) * UH[(k + 1) * NU + q] - S[L.U + (k + 1) * NU + q]);
+        }
+        r += (R(2) * mupn - np) - (R(2) * mumn - nm) + wk;
+        phn = vph + beta * r;
+        if (i == IY) {
+            const R vy1 = R(2) * XH[(k + 1) * 16 + IY] - S[L.X + (k + 1) * 16 + IY];
+            const R vy0 = R(2) * XH[k * 16 + IY] - S[L.X + k * 16 + IY];
+            thp = S[L.TH + k] + beta * (vy1 - vy0 - epsk);
+            thn = thp > R(0) ? thp : R(0);
+        }
+    };
+
+    // extrapolation: S <- (1 - rho) S + rho (fresh iterate)
+    auto extrapolate = [&]() {
+        __syncthreads();
+        if (isx) S[L.X + k * 16 + i] = omr * S[L.X + k * 16 + i] + rho * XH[k * 16 + i];
+        if (isu) S[L.U + k * NU + i] = omr * S[L.U + k * NU + i] + rho * UH[k * NU + i];
+        if (dual) {
+            S[L.MP + k * DST + i] = omr * S[L.MP + k * DST + i] + rho * mupn;
+            S[L.MM + k * DST + i] = omr * S[L.MM + k * DST + i] + rho * mumn;
+            S[L.PH + k * DST + i] = omr * S[L.PH + k * DST + i] + rho * phn;
+            if (i == IY) S[L.TH + k] = omr * S[L.TH + k] + rho * thn;
+        }
+        __syncthreads();
+    };
+
+    R *tape = a.tape + (long)b * (a.n_ckpt + a.ckpt) * L.len;
+    auto save = [&](int slot) {
+        __syncthreads();
+        for (int q = t; q < L.len; q += blockDim.x) tape[(long)slot * L.len + q] = S[q];
+    };
+    auto load = [&](int slot) {
+        __syncthreads();
+        for (int q = t; q < L.len; q += blockDim.x) S[q] = tape[(long)slot * L.len + q];
+        __syncthreads();
+    };
+
+    // -------------------- forward: n steps with checkpoints --------------------
+    const int n = a.nsteps;
+    for (int j = 1; j <= n; ++j) {
+        if ((j - 1) % a.ckpt == 0) save((j - 1) / a.ckpt);
+        primal();
+        dual_step();
+        if (j == n && a.fval && t == 0) {
+            const double mf = double(XB[(K - 1) * 16]) + a.px[0] * double(XH[(K - 1) * 16]);
+            double tf = 0.0;
+            const double dtau = 1.0 / M;
+            for (int q = 0; q < M; ++q)
+                tf += dtau * 0.5 *
+                      (double(UB[q * NU + 3]) + a.pu[3] * double(UH[q * NU + 3]) +
+                       double(UB[(q + 1) * NU + 3]) + a.pu[3] * double(UH[(q + 1) * NU + 3]));
+            a.fval[(long)b * 2] = R(mf);
+            a.fval[(long)b * 2 + 1] = R(tf);
+        }
+        extrapolate();
+    }
+
+    // -------------------- reverse sweep --------------------
+    const R cm = a.cot[(long)b * 2], ct = a.cot[(long)b * 2 + 1];
+    const R dtau = R(1.0 / M);
+    // adjoints of the extrapolated iterate owned by this lane
+    R tbx = R(0), tbu = R(0), tbmp = R(0), tbmm = R(0), tbph = R(0), tbth = R(0);
+    // accumulated derivatives: scaled blocks (row i of interval k), defect, boundary value,
+    // and T_max through the thrust ball
+    R accA[NX], accBm[NU], accBp[NU];
+    for (int q = 0; q < NX; ++q) accA[q] = R(0);
+    for (int q = 0; q < NU; ++q) accBm[q] = accBp[q] = R(0);
+    R accW = R(0), accZ = R(0), accT = R(0);
+
+    for (int m = a.n_ckpt - 1; m >= 0; --m) {
+        const int j0 = m * a.ckpt;
+        const int j1 = (j0 + a.ckpt < n) ? j0 + a.ckpt : n;
+        load(m);
+        for (int j = j0 + 1; j <= j1; ++j) {
+            save(a.n_ckpt + (j - j0 - 1));
+            if (j < j1) {
+                primal();
+                dual_step();
+                extrapolate();
+            }
+        }
+        for (int j = j1; j > j0; --j) {
+            load(a.n_ckpt + (j - j0 - 1));
+            primal();
+            dual_step();
+            // adjoints of the fresh iterate: the extrapolation passes rho of the adjoint on,
+            // the last step also receives the output's cotangent
+            R hxb = rho * tbx, hub = rho * tbu, hmpb = rho * tbmp, hmmb = rho * tbmm;
+            R hphb = rho * tbph, hthb = rho * tbth;
+            if (j == n) {
+                if (isx && k == K - 1 && i == 0) hxb += cm * pxr[0];
+                if (isu && i == 3) hub += ct * pur[3] * dtau * ((k == 0 || k == K - 1) ? R(0.5) : R(1));
+            }
+            R nbx = omr * tbx, nbu = omr * tbu, nbmp = omr * tbmp, nbmm = omr * tbmm;
+            R nbph = omr * tbph, nbth = omr * tbth;
+            // dual step: phi = varphi + beta r, theta = max(0, vartheta + beta (...))
+            R rb = R(0);
+            if (dual) {
+                rb = beta * hphb;
+                RB[k * DST + i] = rb;
+                nbph += hphb;
+                if (i == IY) {
+                    const R pb = thp > R(0) ? hthb : R(0);
+                    PB[k] = pb;
+                    nbth += pb;
+                }
+            }
+            __syncthreads();
+            if (isx) {
+                R vb = R(0);
+                if (k < M)
+                    for (int q = 0; q < NX; ++q) vb += colA[q] * RB[k * DST + q];
+                if (k > 0) vb -= RB[(k - 1) * DST + i];
+                if (i == IY) vb += beta * ((k > 0 ? PB[k - 1] : R(0)) - (k < M ? PB[k] : R(0)));
+                R xb_ = hxb + R(2) * vb;
+                nbx -= vb;
+                if (fixed) {
+                    if (k == 0) accZ += xb_;
+                    xb_ = R(0);
+                }
+                XHB[k * 16 + i] = xb_;
+            }
+            if (isu) {
+                R vub = R(0);
+                if (k < M)
+                    for (int q = 0; q < NX; ++q) vub += BC[(k * 8 + i) * 16 + q] * RB[k * DST + q];
+                if (k > 0)
+                    for (int q = 0; q < NX; ++q)
+                        vub += BC[((k - 1) * 8 + NU + i) * 16 + q] * RB[(k - 1) * DST + q];
+                UHB[k * NU + i] = hub + R(2) * vub;
+                nbu -= vub;
+            }
+            if (dual) {
+                const R mpb = hmpb + R(2) * rb, mmb = hmmb - R(2) * rb;
+                nbmp -= rb;
+                nbmm += rb;
+                accW += rb;
+                for (int q = 0; q < NX; ++q)
+                    accA[q] += rb * (R(2) * XH[k * 16 + q] - S[L.X + k * 16 + q]);
+                for (int q = 0; q < NU; ++q) {
+                    accBm[q] += rb * (R(2) * UH[k * NU + q] - S[L.U + k * NU + q]);
+                    accBp[q] += rb * (R(2) * UH[(k + 1) * NU + q] - S[L.U + (k + 1) * NU + q]);
+                }
+                const R ab = a_mu > R(0) ? mpb : R(0), bb = b_mu > R(0) ? mmb : R(0);
+                nbmp += ab;
+                nbph -= alpha * ab;
+                nbmm += bb;
+                nbph += alpha * bb;
+            }
+            __syncthreads();
+            // projections
+            if (node && i == 0 && (sets.mask & 15))
+                xproj_vjp<R>(sets, XP + k * 16, XB + k * 16, pxr, XHB + k * 16);
+            if (node && i == 1)
+                accT += uproj_vjp<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UHB + k * NU);
+            __syncthreads();
+            // gradient step: x^pre = x~ - alpha g(x~, varphi, vartheta), likewise u
+            if (isx) nbx += XHB[k * 16 + i] * (R(1) - alpha * wprox);
+            if (isu) nbu += UHB[k * NU + i] * (R(1) - alpha * wprox);
+            if (dual) {
+                const R ph = S[L.PH + k * DST + i];
+                R s = alpha * XHB[(k + 1) * 16 + i];
+                for (int q = 0; q < NX; ++q) {
+                    const R gq = -alpha * XHB[k * 16 + q];
+                    s += rowA[q] * gq;
+                    accA[q] += ph * gq;
+                }
+                for (int q = 0; q < NU; ++q) {
+                    const R g0 = -alpha * UHB[k * NU + q];
+                    const R g1 = -alpha * UHB[(k + 1) * NU + q];
+                    s += rowBm[q] * g0 + rowBp[q] * g1;
+                    accBm[q] += ph * g0;
+                    accBp[q] += ph * g1;
+                }
+                nbph += s;
+                if (i == IY) nbth += alpha * (XHB[k * 16 + IY] - XHB[(k + 1) * 16 + IY]);
+            }
+            tbx = nbx;
+            tbu = nbu;
+            tbmp = nbmp;
+            tbmm = nbmm;
+            tbph = nbph;
+            tbth = nbth;
+            __syncthreads();
+        }
+    }
+
+    // -------------------- contraction with the discretization tangents --------------------
+    double part[3] = {0.0, 0.0, 0.0};
+    if (dual) {
+        const R *d0 = a.dblk + (ib * 2) * BLK;
+        const R *d1 = d0 + BLK;
+        const R *w0 = a.dwhat + (ib * 2) * DST;
+        const R *w1 = w0 + DST;
+        for (int q = 0; q < NX; ++q) {
+            part[0] += double(accA[q]) * double(d0[q * CST + i]);
+            part[1] += double(accA[q]) * double(d1[q * CST + i]);
+        }
+        for (int q = 0; q < NU; ++q) {
+            part[0] += double(accBm[q]) * double(d0[(NX + q) * CST + i]) +
+                       double(accBp[q]) * double(d0[(NX + NU + q) * CST + i]);
+            part[1] += double(accBm[q]) * double(d1[(NX + q) * CST + i]) +
+                       double(accBp[q]) * double(d1[(NX + NU + q) * CST + i]);
+        }
+        part[0] += double(accW) * double(w0[i]);
+        part[1] += double(accW) * double(w1[i]);
+    }
+    if (node && i == 1) part[2] = double(accT);
+    block_reduce<3, false>(part, red);
+    if (k == 0 && i < NX) {
+        gout[i] = i < IY ? R(double(accZ) / a.px[i]) : R(0);
+        if (i == 0) gout[15] = R(double(accZ) / a.px[0]);  // m_wet is the initial mass
+    }
+    if (t == 0) {
+        gout[16] = R(part[0]);
+        gout[17] = R(part[1] + part[2]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+template <typename R>
+static hipError_t launch_grad_typed(const Config &cfg, int nsteps, int ckpt, const Problem &prob,
+                                    const Record &rec, const void *cot, void *grad, void *fval,
+                                    const Workspace &ws, const GradWorkspace &gw,
+                                    hipStream_t stream)
+{
+    GradArgs<R> a;
+    a.B = cfg.B;
+    a.kmax = cfg.kmax;
+    a.nsteps = nsteps;
+    a.ckpt = ckpt;
+    a.n_ckpt = (nsteps + ckpt - 1) / ckpt;
+    a.rk4_substeps = cfg.rk4_substeps;
+    a.node_projections = cfg.node_projections;
+    a.w_cost = cfg.w_cost;
+    a.w_prox = cfg.w_prox;
+    a.w_ep = cfg.w_ep;
+    a.omega = cfg.omega;
+    a.rho = cfg.rho;
+    for (int q = 0; q < NX; ++q) a.px[q] = cfg.px[q];
+    for (int q = 0; q < NU; ++q) a.pu[q] = cfg.pu[q];
+    a.x0 = static_cast<const R *>(prob.x0);
+    a.xf = static_cast<const R *>(prob.xf);
+    a.params = static_cast<const R *>(prob.params);
+    a.K = prob.K;
+    a.xbar = static_cast<const R *>(rec.xbar);
+    a.ubar = static_cast<const R *>(rec.ubar);
+    a.mup = static_cast<const R *>(rec.mup);
+    a.mum = static_cast<const R *>(rec.mum);
+    a.phi = static_cast<const R *>(rec.phi);
+    a.th = static_cast<const R *>(rec.th);
+    a.sigma = rec.sigma;
+    a.cot = static_cast<const R *>(cot);
+    a.grad = static_cast<R *>(grad);
+    a.fval = static_cast<R *>(fval);
+    a.blocks = static_cast<const R *>(ws.blocks);
+    a.what = static_cast<const R *>(ws.what);
+    a.dblk = static_cast<R *>(gw.dblk);
+    a.dwhat = static_cast<R *>(gw.dwhat);
+    a.tape = static_cast<R *>(gw.tape);
+    a.gstat = gw.gstat;
+    if (cfg.B == 0) return hipSuccess;
+
+    hipError_t e;
+    grad_status_kernel<<<dim3((unsigned)((cfg.B + 255) / 256)), dim3(256), 0, stream>>>(
+        prob.K, cfg.B, cfg.kmax, gw.gstat);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_discretize_at(cfg, rec.xbar, rec.ubar, prob, gw.gstat, ws, stream)) !=
+        hipSuccess)
+        return e;
+    const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
+    tangent_kernel<R><<<dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, stream>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int threads = qp_block_threads(cfg.kmax);
+    const size_t smem = grad_smem_bytes_r(cfg.kmax, sizeof(R));
+    if (threads <= 640)
+        grad_kernel<R, 640><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
+    else
+        grad_kernel<R, 1024><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const Config &cfg, int nsteps, int ckpt, const Problem &prob,
+                       const Record &rec, const void *cot, void *grad, void *fval,
+                       const Workspace &ws, const GradWorkspace &gw, hipStream_t stream)
+{
+    if (cfg.dtype == 1)
+        return launch_grad_typed<double>(cfg, nsteps, ckpt, prob, rec, cot, grad, fval, ws, gw,
+                                         stream);
+    return launch_grad_typed<float>(cfg, nsteps, ckpt, prob, rec, cot, grad, fval, ws, gw, stream);
+}
+
+size_t grad_smem_bytes(int dtype, int kmax)
+{
+    const size_t b = grad_smem_bytes_r(kmax, dtype == 1 ? 8 : 4);
+    return b <= 65536 ? b : 0;
+}
+
+}  // namespace scp

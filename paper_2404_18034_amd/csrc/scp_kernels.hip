@@ -21,18 +21,10 @@
 #include <utility>
 
 #include "lander_model.hpp"
+#include "scp_common.hpp"
 #include "scp_kernels.hpp"
 
 namespace scp {
-
-constexpr int COLS = 23;         // columns of [A^- | B^- | B^+]
-constexpr int CST = 16;          // stride of one column (15 rows + pad)
-constexpr int BLK = COLS * CST;  // entries per interval
-constexpr int VST = 20;          // node stride of (x, u) vectors in LDS (15 + 4 + pad)
-constexpr int DST = 16;          // interval stride of dual vectors
-
-// Final boundary condition: r, v, (q2, q3) and w are imposed; m, (q0, q1) and y are free.
-__device__ __forceinline__ bool final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8; }
 
 template <typename R>
 struct Args {
@@ -55,6 +47,11 @@ struct Args {
     int32_t *bucket;  // [kmax + 1] counting-sort buckets
     int32_t *order;   // [B] instances by node count, descending
     int use_order;    // subproblem workgroup w solves instance order[w]
+    // optional record of each subproblem's starting point (the last one solved remains):
+    // reference [B][kmax][15], [B][kmax][4]; warm-start duals [B][kmax-1][15], [B][kmax-1];
+    // buffered power-iteration estimate [B]
+    R *rec_x, *rec_u, *rec_mup, *rec_mum, *rec_phi, *rec_th;
+    double *rec_sigma;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -220,30 +217,6 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
         for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) / a.px[i]);
         w[NX] = R(0);
         a.dy[ib] = x[IY] - double(xk[IY]);
-    }
-}
-
-// ------------------------------------------------------------------------------------------
-// Workgroup reductions with a fixed combination order (deterministic).
-// ------------------------------------------------------------------------------------------
-template <int N, bool MAX>
-__device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        for (int q = 0; q < N; ++q) {
-            const double w = __shfl_xor(v[q], o, 64);
-            v[q] = MAX ? fmax(v[q], w) : v[q] + w;
-        }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
-    if (lane == 0)
-        for (int q = 0; q < N; ++q) red[wave * N + q] = v[q];
-    __syncthreads();
-    for (int q = 0; q < N; ++q) {
-        double r = red[q];
-        for (int w = 1; w < nw; ++w) r = MAX ? fmax(r, red[w * N + q]) : r + red[w * N + q];
-        v[q] = r;
     }
 }
 
@@ -541,6 +514,18 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         sPhi[k * DST + i] = vphi;
         if (i == IY) sTh[k] = vth;
     }
+    if (a.rec_x) {
+        if (isx) a.rec_x[xoff + i] = xb;
+        if (node && i < NU) a.rec_u[uoff + i] = a.u[uoff + i];
+        if (dual) {
+            const long ro = ((long)b * (kmax - 1) + k) * NX + i;
+            a.rec_mup[ro] = mup;
+            a.rec_mum[ro] = mum;
+            a.rec_phi[ro] = ph;
+            if (i == IY) a.rec_th[(long)b * (kmax - 1) + k] = th;
+        }
+        if (t == 0) a.rec_sigma[b] = sigma;
+    }
     __syncthreads();
 
     const int jmax = a.pipg_iters_max;
@@ -815,7 +800,8 @@ static size_t qp_smem_bytes(int kmax, size_t rsize)
 
 template <typename R>
 static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Solution &sol,
-                               const Workspace &ws, hipStream_t stream, LaunchTimer *timer)
+                               const Workspace &ws, const Record *rec, hipStream_t stream,
+                               LaunchTimer *timer)
 {
     Args<R> a;
     a.B = cfg.B;
@@ -868,6 +854,13 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.queue = ws.queue;
     a.bucket = ws.bucket;
     a.order = ws.order;
+    a.rec_x = rec ? static_cast<R *>(rec->xbar) : nullptr;
+    a.rec_u = rec ? static_cast<R *>(rec->ubar) : nullptr;
+    a.rec_mup = rec ? static_cast<R *>(rec->mup) : nullptr;
+    a.rec_mum = rec ? static_cast<R *>(rec->mum) : nullptr;
+    a.rec_phi = rec ? static_cast<R *>(rec->phi) : nullptr;
+    a.rec_th = rec ? static_cast<R *>(rec->th) : nullptr;
+    a.rec_sigma = rec ? rec->sigma : nullptr;
 
     if (cfg.B == 0) return hipSuccess;
     int nl = 0;
@@ -926,10 +919,46 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
 }
 
 hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &sol,
-                        const Workspace &ws, hipStream_t stream, LaunchTimer *timer)
+                        const Workspace &ws, const Record *rec, hipStream_t stream,
+                        LaunchTimer *timer)
 {
-    if (cfg.dtype == 1) return launch_typed<double>(cfg, prob, sol, ws, stream, timer);
-    return launch_typed<float>(cfg, prob, sol, ws, stream, timer);
+    if (cfg.dtype == 1) return launch_typed<double>(cfg, prob, sol, ws, rec, stream, timer);
+    return launch_typed<float>(cfg, prob, sol, ws, rec, stream, timer);
+}
+
+// Discretization (blocks, scaled defect, CTCS increment) at a given reference, for the
+// instances whose status entry is negative.
+template <typename R>
+static hipError_t discretize_at_typed(const Config &cfg, const void *x, const void *u,
+                                      const Problem &prob, const int32_t *status,
+                                      const Workspace &ws, hipStream_t stream)
+{
+    Args<R> a = {};
+    a.B = cfg.B;
+    a.kmax = cfg.kmax;
+    a.rk4_substeps = cfg.rk4_substeps;
+    for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
+    for (int i = 0; i < NU; ++i) a.pu[i] = cfg.pu[i];
+    a.params = static_cast<const R *>(prob.params);
+    a.K = prob.K;
+    a.x = const_cast<R *>(static_cast<const R *>(x));
+    a.u = const_cast<R *>(static_cast<const R *>(u));
+    a.status = const_cast<int32_t *>(status);
+    a.blocks = static_cast<R *>(ws.blocks);
+    a.what = static_cast<R *>(ws.what);
+    a.dy = ws.dy;
+    const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
+    discretize_kernel<R><<<dim3((unsigned)((nd + 127) / 128)), dim3(128), 0, stream>>>(a, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
+                                const Problem &prob, const int32_t *status, const Workspace &ws,
+                                hipStream_t stream)
+{
+    if (cfg.B == 0) return hipSuccess;
+    if (cfg.dtype == 1) return discretize_at_typed<double>(cfg, x, u, prob, status, ws, stream);
+    return discretize_at_typed<float>(cfg, x, u, prob, status, ws, stream);
 }
 
 }  // namespace scp

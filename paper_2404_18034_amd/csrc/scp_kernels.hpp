@@ -47,6 +47,23 @@ struct Solution {
     double *defect_inf, *ctcs_viol, *objective;
 };
 
+// Starting point of a subproblem, recorded by a solve and consumed by the gradient: the
+// reference (x^, u^ are zero there), the warm-start duals and the buffered spectral estimate.
+// Dense layouts: xbar [B][kmax][15], ubar [B][kmax][4], mup/mum/phi [B][kmax-1][15],
+// th [B][kmax-1] (R-typed), sigma [B] (double).
+struct Record {
+    void *xbar, *ubar, *mup, *mum, *phi, *th;
+    double *sigma;
+};
+
+// Device scratch of the gradient (carved by the host when gradients are enabled).
+struct GradWorkspace {
+    void *dblk;      // R [B][kmax-1][2][23][16]  d(scaled blocks)/d(alpha_mdot, T_max)
+    void *dwhat;     // R [B][kmax-1][2][16]      d(scaled defect)/d(alpha_mdot, T_max)
+    void *tape;      // R [B][n_ckpt + ckpt][grad_state_len(kmax)]  checkpoints and segment
+    int32_t *gstat;  // i32 [B] -1 for a valid instance, 3 otherwise
+};
+
 // Optional per-launch timing: when `events` is non-null, launch i is bracketed by
 // events[2i] and events[2i+1] (recorded on `stream`) and kinds[i] receives its kernel class
 // (0 init, 1 discretize, 2 subproblem); *n_launches receives the number of launches.
@@ -58,8 +75,32 @@ struct LaunchTimer {
 };
 
 // Enqueue one whole solve on `stream`; returns the first HIP error met while launching.
+// With `rec` non-null every subproblem writes its starting point there (the last one
+// solved by each instance remains).
 hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &sol,
-                        const Workspace &ws, hipStream_t stream, LaunchTimer *timer);
+                        const Workspace &ws, const Record *rec, hipStream_t stream,
+                        LaunchTimer *timer);
+
+// Discretization at the reference (x, u) into ws.blocks / ws.what / ws.dy for every
+// instance whose status entry is negative.
+hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
+                                const Problem &prob, const int32_t *status, const Workspace &ws,
+                                hipStream_t stream);
+
+// Gradient of (m_f, t_f) of the truncated last-iteration map (discretization at the
+// recorded reference, QP build, `nsteps` PIPG steps from the recorded warm start) with
+// respect to theta = (x0[15], m_wet, alpha_mdot, T_max), contracted with the cotangent
+// cot [B][2]: grad [B][18] = cot_m dm_f/dtheta + cot_t dt_f/dtheta.  fval [B][2] (optional)
+// receives (m_f, t_f) of the map.  Checkpoints every `ckpt` steps.
+hipError_t launch_grad(const Config &cfg, int nsteps, int ckpt, const Problem &prob,
+                       const Record &rec, const void *cot, void *grad, void *fval,
+                       const Workspace &ws, const GradWorkspace &gw, hipStream_t stream);
+
+// Values per instance of one saved PIPG state in the gradient tape.
+int grad_state_len(int kmax);
+
+// LDS bytes of the gradient kernel (0 if it does not fit a workgroup).
+size_t grad_smem_bytes(int dtype, int kmax);
 
 // Workgroup size of the subproblem kernel for node count kmax.
 int qp_block_threads(int kmax);

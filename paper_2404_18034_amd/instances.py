@@ -109,6 +109,9 @@ def solver_settings(config, **overrides):
     s = dict(HYPER)
     for k in ("scp_iters_max", "pipg_iters_max", "early_exit"):
         s[k] = cfg[k]
+    for k in ("grad_pipg_steps", "grad_ckpt_every"):
+        if k in cfg:
+            s[k] = cfg[k]
     s.update(overrides)
     return s
 

@@ -72,3 +72,38 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.scp_batch_set_stream(None, None) == 1
     assert lib.scp_batch_destroy(None) == 1
     assert lib.scp_batch_last_error(None) == b"null handle"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors and the C declarations agree on every field offset and size
+    structs = {"scp_settings": api.Settings, "scp_problem": api.Problem,
+               "scp_solution": api.Solution, "scp_lastiter": api.LastIter}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "scp_batch.h"',
+             'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append('return 0; }')
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_gradient_settings_validated(lib):
+    cfg = I.solver_settings("C3")
+    s = api.make_settings(cfg, "f32", 20, 64)
+    n_grad = api.workspace_bytes(s)
+    s0 = api.make_settings(dict(cfg, grad_pipg_steps=0), "f32", 20, 64)
+    assert 0 < api.workspace_bytes(s0) < n_grad
+    bad = api.make_settings(dict(cfg, grad_ckpt_every=0), "f32", 20, 64)
+    assert api.workspace_bytes(bad) == 0
+    bad = api.make_settings(dict(cfg, grad_ckpt_every=201), "f32", 20, 64)
+    assert api.workspace_bytes(bad) == 0

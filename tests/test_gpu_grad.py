@@ -1,0 +1,195 @@
+"""GPU gradient of the last SCP iteration (scp_batch_grad) against finite differences of the
+FP64 oracle's truncated map, and the recorded last-iteration state against the oracle's.
+
+The check feeds the oracle's own recorded starting point to the GPU, so both differentiate
+the same map at the same point: FP64 to finite-difference accuracy, FP32 within 1e-3
+relative to the largest entry of each Jacobian row.  Central differences use h = 1e-6."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_18034_amd import api
+from paper_2404_18034_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-6
+
+
+def _oracle_last(cfg, inst, ids):
+    out = []
+    for b in ids:
+        K = int(inst["K"][b])
+        out.append(oracle.lastiter_state(cfg, inst["x0"][b], inst["xf"][b], inst["params"][b], K))
+    return out
+
+
+def _unpack(ws, K):
+    M = K - 1
+    o = K * 15 + K * 4
+    mup = ws[o:o + M * 15].reshape(M, 15); o += M * 15
+    mum = ws[o:o + M * 15].reshape(M, 15); o += M * 15
+    phi = ws[o:o + M * 15].reshape(M, 15); o += M * 15
+    th = ws[o:o + M]
+    return mup, mum, phi, th
+
+
+def _last_to_device(s, lasts, inst, ids):
+    import torch
+    B = len(ids)
+    last = s.alloc_lastiter(B)
+    host = {k: v.cpu().numpy() for k, v in last.items()}
+    for j, (b, L) in enumerate(zip(ids, lasts)):
+        K = int(inst["K"][b])
+        host["xbar"][j, :K] = L["xbar"]
+        host["ubar"][j, :K] = L["ubar"]
+        mup, mum, phi, th = _unpack(L["ws"], K)
+        host["mup"][j, :K - 1] = mup
+        host["mum"][j, :K - 1] = mum
+        host["phi"][j, :K - 1] = phi
+        host["th"][j, :K - 1] = th
+        host["sigma"][j] = L["sigma"]
+    return {k: torch.as_tensor(v).to(last[k].device) for k, v in host.items()}
+
+
+def _oracle_fd(cfg, inst, b, L, n):
+    x0, xf, p, K = inst["x0"][b], inst["xf"][b], inst["params"][b], int(inst["K"][b])
+    theta = oracle.theta_of(x0, p)
+    F = np.zeros((2, 18))
+    for i in range(18):
+        e = np.zeros(18)
+        e[i] = H
+        F[:, i] = (oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n) -
+                   oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)) / (2 * H)
+    val = oracle.truncated_map(cfg, x0, xf, p, K, theta, L, n)
+    return F, val
+
+
+def _gpu_jac(cfg, inst, ids, lasts, dtype):
+    import torch
+    B = len(ids)
+    sub = {k: v[ids] for k, v in inst.items()}
+    s = api.BatchSolver(cfg, dtype=dtype, k_max=int(sub["K"].max()), max_batch=B)
+    prob = s.to_device(sub)
+    last = _last_to_device(s, lasts, inst, ids)
+    J = np.zeros((B, 2, 18))
+    val = None
+    for o in range(2):
+        cot = torch.zeros((B, 2), dtype=s.dtype, device=prob["x0"].device)
+        cot[:, o] = 1
+        g = torch.empty((B, 18), dtype=s.dtype, device=cot.device)
+        v = torch.empty((B, 2), dtype=s.dtype, device=cot.device)
+        s.grad_into(prob, last, cot, g, v)
+        torch.cuda.synchronize()
+        J[:, o] = g.cpu().numpy()
+        val = v.cpu().numpy()
+    s.close()
+    return J, val
+
+
+def _rel_err(J, F):
+    scale = np.abs(F).max(axis=-1, keepdims=True) + 1e-30
+    return np.abs(J - F) / scale
+
+
+def _run(cfg, inst, ids, dtype, tol, vtol):
+    n = cfg["grad_pipg_steps"]
+    lasts = _oracle_last(cfg, inst, ids)
+    J, val = _gpu_jac(cfg, inst, ids, lasts, dtype)
+    worst = 0.0
+    for j, b in enumerate(ids):
+        F, v = _oracle_fd(cfg, inst, b, lasts[j], n)
+        err = _rel_err(J[j], F).max()
+        worst = max(worst, err)
+        assert err <= tol, "instance %d: rel err %.3e\nGPU %s\nFD  %s" % (b, err, J[j], F)
+        np.testing.assert_allclose(val[j], v, rtol=vtol)
+    print("%s grad: worst rel err %.3e over %d instances" % (dtype, worst, len(ids)), flush=True)
+
+
+@pytest.mark.parametrize("proj", [0, 31])
+def test_grad_fp64_matches_oracle_fd(proj):
+    cfg = I.solver_settings("C3", node_projections=proj, scp_iters_max=5, pipg_iters_max=400)
+    inst = I.make_instances("C3", B=8)
+    _run(cfg, inst, list(range(8)), "f64", 1e-5, 1e-11)
+
+
+def test_grad_fp64_active_thrust_bound():
+    # T_max low enough that the thrust bound is active: its derivative is nonzero both through
+    # the CTCS integrand in the discretization and through the T_max ball of the projection
+    cfg = I.solver_settings("C3", scp_iters_max=5, pipg_iters_max=400)
+    inst = I.make_instances("C3", B=4)
+    inst["params"][:, 13] = 2.3
+    _run(cfg, inst, list(range(4)), "f64", 1e-5, 1e-11)
+
+
+def test_grad_fp32_64_instances_matches_oracle_fd():
+    # the differentiation workload's settings (15 SCP x 1000 PIPG forward, 200 differentiated
+    # PIPG steps with checkpoints every 20) on instances 0..63
+    cfg = I.solver_settings("C3")
+    inst = I.make_instances("C3", B=64)
+    _run(cfg, inst, list(range(64)), "f32", 1e-3, 1e-5)
+
+
+def test_record_matches_oracle_last_iteration():
+    import torch
+    cfg = I.solver_settings("C3", scp_iters_max=3, pipg_iters_max=300)
+    inst = I.make_instances("C3", B=6)
+    s = api.BatchSolver(cfg, dtype="f64", k_max=20, max_batch=6)
+    prob = s.to_device(inst)
+    sol, last = s.solve_record_into(prob, s.alloc_solution(6), s.alloc_lastiter(6))
+    torch.cuda.synchronize()
+    lasts = _oracle_last(cfg, inst, range(6))
+    for b, L in enumerate(lasts):
+        np.testing.assert_allclose(last["xbar"][b].cpu().numpy(), L["xbar"], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(last["ubar"][b].cpu().numpy(), L["ubar"], rtol=0, atol=1e-9)
+        mup, mum, phi, th = _unpack(L["ws"], 20)
+        for name, ref in (("mup", mup), ("mum", mum), ("phi", phi), ("th", th)):
+            np.testing.assert_allclose(last[name][b].cpu().numpy(), ref, rtol=0, atol=1e-8)
+        assert float(last["sigma"][b]) == pytest.approx(L["sigma"], rel=1e-10)
+    s.close()
+
+
+def test_autograd_function_matches_grad_entry_point():
+    import torch
+    cfg = I.solver_settings("C3", scp_iters_max=4, pipg_iters_max=300)
+    inst = I.make_instances("C3", B=5)
+    s = api.BatchSolver(cfg, dtype="f64", k_max=20, max_batch=5)
+    prob = s.to_device(inst)
+    x0 = prob["x0"].clone().requires_grad_(True)
+    params = prob["params"].clone().requires_grad_(True)
+    m_f, t_f = api.solve_differentiable(s, x0, params, prob["xf"], prob["K"])
+    w = torch.arange(1, 6, dtype=torch.float64, device=x0.device)
+    (w * m_f + 0.5 * t_f).sum().backward()
+    # the same vector-Jacobian product through the C ABI directly
+    sol, last = s.solve_record_into(prob, s.alloc_solution(5), s.alloc_lastiter(5))
+    cot = torch.stack([w, torch.full_like(w, 0.5)], dim=1).contiguous()
+    g = torch.empty((5, 18), dtype=torch.float64, device=x0.device)
+    s.grad_into(prob, last, cot, g)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(x0.grad.cpu().numpy(), g[:, :15].cpu().numpy(), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(params.grad[:, 2].cpu().numpy(), g[:, 16].cpu().numpy(), rtol=1e-12)
+    np.testing.assert_allclose(params.grad[:, 13].cpu().numpy(), g[:, 17].cpu().numpy(), rtol=1e-12)
+    assert torch.all(params.grad[:, [0, 1, 3, 12, 14]] == 0)
+    np.testing.assert_allclose(m_f.detach().cpu().numpy(), sol["m_f"].cpu().numpy(), rtol=0, atol=0)
+    s.close()
+
+
+def test_grad_invalid_instances_and_state_errors():
+    import torch
+    cfg = I.solver_settings("C3", scp_iters_max=2, pipg_iters_max=100)
+    inst = I.make_instances("C3", B=3)
+    inst["K"][1] = 1
+    s = api.BatchSolver(cfg, dtype="f32", k_max=20, max_batch=3)
+    prob = s.to_device(inst)
+    sol, last = s.solve_record_into(prob, s.alloc_solution(3), s.alloc_lastiter(3))
+    cot = torch.ones((3, 2), dtype=torch.float32, device=prob["x0"].device)
+    g = torch.full((3, 18), 7.0, dtype=torch.float32, device=cot.device)
+    s.grad_into(prob, last, cot, g)
+    torch.cuda.synchronize()
+    assert torch.all(g[1] == 0) and torch.all(torch.isfinite(g))
+    s.close()
+    s2 = api.BatchSolver(dict(cfg, grad_pipg_steps=0), dtype="f32", k_max=20, max_batch=3)
+    with pytest.raises(api.ScpError) as e:
+        s2.grad_into(prob, last, cot, g)
+    assert "STATE" in str(e.value)
+    s2.close()
