@@ -274,6 +274,43 @@ __device__ __forceinline__ R rowdot15(const R *c, R v, R acc)
     return rowdot_impl<R>(c, v, acc, std::make_integer_sequence<int, NX>{});
 }
 
+// FP32: each broadcast-multiply-add is one v_fmac_f32 whose first source is read through a
+// DPP row_newbcast, instead of a DPP move followed by an FMA.  The leading s_nop covers the
+// wait states a DPP source read needs after a VALU write of that register or of EXEC.
+template <>
+__device__ __forceinline__ float rowdot15<float>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]), "v"(c[8]), "v"(c[9]), "v"(c[10]), "v"(c[11]), "v"(c[12]), "v"(c[13]),
+          "v"(c[14]));
+    return acc;
+}
+
+// Square root and reciprocal for the projections: in FP32 the hardware instructions
+// (about 1 ulp) instead of the correctly rounded sequences; FP64 keeps IEEE arithmetic.
+__device__ __forceinline__ float proj_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double proj_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float proj_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double proj_rcp(double x) { return 1.0 / x; }
+
 // Node-wise convex sets, branch-free: project v = (t, z0, z1) onto the second-order cone
 // {||z|| <= a t} (when `cone`), then onto the ball of radius `rad` centred at the cone's apex
 // (rad = +inf for none); for a cone and a ball sharing that centre the composition is the
@@ -281,16 +318,16 @@ __device__ __forceinline__ R rowdot15(const R *c, R v, R acc)
 template <typename R>
 __device__ __forceinline__ void proj_cone_ball(R &t, R &z0, R &z1, bool cone, R a, R inv1a2, R rad)
 {
-    const R nz = sqrt(z0 * z0 + z1 * z1);
+    const R nz = proj_sqrt(z0 * z0 + z1 * z1);
     const bool inside = !cone || nz <= a * t;
     const bool polar = a * nz <= -t;
     const R tp = (t + a * nz) * inv1a2;
-    const R zs = nz > R(0) ? a * tp / nz : R(0);
+    const R zs = nz > R(0) ? a * tp * proj_rcp(nz) : R(0);
     const R t1 = inside ? t : (polar ? R(0) : tp);
     const R s1 = inside ? R(1) : (polar ? R(0) : zs);
     const R a0 = z0 * s1, a1 = z1 * s1;
-    const R n = sqrt(t1 * t1 + a0 * a0 + a1 * a1);
-    const R bs = n > rad ? rad / n : R(1);
+    const R n = proj_sqrt(t1 * t1 + a0 * a0 + a1 * a1);
+    const R bs = n > rad ? rad * proj_rcp(n) : R(1);
     t = t1 * bs;
     z0 = a0 * bs;
     z1 = a1 * bs;
@@ -533,6 +570,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const int pmask = a.node_projections;
     // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
     // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
+    // Lanes 4-6 (velocity, never in a state set) carry the thrust set, group 5, so that the
+    // state sets and the thrust set are projected by one evaluation across the row.
     int grp = 0, gw = 0, gb = 0;
     if (isx && !fixed) {
         if (i == 0) grp = (pmask & 1) ? 1 : 0;
@@ -541,12 +580,15 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         else if (i >= 11 && i <= 13) { grp = (pmask & 8) ? 4 : 0; gb = 11; }
         gw = i - gb;
     }
+    if (node && i >= 4 && i <= 6 && (pmask & 16)) grp = 5;
     const R INF = R(INFINITY);
     const double tan_g = tan(double(p[15])), tan_d = tan(double(p[14]));
-    const R g_a = grp == 2 ? R(1.0 / tan_g) : R(0);
-    const R g_inv = grp == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g))) : R(1);
-    const R g_rad = grp == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16]))))) : (grp == 4 ? p[17] : INF);
-    const R T_a = R(tan_d), T_inv = R(1.0 / (1.0 + tan_d * tan_d)), Tmax = p[13];
+    const R g_a = grp == 2 ? R(1.0 / tan_g) : (grp == 5 ? R(tan_d) : R(0));
+    const R g_inv = grp == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g)))
+                             : (grp == 5 ? R(1.0 / (1.0 + tan_d * tan_d)) : R(1));
+    const R g_rad = grp == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16])))))
+                             : (grp == 4 ? p[17] : (grp == 5 ? p[13] : INF));
+    const bool g_cone = grp == 2 || grp == 5;
     const R mdry = p[1];
     const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
     const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
@@ -586,24 +628,25 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             const R v1 = rowb<1>(xn), v2 = rowb<2>(xn), v3 = rowb<3>(xn);
             const R v9 = rowb<9>(xn), v10 = rowb<10>(xn);
             const R v11 = rowb<11>(xn), v12 = rowb<12>(xn), v13 = rowb<13>(xn);
-            R t0 = gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
-            R t1 = gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
-            R t2 = grp == 3 ? R(0) : gr2 + pxi * (grp == 2 ? v3 : v13);
-            proj_cone_ball<R>(t0, t1, t2, grp == 2, g_a, g_inv, g_rad);
+            const bool thr = grp == 5;
+            R t0 = thr ? ub[0] + pT * un[0] : gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
+            R t1 = thr ? ub[1] + pT * un[1] : gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
+            R t2 = thr ? ub[2] + pT * un[2]
+                       : (grp == 3 ? R(0) : gr2 + pxi * (grp == 2 ? v3 : v13));
+            // glide-slope cone; tilt disk; rate ball; thrust: gimbal cone, then the ball
+            // ||T|| <= T_max centred at its apex
+            proj_cone_ball<R>(t0, t1, t2, g_cone, g_a, g_inv, g_rad);
             const R o = gw == 0 ? t0 : (gw == 1 ? t1 : t2);
             const R gref = gw == 0 ? gr0 : (gw == 1 ? gr1 : gr2);
-            if (grp >= 2) xn = (o - gref) * ipxi;
+            if (grp >= 2 && grp <= 4) xn = (o - gref) * ipxi;
             if (grp == 1) {
                 const R m = xb + pxi * xn;
                 xn = m < mdry ? (mdry - xb) * ipxi : xn;
             }
             if (pmask & 16) {
-                // gimbal cone, then the ball ||T|| <= T_max centred at its apex
-                R T0 = ub[0] + pT * un[0], T1 = ub[1] + pT * un[1], T2 = ub[2] + pT * un[2];
-                proj_cone_ball<R>(T0, T1, T2, true, T_a, T_inv, Tmax);
-                un[0] = (T0 - ub[0]) * ipT;
-                un[1] = (T1 - ub[1]) * ipT;
-                un[2] = (T2 - ub[2]) * ipT;
+                un[0] = (rowb<4>(t0) - ub[0]) * ipT;
+                un[1] = (rowb<4>(t1) - ub[1]) * ipT;
+                un[2] = (rowb<4>(t2) - ub[2]) * ipT;
             }
         }
         if (fixed) xn = fixv;
@@ -616,7 +659,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         if (node) {
             sVx[k * DST + i] = vx;
-            if (i < NU) sVu[k * NU + i] = i == 0 ? vu[0] : (i == 1 ? vu[1] : (i == 2 ? vu[2] : vu[3]));
+            if (i == 0)
+                for (int q = 0; q < NU; ++q) sVu[k * NU + q] = vu[q];
         }
         }  // wact
         __syncthreads();
