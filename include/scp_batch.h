@@ -86,7 +86,9 @@ typedef struct {
     int32_t grad_pipg_steps;    /* PIPG steps of the differentiated last iteration (0: the
                                    handle computes no gradients and carves no scratch)     */
     int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */
-    int32_t reserved;
+    int32_t occupancy;          /* subproblem kernel variant: 0 = the compiler's register
+                                   budget (three waves per SIMD), 4 = limited to 128 VGPRs
+                                   for four waves per SIMD                                */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;
@@ -158,18 +160,20 @@ const char *scp_batch_create_error(void);
 scp_status scp_batch_profile(scp_batch h, int enable);
 scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
 
-/* Autotuner.  Times dispatch modes 1, 2 and 3 (see scp_settings.mode) with HIP events by
- * solving `problem` into `solution` (whose contents are overwritten) and keeps the fastest
- * mode for later solves on this handle; *mode_out receives it and ms_out[4] the measured
- * milliseconds per mode (-1 where not timed).  With a non-NULL cache_path, a JSON-lines
- * file keyed by (GPU arch, k_max, dtype, early_exit, node_projections, batch) is consulted
- * first -- a hit skips the timing -- and the new result is appended.  Synchronizes the
- * handle's stream. */
+/* Autotuner.  Times the launch variants (mode, occupancy) = (1, 0), (2, 0), (3, 0), (1, 4),
+ * (2, 4) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
+ * HIP events, solving `problem` into `solution` (whose contents are overwritten), and keeps
+ * the fastest for later solves on this handle.  *variant_out receives its index and
+ * ms_out[SCP_TUNE_VARIANTS] the measured milliseconds per variant (-1 where not timed).
+ * With a non-NULL cache_path, a JSON-lines file keyed by (GPU arch, k_max, dtype,
+ * early_exit, node_projections, batch) is consulted first -- a hit skips the timing -- and
+ * the new result is appended.  Synchronizes the handle's stream. */
+#define SCP_TUNE_VARIANTS 5
 scp_status scp_batch_autotune(scp_batch h, const scp_problem *problem, scp_solution *solution,
-                              const char *cache_path, int32_t *mode_out, double *ms_out);
+                              const char *cache_path, int32_t *variant_out, double *ms_out);
 
-/* The dispatch mode the handle currently uses. */
-scp_status scp_batch_mode(scp_batch h, int32_t *mode_out);
+/* The dispatch mode and occupancy variant the handle currently uses. */
+scp_status scp_batch_mode(scp_batch h, int32_t *mode_out, int32_t *occupancy_out);
 
 /* Starting point of the last convex subproblem an instance solved: the reference trajectory
  * it linearized about, the warm-start duals (mu+, mu-, the dynamics dual phi and the CTCS

@@ -33,6 +33,10 @@ class ScpError(RuntimeError):
         self.code = code
 
 
+# launch variants timed by scp_batch_autotune: (dispatch mode, occupancy)
+TUNE_VARIANTS = ((1, 0), (2, 0), (3, 0), (1, 4), (2, 4))
+
+
 class Settings(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int32), ("k_max", ctypes.c_int32), ("max_batch", ctypes.c_int32),
@@ -41,7 +45,7 @@ class Settings(ctypes.Structure):
         ("power_iters_max", ctypes.c_int32), ("early_exit", ctypes.c_int32),
         ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("grad_pipg_steps", ctypes.c_int32), ("grad_ckpt_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("occupancy", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
         ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
@@ -105,7 +109,8 @@ def load():
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double)]
         L.scp_batch_autotune.restype = ctypes.c_int
-        L.scp_batch_mode.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+        L.scp_batch_mode.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
         L.scp_batch_mode.restype = ctypes.c_int
         L.scp_batch_solve_record.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
                                              ctypes.POINTER(Solution), ctypes.POINTER(LastIter)]
@@ -130,6 +135,7 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
                  "power_iters_max", "early_exit", "node_projections"):
         setattr(s, name, int(cfg[name]))
     s.mode = int(cfg.get("mode", 0))
+    s.occupancy = int(cfg.get("occupancy", 0))
     s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
     s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",
@@ -227,20 +233,22 @@ class BatchSolver:
         return p, s
 
     def autotune(self, prob, sol, cache_path=None):
-        """Time the dispatch modes on this batch and keep the fastest (see
-        scp_batch_autotune); returns (mode, {mode: ms})."""
+        """Time the launch variants on this batch and keep the fastest (see
+        scp_batch_autotune); returns ((mode, occupancy), {(mode, occupancy): ms})."""
         p, s = self._structs(prob, sol)
-        mode = ctypes.c_int32(-1)
-        ms = (ctypes.c_double * 4)()
+        var = ctypes.c_int32(-1)
+        ms = (ctypes.c_double * len(TUNE_VARIANTS))()
         path = None if cache_path is None else str(cache_path).encode()
         self._check(load().scp_batch_autotune(self.handle, ctypes.byref(p), ctypes.byref(s),
-                                              path, ctypes.byref(mode), ms))
-        return mode.value, {m: ms[m] for m in range(1, 4) if ms[m] >= 0}
+                                              path, ctypes.byref(var), ms))
+        return TUNE_VARIANTS[var.value], {TUNE_VARIANTS[v]: ms[v]
+                                          for v in range(len(TUNE_VARIANTS)) if ms[v] >= 0}
 
     def mode(self):
-        m = ctypes.c_int32(-1)
-        self._check(load().scp_batch_mode(self.handle, ctypes.byref(m)))
-        return m.value
+        """(dispatch mode, occupancy variant) in use."""
+        m, o = ctypes.c_int32(-1), ctypes.c_int32(-1)
+        self._check(load().scp_batch_mode(self.handle, ctypes.byref(m), ctypes.byref(o)))
+        return m.value, o.value
 
     def _check_problem(self, prob):
         B = int(prob["x0"].shape[0])

@@ -42,6 +42,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
     }
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
     if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
+    if (s->occupancy != 0 && s->occupancy != 4) { why = "occupancy must be 0 or 4"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -251,6 +252,7 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.node_projections = s.node_projections;
     cfg.persistent_blocks = 0;
     cfg.ordered = s.mode == 2 ? 1 : 0;
+    cfg.occupancy = s.occupancy;
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -506,6 +508,9 @@ static std::string tune_key(scp_batch h, int batch)
     return k.str();
 }
 
+static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2};
+static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 4, 4};
+
 static int cache_lookup(const char *path, const std::string &key)
 {
     if (!path) return -1;
@@ -513,27 +518,34 @@ static int cache_lookup(const char *path, const std::string &key)
     std::string line;
     int found = -1;
     const std::string pat = "\"key\": \"" + key + "\"";
+    const std::string tag = "\"variant\": ";
     while (std::getline(f, line)) {
         if (line.find(pat) == std::string::npos) continue;
-        const size_t m = line.find("\"mode\": ");
-        if (m != std::string::npos) found = atoi(line.c_str() + m + 8);
+        const size_t m = line.find(tag);
+        if (m != std::string::npos) found = atoi(line.c_str() + m + tag.size());
     }
-    return (found >= 0 && found <= 3) ? found : -1;
+    return (found >= 0 && found < SCP_TUNE_VARIANTS) ? found : -1;
+}
+
+static void set_variant(scp_batch h, int v)
+{
+    h->st.mode = TUNE_MODE[v];
+    h->st.occupancy = TUNE_OCC[v];
+    drop_graph(h);
 }
 
 scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution *sol,
-                              const char *cache_path, int32_t *mode_out, double *ms_out)
+                              const char *cache_path, int32_t *variant_out, double *ms_out)
 {
     if (!h) return SCP_ERR_ARG;
     h->err.clear();
-    if (!prob || !sol || !mode_out || !ms_out) return fail(h, SCP_ERR_ARG, "null argument");
-    for (int m = 0; m < 4; ++m) ms_out[m] = -1.0;
+    if (!prob || !sol || !variant_out || !ms_out) return fail(h, SCP_ERR_ARG, "null argument");
+    for (int v = 0; v < SCP_TUNE_VARIANTS; ++v) ms_out[v] = -1.0;
     const std::string key = tune_key(h, prob->batch);
     const int cached = cache_lookup(cache_path, key);
     if (cached >= 0) {
-        h->st.mode = cached;
-        drop_graph(h);
-        *mode_out = cached;
+        set_variant(h, cached);
+        *variant_out = cached;
         return SCP_OK;
     }
     if (h->profiling) return fail(h, SCP_ERR_STATE, "disable profiling before autotuning");
@@ -544,12 +556,11 @@ scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution
         if (e0) (void)hipEventDestroy(e0);
         return fail(h, SCP_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
     }
-    const int saved_mode = h->st.mode;
+    const int saved_mode = h->st.mode, saved_occ = h->st.occupancy;
     int best = -1;
     double best_ms = 0.0;
-    for (int m = 1; m <= 3; ++m) {
-        h->st.mode = m;
-        drop_graph(h);
+    for (int m = 0; m < SCP_TUNE_VARIANTS; ++m) {
+        set_variant(h, m);
         scp_status st = scp_batch_solve(h, prob, sol);  // capture + warm-up
         if (st != SCP_OK) break;
         float t = 0.0f;
@@ -569,25 +580,28 @@ scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution
     (void)hipEventDestroy(e1);
     if (best < 0) {
         h->st.mode = saved_mode;
+        h->st.occupancy = saved_occ;
         drop_graph(h);
         if (h->err.empty()) h->err = std::string("autotune: ") + hipGetErrorString(e);
         return SCP_ERR_HIP;
     }
-    h->st.mode = best;
-    drop_graph(h);
-    *mode_out = best;
+    set_variant(h, best);
+    *variant_out = best;
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        f << "{\"key\": \"" << key << "\", \"mode\": " << best << ", \"ms\": [" << ms_out[1]
-          << ", " << ms_out[2] << ", " << ms_out[3] << "]}\n";
+        f << "{\"key\": \"" << key << "\", \"variant\": " << best << ", \"mode\": "
+          << TUNE_MODE[best] << ", \"occupancy\": " << TUNE_OCC[best] << ", \"ms\": [";
+        for (int v = 0; v < SCP_TUNE_VARIANTS; ++v) f << (v ? ", " : "") << ms_out[v];
+        f << "]}\n";
     }
     return SCP_OK;
 }
 
-scp_status scp_batch_mode(scp_batch h, int32_t *mode_out)
+scp_status scp_batch_mode(scp_batch h, int32_t *mode_out, int32_t *occupancy_out)
 {
-    if (!h || !mode_out) return SCP_ERR_ARG;
+    if (!h || !mode_out || !occupancy_out) return SCP_ERR_ARG;
     *mode_out = h->st.mode;
+    *occupancy_out = h->st.occupancy;
     return SCP_OK;
 }
 

@@ -261,6 +261,34 @@ __device__ __forceinline__ R row_allreduce(R v)
     v = v + dppmov<0x128>(v);  // row_ror:8
     return v;
 }
+// Four row sums at once, scattered: lane i receives sum over the row of v[i >> 2], where
+// v[q] is this lane's q-th addend.  Three exchange steps (row_mirror pairs lanes differing
+// in bit 3, row_half_mirror lanes differing in bit 2, then the two quad swaps) keep half of
+// the values each time; the four lanes of a quad end with bitwise identical sums.
+template <typename R>
+__device__ __forceinline__ R row_reduce_scatter4(const R (&v)[NU], int i)
+{
+    const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0;
+    const R k0 = b3 ? v[2] : v[0], k1 = b3 ? v[3] : v[1];
+    const R s0 = b3 ? v[0] : v[2], s1 = b3 ? v[1] : v[3];
+    const R a0 = k0 + dppmov<0x140>(s0);  // row_mirror
+    const R a1 = k1 + dppmov<0x140>(s1);
+    const R kk = b2 ? a1 : a0, ss = b2 ? a0 : a1;
+    R w = kk + dppmov<0x141>(ss);         // row_half_mirror
+    w = w + dppmov<0xB1>(w);              // quad_perm [1,0,3,2]
+    w = w + dppmov<0x4E>(w);              // quad_perm [2,3,0,1]
+    return w;
+}
+// sum_q c[q] * (value of lane 4q of this row), q = 0..3
+template <typename R>
+__device__ __forceinline__ R rowdot4q(const R *c, R v, R acc)
+{
+    acc = acc + c[0] * rowb<0>(v);
+    acc = acc + c[1] * rowb<4>(v);
+    acc = acc + c[2] * rowb<8>(v);
+    acc = acc + c[3] * rowb<12>(v);
+    return acc;
+}
 // sum_j c[j] * (value of lane j of this row), j = 0..14, in a fixed order
 template <typename R, int... J>
 __device__ __forceinline__ R rowdot_impl(const R *c, R v, R acc, std::integer_sequence<int, J...>)
@@ -277,6 +305,19 @@ __device__ __forceinline__ R rowdot15(const R *c, R v, R acc)
 // FP32: each broadcast-multiply-add is one v_fmac_f32 whose first source is read through a
 // DPP row_newbcast, instead of a DPP move followed by an FMA.  The leading s_nop covers the
 // wait states a DPP source read needs after a VALU write of that register or of EXEC.
+template <>
+__device__ __forceinline__ float rowdot4q<float>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
 template <>
 __device__ __forceinline__ float rowdot15<float>(const float *c, float v, float acc)
 {
@@ -433,8 +474,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // boundary values, bounds, reference values
     const R xb = isx ? a.x[xoff + i] : R(0);
-    R ub[NU];
-    for (int q = 0; q < NU; ++q) ub[q] = node ? a.u[uoff + q] : R(0);
+    const int qi = i >> 2;  // control component of this lane (lanes 4q..4q+3 hold u_q)
+    const R ubq = node ? a.u[uoff + qi] : R(0);
+    const R ub3 = node ? a.u[uoff + 3] : R(0);
     bool fixed = false;
     R fixv = R(0);
     if (isx) {
@@ -447,8 +489,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             fixv = R((double(a.xf[(long)b * NXF + i - 1]) - double(xb)) / a.px[i]);
         }
     }
-    const R slo = R((double(p[18]) - double(ub[3])) / a.pu[3]);
-    const R shi = R((double(p[19]) - double(ub[3])) / a.pu[3]);
+    const R slo = R((double(p[18]) - double(ub3)) / a.pu[3]);
+    const R shi = R((double(p[19]) - double(ub3)) / a.pu[3]);
     R wk = R(0), epsk = R(0);
     if (dual) {
         wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
@@ -535,8 +577,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // fresh iterates (x^, u^, mu, phi, theta) double as the previous iterate of the stopping
     // test; the extrapolated ones are x~, u~, nu, varphi, vartheta
     R xt = R(0), xh = R(0);
-    R ut[NU], uh[NU];
-    for (int q = 0; q < NU; ++q) ut[q] = uh[q] = R(0);
+    R ut = R(0), uh = R(0);  // control component qi of node k
     R vphi = R(0), ph = R(0);
     R nup = R(0), num = R(0), mup = R(0), mum = R(0);
     R vth = R(0), th = R(0);
@@ -592,6 +633,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const R mdry = p[1];
     const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
     const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
+    const R ubT0 = rowb<0>(ubq), ubT1 = rowb<4>(ubq), ubT2 = rowb<8>(ubq);  // reference thrust
     // reference values of the group members (original units)
     const R xbb1 = rowb<1>(xb), xbb2 = rowb<2>(xb), xbb3 = rowb<3>(xb);
     const R xbb9 = rowb<9>(xb), xbb10 = rowb<10>(xb);
@@ -602,8 +644,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     int it = 1;
     for (; it <= jmax; ++it) {
-        R xn = R(0), un[NU] = {R(0), R(0), R(0), R(0)};
-        R vx = R(0), vu[NU] = {R(0), R(0), R(0), R(0)};
+        R xn = R(0), un = R(0);
+        R vx = R(0), vu = R(0);
         R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
         if (wact) {
         // ---- projected gradient step on the primal variables ----
@@ -616,22 +658,23 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         if (i == IY) g += (k < M ? -thk : R(0)) + (k > 0 ? thm1 : R(0));
         xn = xt - alpha * g;
         // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
-        for (int q = 0; q < NU; ++q) {
-            R gq = rowBm[q] * vphi + rowBq[q] * phm1;
-            gq = row_allreduce<R>(gq);
-            gq = wprox * ut[q] + gq;
-            un[q] = ut[q] - alpha * gq;
+        {
+            R gq[NU];
+            for (int q = 0; q < NU; ++q) gq[q] = rowBm[q] * vphi + rowBq[q] * phm1;
+            const R g = wprox * ut + row_reduce_scatter4<R>(gq, i);
+            un = ut - alpha * g;
         }
-        un[3] = fmin(fmax(un[3], slo), shi);
+        if (qi == 3) un = fmin(fmax(un, slo), shi);
         if (pmask) {
             // state sets: gather the pre-projection values of this lane's group
             const R v1 = rowb<1>(xn), v2 = rowb<2>(xn), v3 = rowb<3>(xn);
             const R v9 = rowb<9>(xn), v10 = rowb<10>(xn);
             const R v11 = rowb<11>(xn), v12 = rowb<12>(xn), v13 = rowb<13>(xn);
             const bool thr = grp == 5;
-            R t0 = thr ? ub[0] + pT * un[0] : gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
-            R t1 = thr ? ub[1] + pT * un[1] : gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
-            R t2 = thr ? ub[2] + pT * un[2]
+            const R u0 = rowb<0>(un), u1 = rowb<4>(un), u2 = rowb<8>(un);
+            R t0 = thr ? ubT0 + pT * u0 : gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
+            R t1 = thr ? ubT1 + pT * u1 : gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
+            R t2 = thr ? ubT2 + pT * u2
                        : (grp == 3 ? R(0) : gr2 + pxi * (grp == 2 ? v3 : v13));
             // glide-slope cone; tilt disk; rate ball; thrust: gimbal cone, then the ball
             // ||T|| <= T_max centred at its apex
@@ -644,23 +687,19 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                 xn = m < mdry ? (mdry - xb) * ipxi : xn;
             }
             if (pmask & 16) {
-                un[0] = (rowb<4>(t0) - ub[0]) * ipT;
-                un[1] = (rowb<4>(t1) - ub[1]) * ipT;
-                un[2] = (rowb<4>(t2) - ub[2]) * ipT;
+                const R T0 = rowb<4>(t0), T1 = rowb<4>(t1), T2 = rowb<4>(t2);
+                if (qi < 3) un = ((qi == 0 ? T0 : (qi == 1 ? T1 : T2)) - ubq) * ipT;
             }
         }
         if (fixed) xn = fixv;
         if (!isx) xn = R(0);
         vx = R(2) * xn - xt;
         xt = omr * xt + rho * xn;
-        for (int q = 0; q < NU; ++q) {
-            vu[q] = R(2) * un[q] - ut[q];
-            ut[q] = omr * ut[q] + rho * un[q];
-        }
+        vu = R(2) * un - ut;
+        ut = omr * ut + rho * un;
         if (node) {
             sVx[k * DST + i] = vx;
-            if (i == 0)
-                for (int q = 0; q < NU; ++q) sVu[k * NU + q] = vu[q];
+            if ((i & 3) == 0) sVu[k * NU + qi] = vu;
         }
         }  // wact
         __syncthreads();
@@ -673,9 +712,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
         const R vnext = (k + 1 < K) ? sVx[(k + 1) * DST + i] : R(0);
         r -= vnext;
+        r = rowdot4q<R>(rowBm, vu, r);  // B^-_k (2u^ - u~)_k
         for (int q = 0; q < NU; ++q) {
             const R vun = (k + 1 < K) ? sVu[(k + 1) * NU + q] : R(0);
-            r += rowBm[q] * vu[q];
             r += rowBp[q] * vun;
         }
         r += (R(2) * mupn - nup) - (R(2) * mumn - num);
@@ -705,12 +744,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                 nz[1] = fabs(double(xh));
                 nz[2] = fabs(double(xn) - double(xh));
             }
-            if (node && i == 0)
-                for (int q = 0; q < NU; ++q) {
-                    nz[0] = fmax(nz[0], fabs(double(un[q])));
-                    nz[1] = fmax(nz[1], fabs(double(uh[q])));
-                    nz[2] = fmax(nz[2], fabs(double(un[q]) - double(uh[q])));
-                }
+            if (node && (i & 3) == 0) {
+                nz[0] = fmax(nz[0], fabs(double(un)));
+                nz[1] = fmax(nz[1], fabs(double(uh)));
+                nz[2] = fmax(nz[2], fabs(double(un) - double(uh)));
+            }
             if (dual) {
                 nz[0] = fmax(nz[0], fmax(fabs(double(mupn)), fabs(double(mumn))));
                 nz[1] = fmax(nz[1], fmax(fabs(double(mup)), fabs(double(mum))));
@@ -730,7 +768,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                    nz[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(nz[3], nz[4]);
         }
         xh = xn;
-        for (int q = 0; q < NU; ++q) uh[q] = un[q];
+        uh = un;
         mup = mupn;
         mum = mumn;
         ph = phn;
@@ -749,11 +787,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         st[0] = fabs(double(xh));
         a.x[xoff + i] = R(double(xb) + a.px[i] * double(xh));
     }
-    if (node && i < NU) {
-        const R uq = i == 0 ? uh[0] : (i == 1 ? uh[1] : (i == 2 ? uh[2] : uh[3]));
-        const R ubq = i == 0 ? ub[0] : (i == 1 ? ub[1] : (i == 2 ? ub[2] : ub[3]));
-        st[0] = fmax(st[0], fabs(double(uq)));
-        a.u[uoff + i] = R(double(ubq) + a.pu[i] * double(uq));
+    if (node && (i & 3) == 0) {
+        st[0] = fmax(st[0], fabs(double(uh)));
+        a.u[uoff + qi] = R(double(ubq) + a.pu[qi] * double(uh));
     }
     if (dual) {
         a.mup[doff] = mup;
@@ -770,8 +806,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
 // ------------------------------------------------------------------------------------------
 
-template <typename R, int MAXT>
-__global__ void __launch_bounds__(MAXT) subproblem_kernel(Args<R> a)
+// WPE: minimum waves per SIMD the register allocation must allow (1: no constraint).
+template <typename R, int MAXT, int WPE>
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE)))
+subproblem_kernel(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // with ordered dispatch, workgroup w takes the w-th instance by node count (descending):
@@ -952,9 +990,12 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
             else
                 subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
         } else if (qthreads <= 640) {
-            subproblem_kernel<R, 640><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+            if (cfg.occupancy == 4)
+                subproblem_kernel<R, 640, 4><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+            else
+                subproblem_kernel<R, 640, 1><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
         } else {
-            subproblem_kernel<R, 1024><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+            subproblem_kernel<R, 1024, 1><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(2, false)) != hipSuccess) return e;

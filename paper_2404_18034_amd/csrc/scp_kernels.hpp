@@ -30,6 +30,7 @@ struct Config {
     int early_exit, node_projections;
     int persistent_blocks;  // 0: one workgroup per instance; > 0: persistent grid size
     int ordered;            // 1: workgroups take instances by node count, descending
+    int occupancy;          // 4: subproblem variant limited to four waves per SIMD
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;

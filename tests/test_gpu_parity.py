@@ -235,15 +235,16 @@ def test_invalid_arguments_raise():
     s.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
-def test_dispatch_modes_match_plain_launches(mode):
+@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (2, 4)])
+def test_dispatch_modes_match_plain_launches(mode, occupancy):
     # graph replay, K-ordered dispatch and the persistent work queue compute the same thing as
     # plain launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
     import torch
     cfg = I.solver_settings("C2")
     inst = I.make_instances("C2", B=40)
     ref = _gpu(cfg, inst, "f32", k_max=30)
-    s = api.BatchSolver(dict(cfg, mode=mode), dtype="f32", k_max=30, max_batch=64)
+    s = api.BatchSolver(dict(cfg, mode=mode, occupancy=occupancy), dtype="f32", k_max=30,
+                        max_batch=64)
     prob = s.to_device(inst)
     sol = s.alloc_solution(40)
     for rep in range(3):
@@ -273,7 +274,7 @@ def test_autotune_picks_a_mode_and_keeps_results(tmp_path):
     cache = tmp_path / "tune.jsonl"
     mode, ms = s.autotune(prob, sol, cache_path=cache)
     print("autotune", mode, ms)
-    assert mode in (1, 2, 3) and s.mode() == mode and len(ms) == 3
+    assert mode in api.TUNE_VARIANTS and s.mode() == mode and len(ms) == len(api.TUNE_VARIANTS)
     assert cache.read_text().count("\n") == 1
     mode2, ms2 = s.autotune(prob, sol, cache_path=cache)     # cache hit: no timing
     assert mode2 == mode and ms2 == {}
