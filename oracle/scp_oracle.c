@@ -38,10 +38,13 @@
  * that rounding. */
 #define NORM_EPS 1e-4
 
-/* Final boundary condition E_f: r, v, the tilt part (q2, q3) of the attitude and w are fixed;
- * the roll part (q0, q1), the mass and y are free.  Reading of "land upright": with thrust as
- * the only input, roll about the body axis is not controllable, so it cannot be prescribed. */
-static int final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8; }
+/* Final boundary condition E_f: r, v, the tilt part (q2, q3) of the attitude and the
+ * transverse rates (w2, w3) are fixed; the roll angle part (q0, q1), the roll rate w1, the
+ * mass and y are free.  Reading of "land upright at rest": with thrust as the only input the
+ * torque r_T x T has no component about the thrust axis, so roll is not controllable and
+ * neither its angle nor its rate can be prescribed (with unequal transverse inertias the
+ * gyroscopic coupling drives w1, and a fixed w1 = 0 leaves a defect no iteration removes). */
+static int final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8 && i != 11; }
 
 enum {
     P_MWET = 0, P_MDRY = 1, P_ALPHA = 2, P_G = 3, P_J = 6, P_RT = 9, P_TMIN = 12, P_TMAX = 13,

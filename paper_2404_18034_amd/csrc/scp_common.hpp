@@ -13,8 +13,13 @@ constexpr int BLK = COLS * CST;  // entries per interval
 constexpr int VST = 20;          // node stride of (x, u) vectors in LDS (15 + 4 + pad)
 constexpr int DST = 16;          // interval stride of dual vectors
 
-// Final boundary condition: r, v, (q2, q3) and w are imposed; m, (q0, q1) and y are free.
-__device__ __forceinline__ bool final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8; }
+// Final boundary condition: r, v, (q2, q3) and the transverse rates (w2, w3) are imposed; m,
+// the roll angle part (q0, q1), the roll rate w1 and y are free (roll is not controllable by
+// thrust alone).
+__device__ __forceinline__ bool final_fixed(int i)
+{
+    return i >= 1 && i <= 13 && i != 7 && i != 8 && i != 11;
+}
 
 // ------------------------------------------------------------------------------------------
 // Workgroup reductions with a fixed combination order (deterministic).

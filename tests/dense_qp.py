@@ -55,7 +55,7 @@ def join(d):
     return np.concatenate([d["x"].ravel(), d["u"].ravel(), d["mup"].ravel(), d["mum"].ravel()])
 
 
-FINAL_FIXED = [1, 2, 3, 4, 5, 6, 9, 10, 11, 12, 13]   # r, v, (q2, q3), w
+FINAL_FIXED = [1, 2, 3, 4, 5, 6, 9, 10, 12, 13]   # r, v, (q2, q3), (w2, w3)
 
 
 def project(z, qp, K):

@@ -30,7 +30,7 @@ def test_c0_boundary_conditions_exact(c0):
     x = r["x"][0, :K]
     np.testing.assert_allclose(x[0, :14], inst["x0"][0, :14], atol=1e-12)
     assert abs(x[0, 14]) <= 1e-12
-    fixed = [1, 2, 3, 4, 5, 6, 9, 10, 11, 12, 13]
+    fixed = [1, 2, 3, 4, 5, 6, 9, 10, 12, 13]
     np.testing.assert_allclose(x[K - 1, fixed], inst["xf"][0, [i - 1 for i in fixed]], atol=1e-12)
 
 
