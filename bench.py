@@ -41,19 +41,27 @@ def pipg_flops_per_iter(K):
     return M * (4 * 316 + 428) + 171 * K
 
 
-def cpu_baseline(cfg, inst, n_sample, threads):
+def cpu_baseline(cfg, inst, n_sample, threads, kmax):
+    """The FP64 oracle on the host cores: `n_sample` instances on `threads` threads, plus a
+    serial run on a quarter of them (the paper's CPU reference solves one instance at a
+    time)."""
     import oracle
-    ids = np.arange(n_sample)
-    sub = {k: v[ids] for k, v in inst.items()}
     oracle.build()
-    t = time.perf_counter()
-    r = oracle.solve(cfg, sub["x0"], sub["xf"], sub["params"], sub["K"], nthreads=threads)
-    dt = time.perf_counter() - t
-    conv = int(np.sum(r["status"] == 0))
+    out = {}
+    for n, th in ((n_sample, threads), (max(1, n_sample // 16), 1)):
+        sub = {k: v[:n] for k, v in inst.items()}
+        t = time.perf_counter()
+        r = oracle.solve(cfg, sub["x0"], sub["xf"], sub["params"], sub["K"], kmax=kmax,
+                         nthreads=th)
+        out[th] = (n, time.perf_counter() - t, int(np.sum(r["status"] == 0)))
+    n, dt, conv = out[threads]
+    n1, dt1, conv1 = out[1]
     return dict(value=round(conv / dt, 3), unit="converged solves/s", cores=threads,
                 kind="oracle",
                 sample="first %d of the %d instances (same settings), %d threads, %.1f s wall, "
-                       "%d converged" % (n_sample, inst["K"].shape[0], threads, dt, conv))
+                       "%d converged" % (n, inst["K"].shape[0], threads, dt, conv),
+                single_thread=dict(value=round(conv1 / dt1, 3), instances=n1,
+                                   wall_s=round(dt1, 2), converged=conv1))
 
 
 def main():
@@ -165,7 +173,7 @@ def main():
         out["autotune_ms"] = {str(m): round(v, 3) for m, v in tuned[1].items()}
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(cfg, inst, args.cpu_sample, threads)
+        out["cpu_baseline"] = cpu_baseline(cfg, inst, args.cpu_sample, threads, K)
     print(json.dumps(out), flush=True)
     solver.close()
 
