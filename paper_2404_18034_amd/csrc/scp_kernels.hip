@@ -400,10 +400,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     double *dZ = red + 128;                                       // [kmax][VST]
     double *dPhi = dZ + kmax * VST;                               // [kmax][DST]
     double *dTh = dPhi + kmax * DST;                              // [kmax]
-    R *sPhi = reinterpret_cast<R *>(dTh + kmax);                  // [kmax][DST]
-    R *sTh = sPhi + kmax * DST;                                   // [kmax]
-    R *sVx = sTh + kmax;                                          // [kmax][DST]
-    R *sVu = sVx + kmax * DST;                                    // [kmax][4]
+    // staging of neighbour values, one row per workgroup row (KR of them) plus a zero row:
+    // row -1 of sPhi/sTh (phi_0, theta_0 of the first node) and row KR of sVx/sVu, so that
+    // rows k - 1 and k + 1 are read without bounds tests
+    const int KR = (kmax + 3) / 4 * 4;
+    R *sPhi = reinterpret_cast<R *>(dTh + kmax) + DST;            // rows -1..KR-1 of [DST]
+    R *sTh = sPhi + KR * DST + 1;                                 // rows -1..KR-1
+    R *sVx = sTh + KR;                                            // rows 0..KR of [DST]
+    R *sVu = sVx + (KR + 1) * DST;                                // rows 0..KR of [4]
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -588,9 +592,13 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         ph = vphi = a.phi[doff];
         if (i == IY) th = vth = a.th[(long)b * kmax + k];
     }
-    if (k < kmax) {
-        sPhi[k * DST + i] = vphi;
-        if (i == IY) sTh[k] = vth;
+    sPhi[k * DST + i] = vphi;
+    if (i == IY) sTh[k] = vth;
+    if (k == 0) {
+        sPhi[i - DST] = R(0);
+        sVx[KR * DST + i] = R(0);
+        if (i == 0) sTh[-1] = R(0);
+        if (i < NU) sVu[KR * NU + i] = R(0);
     }
     if (a.rec_x) {
         if (isx) a.rec_x[xoff + i] = xb;
@@ -649,13 +657,13 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
         if (wact) {
         // ---- projected gradient step on the primal variables ----
-        const R phm1 = (k > 0 && k < kmax) ? sPhi[(k - 1) * DST + i] : R(0);  // phi_{k-1}[i]
-        const R thm1 = (k > 0 && k < kmax) ? sTh[k - 1] : R(0);               // theta_{k-1}
+        const R phm1 = sPhi[(k - 1) * DST + i];  // phi_{k-1}[i] (zero row above the first node)
+        const R thm1 = sTh[k - 1];               // theta_{k-1}
         const R thk = rowb<IY>(vth);                                          // theta_k
         R g = wprox * xt + cost;
         g = rowdot15<R>(colA, vphi, g);  // (A^-_k)^T phi_k, column i
-        g -= (k > 0) ? phm1 : R(0);
-        if (i == IY) g += (k < M ? -thk : R(0)) + (k > 0 ? thm1 : R(0));
+        g -= phm1;
+        if (i == IY) g += (k < M ? -thk : R(0)) + thm1;
         xn = xt - alpha * g;
         // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
         {
@@ -710,11 +718,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
         R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
-        const R vnext = (k + 1 < K) ? sVx[(k + 1) * DST + i] : R(0);
+        const R vnext = sVx[(k + 1) * DST + i];  // used by the dynamics rows k < K - 1 only
         r -= vnext;
         r = rowdot4q<R>(rowBm, vu, r);  // B^-_k (2u^ - u~)_k
         for (int q = 0; q < NU; ++q) {
-            const R vun = (k + 1 < K) ? sVu[(k + 1) * NU + q] : R(0);
+            const R vun = sVu[(k + 1) * NU + q];
             r += rowBp[q] * vun;
         }
         r += (R(2) * mupn - nup) - (R(2) * mumn - num);
@@ -730,10 +738,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         nup = omr * nup + rho * mupn;
         num = omr * num + rho * mumn;
         vth = omr * vth + rho * thn;
-        if (k < kmax) {
-            sPhi[k * DST + i] = vphi;
-            if (i == IY) sTh[k] = vth;
-        }
+        sPhi[k * DST + i] = vphi;
+        if (i == IY) sTh[k] = vth;
         }  // wact
         bool done = false;
         if (check > 0 && it % check == 0) {
@@ -876,8 +882,9 @@ int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
 static size_t qp_smem_bytes(int kmax, size_t rsize)
 {
+    const size_t KR = (size_t)(kmax + 3) / 4 * 4;
     return sizeof(double) * (128 + kmax * VST + kmax * DST + kmax) +
-           rsize * (kmax * DST + kmax + kmax * DST + kmax * NU);
+           rsize * ((KR + 1) * DST + (KR + 1) + (KR + 1) * DST + (KR + 1) * NU);
 }
 
 template <typename R>
