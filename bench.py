@@ -41,6 +41,40 @@ def pipg_flops_per_iter(K):
     return M * (4 * 316 + 428) + 171 * K
 
 
+KERNEL_SOURCES = ("paper_2404_18034_amd/csrc/scp_kernels.hip",
+                  "paper_2404_18034_amd/csrc/scp_common.hpp",
+                  "paper_2404_18034_amd/csrc/lander_model.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "subproblem_kernel_traffic_mc1024.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per subproblem launch from the committed hardware-counter summary, or None
+    when there is none or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, inst, n_sample, threads, kmax):
     """The FP64 oracle on the host cores: `n_sample` instances on `threads` threads, plus a
     serial run on a quarter of them (the paper's CPU reference solves one instance at a
@@ -149,7 +183,7 @@ def main():
     achieved = flops_per_solve / (sub_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    traffic=None, kernel="subproblem_kernel",
+                    traffic=measured_traffic(), kernel="subproblem_kernel",
                     avg_launch_ms=round(sub_ms / max(sub_launches, 1), 4),
                     kernel_ms_per_step={k: round(v[0] / nprof, 3) for k, v in per.items()})
 
