@@ -89,6 +89,9 @@ typedef struct {
     int32_t occupancy;          /* subproblem kernel variant: 0 = the compiler's register
                                    budget (three waves per SIMD), 4 = limited to 128 VGPRs
                                    for four waves per SIMD                                */
+    int32_t grad_rk4_tangent;   /* how scp_batch_grad differentiates the discretization:
+                                   0 = reverse (adjoint) sweep through the RK4 stages,
+                                   1 = forward tangents along (alpha_mdot, T_max)          */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;

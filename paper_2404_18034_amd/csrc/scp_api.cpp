@@ -25,7 +25,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, queue, bucket, order;
-    size_t dblk, dwhat, tape, gstat;  // gradient scratch (present when grad_pipg_steps > 0)
+    size_t dblk, dwhat, tape, gstat, pbar;  // gradient scratch (when grad_pipg_steps > 0)
     size_t total;
 };
 
@@ -43,6 +43,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
     if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
     if (s->occupancy != 0 && s->occupancy != 4) { why = "occupancy must be 0 or 4"; return false; }
+    if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -91,13 +92,14 @@ Layout layout_of(const scp_settings *s)
     L.queue = take((size_t)(s->scp_iters_max + 2) * 4);
     L.bucket = take((K + 1) * 4);
     L.order = take(B * 4);
-    L.dblk = L.dwhat = L.tape = L.gstat = 0;
+    L.dblk = L.dwhat = L.tape = L.gstat = L.pbar = 0;
     if (s->grad_pipg_steps > 0) {
         const size_t n_ckpt = (size_t)((s->grad_pipg_steps + s->grad_ckpt_every - 1) / s->grad_ckpt_every);
         L.dblk = take(B * M * 2 * 23 * 16 * rs);
         L.dwhat = take(B * M * 2 * 16 * rs);
         L.tape = take(B * (n_ckpt + (size_t)s->grad_ckpt_every) * (size_t)scp::grad_state_len(s->k_max) * rs);
         L.gstat = take(B * 4);
+        L.pbar = take(B * M * 2 * 8);
     }
     L.total = off == 0 ? ALIGN : off;
     return L;
@@ -253,6 +255,7 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.persistent_blocks = 0;
     cfg.ordered = s.mode == 2 ? 1 : 0;
     cfg.occupancy = s.occupancy;
+    cfg.grad_rk4_tangent = s.grad_rk4_tangent;
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -430,6 +433,7 @@ scp_status scp_batch_grad(scp_batch h, const scp_problem *prob, const scp_lastit
     G.dwhat = h->ws + h->L.dwhat;
     G.tape = h->ws + h->L.tape;
     G.gstat = reinterpret_cast<int32_t *>(h->ws + h->L.gstat);
+    G.pbar = reinterpret_cast<double *>(h->ws + h->L.pbar);
     const scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
     const scp::Record Rc{last->xbar, last->ubar, last->mup, last->mum, last->phi, last->th,
                          last->sigma};

@@ -8,23 +8,24 @@
 // recorded warm start with the recorded step sizes, and the reference update.  The paper
 // does not differentiate its solver; this is an extension.
 //
-//   tangent_kernel  one lane per (instance, interval, column of [A | B- | B+]): the RK4 of the
-//                   discretization run on two-direction dual numbers, giving the derivative of
-//                   the scaled blocks and of the scaled defect with respect to alpha_mdot and
-//                   T_max (the only entries of theta the discretization sees; x0 and m_wet
-//                   enter through the initial boundary value alone).
 //   grad_kernel     one workgroup per instance, one 16-lane row per node: the PIPG steps
 //                   forward with a checkpoint every `ckpt` steps, then the reverse (adjoint)
 //                   sweep segment by segment, each segment recomputed from its checkpoint.
 //                   The adjoint accumulates the derivative of the output with respect to
-//                   the scaled blocks, the defect and the initial boundary value; the
-//                   first two are contracted with the tangents at the end.
+//                   the scaled blocks, the defect and the initial boundary value.
+//   rk4_adjoint_kernel  one 32-lane group per (instance, interval): the reverse sweep through
+//                   the RK4 discretization that carries the block and defect adjoints back to
+//                   alpha_mdot and T_max (the only entries of theta the discretization sees;
+//                   x0 and m_wet enter through the initial boundary value alone).
+//   tangent_kernel  alternative to the reverse sweep (settings.grad_rk4_tangent): the RK4 run
+//                   on two-direction dual numbers gives the tangents of the blocks and defect
+//                   along (alpha_mdot, T_max), contracted with the adjoints in grad_kernel.
 // Every projection is differentiated on the branch the forward evaluation takes; a kink is
 // given the derivative of that branch (the derivative of max(0, .) at 0 is that of the
 // clamped side).
 #include <math.h>
 
-#include "dual2.hpp"
+#include "dual.hpp"
 #include "lander_model.hpp"
 #include "scp_common.hpp"
 #include "scp_kernels.hpp"
@@ -67,6 +68,8 @@ struct GradArgs {
     R *dblk, *dwhat;
     R *tape;
     int32_t *gstat;
+    int rk4_reverse;  // 1: the grad kernel leaves the block adjoints for the RK4 reverse sweep
+    double *pbar;     // [B][kmax-1][2] derivative with respect to (alpha_mdot, T_max) per interval
 };
 
 __global__ void grad_status_kernel(const int32_t *K, int B, int kmax, int32_t *gstat)
@@ -77,13 +80,38 @@ __global__ void grad_status_kernel(const int32_t *K, int B, int kmax, int32_t *g
     gstat[b] = (k >= 2 && k <= kmax) ? -1 : 3;
 }
 
+// Vehicle data on dual numbers; with `params` the tangents 0 and 1 are seeded on alpha_mdot
+// and T_max.
+template <int N>
+__device__ __forceinline__ Vehicle<Dual<double, N>> lift_vehicle(const Vehicle<double> &W,
+                                                                 bool params)
+{
+    using D = Dual<double, N>;
+    Vehicle<D> V;
+    V.m_dry = D(W.m_dry);
+    V.alpha = params ? seed<double, N>(W.alpha, 0, 1.0) : D(W.alpha);
+    for (int q = 0; q < 3; ++q) {
+        V.g[q] = D(W.g[q]);
+        V.Jinv[q] = D(W.Jinv[q]);
+        V.J[q] = D(W.J[q]);
+        V.rT[q] = D(W.rT[q]);
+    }
+    V.T_min = D(W.T_min);
+    V.T_max = params ? seed<double, N>(W.T_max, N > 1 ? 1 : 0, 1.0) : D(W.T_max);
+    V.sec_delta = D(W.sec_delta);
+    V.tan_gamma = D(W.tan_gamma);
+    V.tilt_c = D(W.tilt_c);
+    V.w_max2 = D(W.w_max2);
+    return V;
+}
+
 // ------------------------------------------------------------------------------------------
 // Tangents of the discretization with respect to (alpha_mdot, T_max), in double.
 // ------------------------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
 {
-    using D = Dual2<double>;
+    using D = Dual<double, 2>;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long per_b = (long)(a.kmax - 1) * COLS;
     const int b = (int)(gid / per_b);
@@ -96,21 +124,7 @@ __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
     double pd[NP];
     for (int q = 0; q < NP; ++q) pd[q] = double(a.params[(long)b * NP + q]);
     const Vehicle<double> W = load_vehicle<double>(pd);
-    Vehicle<D> V;
-    V.m_dry = D(W.m_dry);
-    V.alpha = D(W.alpha, 1.0, 0.0);
-    for (int q = 0; q < 3; ++q) {
-        V.g[q] = D(W.g[q]);
-        V.Jinv[q] = D(W.Jinv[q]);
-        V.J[q] = D(W.J[q]);
-        V.rT[q] = D(W.rT[q]);
-    }
-    V.T_min = D(W.T_min);
-    V.T_max = D(W.T_max, 0.0, 1.0);
-    V.sec_delta = D(W.sec_delta);
-    V.tan_gamma = D(W.tan_gamma);
-    V.tilt_c = D(W.tilt_c);
-    V.w_max2 = D(W.w_max2);
+    const Vehicle<D> V = lift_vehicle<2>(W, true);
 
     const R *xk = a.xbar + ((long)b * a.kmax + k) * NX;
     const R *uk = a.ubar + ((long)b * a.kmax + k) * NU;
@@ -171,19 +185,263 @@ __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
     R *d0 = a.dblk + (ib * 2) * BLK + c * CST;
     R *d1 = d0 + BLK;
     for (int i = 0; i < NX; ++i) {
-        d0[i] = R(col[i].d0 * pc / a.px[i]);
-        d1[i] = R(col[i].d1 * pc / a.px[i]);
+        d0[i] = R(col[i].d[0] * pc / a.px[i]);
+        d1[i] = R(col[i].d[1] * pc / a.px[i]);
     }
     d0[NX] = d1[NX] = R(0);
     if (c == 0) {
         R *w0 = a.dwhat + (ib * 2) * DST;
         R *w1 = w0 + DST;
         for (int i = 0; i < NX; ++i) {
-            w0[i] = R(x[i].d0 / a.px[i]);
-            w1[i] = R(x[i].d1 / a.px[i]);
+            w0[i] = R(x[i].d[0] / a.px[i]);
+            w1[i] = R(x[i].d[1] / a.px[i]);
         }
         w0[NX] = w1[NX] = R(0);
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Reverse (adjoint) sweep through the RK4 discretization, in double.
+//
+// One 32-lane group per (instance, interval); lane c < 23 owns column c of the variational
+// system [A | B- | B+] (lanes 23..31 carry zero adjoints), and every lane carries the shared
+// state x.  The cotangents entering at the end of the interval are the grad kernel's
+// derivatives of the output with respect to the scaled column c and the scaled defect.  The
+// sweep runs the RK4 substeps and their four stages backwards.  At a stage with input (X, P)
+// the local vector-Jacobian products are
+//     X^bar = J(X)^T K^bar + sum over columns c of (d/dX <L^bar_c, Df(X)[P_c, du_c]>)
+//     P^bar_c = J(X)^T L^bar_c
+// where K = f(X) and L_c = Df(X)[P_c, du_c] are the stage slopes of the state and of column c.
+// The products with the state Jacobian and with the second derivative are both taken from
+// evaluations of the model on one-direction dual numbers along e_i, i = 0..14 (the value part
+// of the slope then carries J e_i and the column slope carries the second derivative along
+// e_i); the column sum is a 32-lane reduction.  The parameter derivative accumulates
+// <K^bar, df/dp> (state part, counted once) + <L^bar_c, d(Df[P_c])/dp> along the way.
+// Substep starts and stage inputs are recomputed from the interval start.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double group_sum32(double v)
+{
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+    return v;
+}
+
+// FOH control and the control part of the column direction at stage time sg.
+__device__ __forceinline__ void stage_controls(const double *ua, const double *ub, double sg,
+                                               double dtau, int uj, bool plus, double *u,
+                                               double *du)
+{
+    const double lp = sg / dtau, lm = 1.0 - lp;
+    for (int i = 0; i < NU; ++i) {
+        u[i] = lm * ua[i] + lp * ub[i];
+        du[i] = i == uj ? (plus ? lp : lm) : 0.0;
+    }
+}
+
+// Slopes (f, Df[col, du]) of the state and of one column.
+__device__ __forceinline__ void slopes(const Vehicle<double> &V, const double *x,
+                                       const double *col, const double *u, const double *du,
+                                       double *fx, double *fc)
+{
+    double fy;
+    f_jvp<double, true>(V, x, u, col, du, fx, fy, fc);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) rk4_adjoint_kernel(GradArgs<R> a)
+{
+    using D1 = Dual<double, 1>;
+    using D2 = Dual<double, 2>;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per_b = (long)(a.kmax - 1) * 32;
+    const int b = (int)(gid / per_b);
+    const int rem = (int)(gid % per_b), k = rem >> 5, c = rem & 31;
+    // whole 32-lane groups leave together (b, k are uniform over a group)
+    if (b >= a.B) return;
+    if (a.gstat[b] >= 0) return;
+    const int K = a.K[b];
+    if (k >= K - 1) return;
+    const bool col_lane = c < COLS;
+    const int cc = col_lane ? c : 0;
+
+    double pd[NP];
+    for (int q = 0; q < NP; ++q) pd[q] = double(a.params[(long)b * NP + q]);
+    const Vehicle<double> V = load_vehicle<double>(pd);
+    const Vehicle<D1> V1 = lift_vehicle<1>(V, false);
+    const Vehicle<D2> V2 = lift_vehicle<2>(V, true);
+
+    const R *xk = a.xbar + ((long)b * a.kmax + k) * NX;
+    const R *uk = a.ubar + ((long)b * a.kmax + k) * NU;
+    double x0[NX], ua[NU], ub[NU];
+    for (int i = 0; i < NX; ++i) x0[i] = double(xk[i]);
+    for (int i = 0; i < NU; ++i) {
+        ua[i] = double(uk[i]);
+        ub[i] = double(uk[NU + i]);
+    }
+    const int uj = cc < NX ? -1 : (cc - NX) % NU;
+    const bool plus = cc >= NX + NU;
+    const double dtau = 1.0 / double(K - 1);
+    const int nsub = a.rk4_substeps;
+    const double h = dtau / nsub, hh = 0.5 * h;
+
+    // cotangents at the end of the interval: scaled quantities back to original units
+    const long ib = (long)b * (a.kmax - 1) + k;
+    const double pc = cc < NX ? a.px[cc] : a.pu[(cc - NX) % NU];
+    double xb[NX], cb[NX];
+    for (int i = 0; i < NX; ++i) {
+        xb[i] = double(a.dwhat[ib * 2 * DST + i]) / a.px[i];
+        cb[i] = col_lane ? double(a.dblk[ib * 2 * BLK + cc * CST + i]) * pc / a.px[i] : 0.0;
+    }
+    double pb0 = 0.0, pb1 = 0.0;
+
+    double xs[NX], cs[NX], X[NX], P[NX], fx[NX], fc[NX], u[NU], du[NU];
+    for (int n = nsub - 1; n >= 0; --n) {
+        // state and column at the start of substep n
+        for (int i = 0; i < NX; ++i) {
+            xs[i] = x0[i];
+            cs[i] = (col_lane && cc < NX && i == cc) ? 1.0 : 0.0;
+        }
+        for (int m = 0; m < n; ++m) {
+            double ax[NX], ac[NX];
+            for (int st = 0; st < 4; ++st) {
+                const double sg = m * h + (st == 0 ? 0.0 : (st == 3 ? h : hh));
+                stage_controls(ua, ub, sg, dtau, uj, plus, u, du);
+                if (st == 0)
+                    for (int i = 0; i < NX; ++i) {
+                        X[i] = xs[i];
+                        P[i] = cs[i];
+                    }
+                slopes(V, X, P, u, du, fx, fc);
+                const double w = (st == 0 || st == 3) ? 1.0 : 2.0;
+                for (int i = 0; i < NX; ++i) {
+                    ax[i] = st == 0 ? fx[i] : ax[i] + w * fx[i];
+                    ac[i] = st == 0 ? fc[i] : ac[i] + w * fc[i];
+                }
+                if (st < 3) {
+                    const double hs = st == 2 ? h : hh;
+                    for (int i = 0; i < NX; ++i) {
+                        X[i] = xs[i] + hs * fx[i];
+                        P[i] = cs[i] + hs * fc[i];
+                    }
+                }
+            }
+            for (int i = 0; i < NX; ++i) {
+                xs[i] += h / 6.0 * ax[i];
+                cs[i] += h / 6.0 * ac[i];
+            }
+        }
+        // stages of substep n, backwards
+        double xa[NX], ca[NX], kx[NX], kc[NX];
+        for (int i = 0; i < NX; ++i) {
+            xa[i] = xb[i];
+            ca[i] = cb[i];
+            kx[i] = kc[i] = 0.0;
+        }
+        for (int st = 3; st >= 0; --st) {
+            // stage input (X, P): the stages before st, from the substep start
+            for (int i = 0; i < NX; ++i) {
+                X[i] = xs[i];
+                P[i] = cs[i];
+            }
+            for (int r = 0; r < st; ++r) {
+                const double sg = n * h + (r == 0 ? 0.0 : hh);
+                stage_controls(ua, ub, sg, dtau, uj, plus, u, du);
+                slopes(V, X, P, u, du, fx, fc);
+                const double hs = r == 2 ? h : hh;
+                for (int i = 0; i < NX; ++i) {
+                    X[i] = xs[i] + hs * fx[i];
+                    P[i] = cs[i] + hs * fc[i];
+                }
+            }
+            const double sg = n * h + (st == 0 ? 0.0 : (st == 3 ? h : hh));
+            stage_controls(ua, ub, sg, dtau, uj, plus, u, du);
+            const double w = (st == 0 || st == 3) ? h / 6.0 : h / 3.0;
+            double Kb[NX], Lb[NX];
+            for (int i = 0; i < NX; ++i) {
+                Kb[i] = w * xb[i] + kx[i];
+                Lb[i] = w * cb[i] + kc[i];
+            }
+            // local products along e_i
+            double Xb[NX], Pb[NX];
+            D1 Xd[NX], Pd[NX], ud[NU], dud[NU], fd[NX], gd[NX];
+            for (int i = 0; i < NU; ++i) {
+                ud[i] = D1(u[i]);
+                dud[i] = D1(du[i]);
+            }
+            for (int i = 0; i < NX; ++i) Pd[i] = D1(P[i]);
+            for (int e = 0; e < NX; ++e) {
+                for (int i = 0; i < NX; ++i) Xd[i] = seed<double, 1>(X[i], 0, i == e ? 1.0 : 0.0);
+                double fy;
+                f_jvp<D1, true>(V1, Xd, ud, Pd, dud, fd, fy, gd);
+                double jk = 0.0, jl = 0.0, hl = 0.0;
+                for (int r = 0; r < NX; ++r) {
+                    jk += Kb[r] * fd[r].d[0];
+                    jl += Lb[r] * fd[r].d[0];
+                    hl += Lb[r] * gd[r].d[0];
+                }
+                Xb[e] = jk + group_sum32(hl);
+                Pb[e] = jl;
+            }
+            // parameter derivatives at this stage
+            {
+                D2 Xp[NX], Pp[NX], up[NU], dup[NU], fp[NX], gp[NX];
+                for (int i = 0; i < NX; ++i) {
+                    Xp[i] = D2(X[i]);
+                    Pp[i] = D2(P[i]);
+                }
+                for (int i = 0; i < NU; ++i) {
+                    up[i] = D2(u[i]);
+                    dup[i] = D2(du[i]);
+                }
+                double fy;
+                f_jvp<D2, true>(V2, Xp, up, Pp, dup, fp, fy, gp);
+                for (int r = 0; r < NX; ++r) {
+                    if (c == 0) {
+                        pb0 += Kb[r] * fp[r].d[0];
+                        pb1 += Kb[r] * fp[r].d[1];
+                    }
+                    pb0 += Lb[r] * gp[r].d[0];
+                    pb1 += Lb[r] * gp[r].d[1];
+                }
+            }
+            for (int i = 0; i < NX; ++i) {
+                xa[i] += Xb[i];
+                ca[i] += Pb[i];
+            }
+            // this stage's input was substep start + coefficient * previous slope
+            const double cf = st == 3 ? h : hh;
+            for (int i = 0; i < NX; ++i) {
+                kx[i] = st > 0 ? cf * Xb[i] : 0.0;
+                kc[i] = st > 0 ? cf * Pb[i] : 0.0;
+            }
+        }
+        for (int i = 0; i < NX; ++i) {
+            xb[i] = xa[i];
+            cb[i] = col_lane ? ca[i] : 0.0;
+        }
+    }
+    pb0 = group_sum32(pb0);
+    pb1 = group_sum32(pb1);
+    if (c == 0) {
+        a.pbar[ib * 2] = pb0;
+        a.pbar[ib * 2 + 1] = pb1;
+    }
+}
+
+// Adds the discretization part of d/d(alpha_mdot, T_max), summed over intervals in order.
+template <typename R>
+__global__ void grad_finalize_kernel(GradArgs<R> a)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B || a.gstat[b] >= 0) return;
+    const int M = a.K[b] - 1;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < M; ++k) {
+        s0 += a.pbar[((long)b * (a.kmax - 1) + k) * 2];
+        s1 += a.pbar[((long)b * (a.kmax - 1) + k) * 2 + 1];
+    }
+    R *g = a.grad + (long)b * 18;
+    g[16] = R(double(g[16]) + s0);
+    g[17] = R(double(g[17]) + s1);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -722,9 +980,20 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
         }
     }
 
-    // -------------------- contraction with the discretization tangents --------------------
+    // -------------------- the discretization's share --------------------
+    // reverse mode: hand the block and defect adjoints (scaled) to the RK4 reverse sweep,
+    // stored where the tangents would be; tangent mode: contract with the tangents here
     double part[3] = {0.0, 0.0, 0.0};
-    if (dual) {
+    if (a.rk4_reverse && dual) {
+        R *ab = a.dblk + (ib * 2) * BLK;
+        for (int q = 0; q < NX; ++q) ab[q * CST + i] = accA[q];
+        for (int q = 0; q < NU; ++q) {
+            ab[(NX + q) * CST + i] = accBm[q];
+            ab[(NX + NU + q) * CST + i] = accBp[q];
+        }
+        a.dwhat[(ib * 2) * DST + i] = accW;
+    }
+    if (!a.rk4_reverse && dual) {
         const R *d0 = a.dblk + (ib * 2) * BLK;
         const R *d1 = d0 + BLK;
         const R *w0 = a.dwhat + (ib * 2) * DST;
@@ -796,6 +1065,8 @@ static hipError_t launch_grad_typed(const Config &cfg, int nsteps, int ckpt, con
     a.dwhat = static_cast<R *>(gw.dwhat);
     a.tape = static_cast<R *>(gw.tape);
     a.gstat = gw.gstat;
+    a.rk4_reverse = cfg.grad_rk4_tangent ? 0 : 1;
+    a.pbar = gw.pbar;
     if (cfg.B == 0) return hipSuccess;
 
     hipError_t e;
@@ -805,15 +1076,24 @@ static hipError_t launch_grad_typed(const Config &cfg, int nsteps, int ckpt, con
     if ((e = launch_discretize_at(cfg, rec.xbar, rec.ubar, prob, gw.gstat, ws, stream)) !=
         hipSuccess)
         return e;
-    const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
-    tangent_kernel<R><<<dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, stream>>>(a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!a.rk4_reverse) {
+        const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
+        tangent_kernel<R><<<dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, stream>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int threads = qp_block_threads(cfg.kmax);
     const size_t smem = grad_smem_bytes_r(cfg.kmax, sizeof(R));
     if (threads <= 640)
         grad_kernel<R, 640><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
     else
         grad_kernel<R, 1024><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.rk4_reverse) {
+        const long nl = (long)cfg.B * (cfg.kmax - 1) * 32;
+        rk4_adjoint_kernel<R><<<dim3((unsigned)((nl + 63) / 64)), dim3(64), 0, stream>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        grad_finalize_kernel<R><<<dim3((unsigned)((cfg.B + 255) / 256)), dim3(256), 0, stream>>>(a);
+    }
     return hipGetLastError();
 }
 

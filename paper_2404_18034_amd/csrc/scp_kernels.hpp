@@ -31,6 +31,7 @@ struct Config {
     int persistent_blocks;  // 0: one workgroup per instance; > 0: persistent grid size
     int ordered;            // 1: workgroups take instances by node count, descending
     int occupancy;          // 4: subproblem variant limited to four waves per SIMD
+    int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
@@ -59,10 +60,12 @@ struct Record {
 
 // Device scratch of the gradient (carved by the host when gradients are enabled).
 struct GradWorkspace {
-    void *dblk;      // R [B][kmax-1][2][23][16]  d(scaled blocks)/d(alpha_mdot, T_max)
-    void *dwhat;     // R [B][kmax-1][2][16]      d(scaled defect)/d(alpha_mdot, T_max)
+    void *dblk;      // R [B][kmax-1][2][23][16]  tangents of the scaled blocks along
+                     //   (alpha_mdot, T_max), or (first half) the adjoint of the blocks
+    void *dwhat;     // R [B][kmax-1][2][16]      likewise for the scaled defect
     void *tape;      // R [B][n_ckpt + ckpt][grad_state_len(kmax)]  checkpoints and segment
     int32_t *gstat;  // i32 [B] -1 for a valid instance, 3 otherwise
+    double *pbar;    // f64 [B][kmax-1][2] RK4 share of d/d(alpha_mdot, T_max) per interval
 };
 
 // Optional per-launch timing: when `events` is non-null, launch i is bracketed by

@@ -193,3 +193,18 @@ def test_grad_invalid_instances_and_state_errors():
         s2.grad_into(prob, last, cot, g)
     assert "STATE" in str(e.value)
     s2.close()
+
+
+def test_rk4_reverse_sweep_matches_forward_tangents():
+    # the two ways of differentiating the discretization give the same gradient
+    import torch
+    cfg = I.solver_settings("C3", scp_iters_max=4, pipg_iters_max=300)
+    inst = I.make_instances("C3", B=6)
+    inst["params"][:, 13] = 2.3   # thrust bound active: T_max reaches the CTCS integrand
+    ids = list(range(6))
+    lasts = _oracle_last(cfg, inst, ids)
+    J_rev, _ = _gpu_jac(dict(cfg, grad_rk4_tangent=0), inst, ids, lasts, "f64")
+    J_tan, _ = _gpu_jac(dict(cfg, grad_rk4_tangent=1), inst, ids, lasts, "f64")
+    print("reverse vs tangent: max rel diff %.3e" % _rel_err(J_rev, J_tan).max())
+    assert _rel_err(J_rev, J_tan).max() <= 1e-10
+    assert np.any(np.abs(J_rev[:, :, 17]) > 0)
