@@ -532,28 +532,25 @@ __device__ __forceinline__ void xproj_fwd(const NodeSets<R> &S, const R *xp, con
     for (int q = 0; q < NX; ++q) xo[q] = xb[q] + px[q] * xp[q];
     if (S.mask & 1)
         if (!fixed[0] && xo[0] < S.mdry) xh[0] = (S.mdry - xb[0]) / px[0];
+    // a group member that is a fixed boundary value keeps that value (the projection acts on
+    // the pre-boundary values, then the boundary values overwrite, as in the solve)
     if (S.mask & 2) {
-        R t = xo[1], z0 = xo[2], z1 = xo[3];
-        soc2_fwd<R>(t, z0, z1, S.glide_a);
-        if (!fixed[1]) {
-            xh[1] = (t - xb[1]) / px[1];
-            xh[2] = (z0 - xb[2]) / px[2];
-            xh[3] = (z1 - xb[3]) / px[3];
-        }
+        R z[3] = {xo[1], xo[2], xo[3]};
+        soc2_fwd<R>(z[0], z[1], z[2], S.glide_a);
+        for (int q = 0; q < 3; ++q)
+            if (!fixed[1 + q]) xh[1 + q] = (z[q] - xb[1 + q]) / px[1 + q];
     }
     if (S.mask & 4) {
         R z[2] = {xo[9], xo[10]};
         ball_fwd<R, 2>(z, S.tilt_rad);
-        if (!fixed[9]) {
-            xh[9] = (z[0] - xb[9]) / px[9];
-            xh[10] = (z[1] - xb[10]) / px[10];
-        }
+        for (int q = 0; q < 2; ++q)
+            if (!fixed[9 + q]) xh[9 + q] = (z[q] - xb[9 + q]) / px[9 + q];
     }
     if (S.mask & 8) {
         R z[3] = {xo[11], xo[12], xo[13]};
         ball_fwd<R, 3>(z, S.w_max);
-        if (!fixed[11])
-            for (int q = 0; q < 3; ++q) xh[11 + q] = (z[q] - xb[11 + q]) / px[11 + q];
+        for (int q = 0; q < 3; ++q)
+            if (!fixed[11 + q]) xh[11 + q] = (z[q] - xb[11 + q]) / px[11 + q];
     }
 }
 

@@ -127,7 +127,7 @@ def test_grad_fp32_64_instances_matches_oracle_fd():
     # PIPG steps with checkpoints every 20) on instances 0..63
     cfg = I.solver_settings("C3")
     inst = I.make_instances("C3", B=64)
-    _run(cfg, inst, list(range(64)), "f32", 1e-3, 1e-5)
+    _run(cfg, inst, list(range(64)), "f32", 1e-3, 1e-4)
 
 
 def test_record_matches_oracle_last_iteration():
