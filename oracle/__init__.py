@@ -8,6 +8,11 @@ fast-math and without FMA contraction, into ``_scp_oracle.so`` next to it.
 
 Layouts (row-major float64 numpy arrays):
   x0[B,15], xf[B,13], params[B,22], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
+
+``solve_f32`` runs the same C source compiled with float in place of double
+(``_scp_oracle_f32.so``): a single-precision evaluation of the same algorithm.  Tests use it
+only to measure how far FP32 rounding alone moves an instance's result (its FP32
+conditioning); it is never an expected value.
 """
 import ctypes
 import os
@@ -19,19 +24,33 @@ NX, NU, NP, NXF = 15, 4, 22, 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scp_oracle.c")
 _SO = os.path.join(_HERE, "_scp_oracle.so")
+_SO32 = os.path.join(_HERE, "_scp_oracle_f32.so")
 
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
           "-D_POSIX_C_SOURCE=200809L", "-pthread"]
 
 
 def build(force=False):
-    """Compile the oracle with gcc (idempotent unless ``force``)."""
-    if (not force and os.path.exists(_SO)
-            and os.path.getmtime(_SO) >= os.path.getmtime(_SRC)):
+    """Compile the oracle with gcc (idempotent unless ``force``), and its single-precision
+    twin (every ``double`` of the source read as ``float``)."""
+    import re
+    import tempfile
+    if (not force and os.path.exists(_SO) and os.path.exists(_SO32)
+            and os.path.getmtime(_SO) >= os.path.getmtime(_SRC)
+            and os.path.getmtime(_SO32) >= os.path.getmtime(_SRC)):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _SO)
+    with tempfile.TemporaryDirectory() as d:
+        src32 = os.path.join(d, "scp_oracle_f32.c")
+        with open(_SRC) as f:
+            text = f.read()
+        with open(src32, "w") as f:
+            f.write(re.sub(r"\bdouble\b", "float", text))
+        tmp = _SO32 + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src32, "-lm"])
+        os.replace(tmp, _SO32)
     return _SO
 
 
@@ -51,9 +70,15 @@ class Settings(ctypes.Structure):
     ]
 
 
-def make_settings(cfg):
+class Settings32(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float if t is ctypes.c_double else
+                 (ctypes.c_float * NX if n == "px" else ctypes.c_float * NU if n == "pu" else t))
+                for n, t in Settings._fields_]
+
+
+def make_settings(cfg, cls=None):
     """Build the oracle's settings struct from a plain dict of solver settings."""
-    s = Settings()
+    s = (cls or Settings)()
     for name, _ in Settings._fields_:
         if name in ("px", "pu", "pad"):
             continue
@@ -245,6 +270,37 @@ def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
     if rc != 0:
         raise ValueError("oracle: invalid node count")
     return out
+
+
+_lib32 = None
+
+
+def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None):
+    """The same solve evaluated in single precision (see the module note); float64 results."""
+    global _lib32
+    if _lib32 is None:
+        build()
+        _lib32 = ctypes.CDLL(_SO32)
+    st = make_settings(cfg, Settings32)
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    x0, xf, params = f(x0), f(xf), f(params)
+    K = np.ascontiguousarray(K, dtype=np.int32)
+    B = x0.shape[0]
+    kmax = int(K.max()) if kmax is None else int(kmax)
+    nthreads = os.cpu_count() if nthreads is None else int(nthreads)
+    out = dict(x=np.zeros((B, kmax, NX), np.float32), u=np.zeros((B, kmax, NU), np.float32),
+               t_f=np.zeros(B, np.float32), m_f=np.zeros(B, np.float32),
+               status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
+               pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B, np.float32),
+               ctcs_viol=np.zeros(B, np.float32), objective=np.zeros(B, np.float32))
+    v = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = _lib32.orc_solve_batch(
+        ctypes.byref(st), B, kmax, v(x0), v(xf), v(params), v(K), nthreads, v(out["x"]),
+        v(out["u"]), v(out["t_f"]), v(out["m_f"]), v(out["status"]), v(out["scp_iters"]),
+        v(out["pipg_iters"]), v(out["defect_inf"]), v(out["ctcs_viol"]), v(out["objective"]))
+    if rc != 0:
+        raise ValueError("oracle: invalid node count")
+    return {k: (a.astype(np.float64) if a.dtype == np.float32 else a) for k, a in out.items()}
 
 
 def solve_trace(cfg, x0, xf, p, K, trace_n=64):

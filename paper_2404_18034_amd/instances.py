@@ -77,7 +77,7 @@ def nominal_params():
 HYPER = dict(
     pipg_check_every=10, rk4_substeps=5, power_iters_max=50, node_projections=31, pad=0,
     scp_tol=1e-4, feas_tol=1e-4, pipg_eps_abs=1e-5, pipg_eps_rel=1e-5,
-    power_eps_abs=0.0, power_eps_rel=1e-6, power_buff=0.05,
+    power_eps_abs=0.0, power_eps_rel=1e-6, power_buff=0.1,
     w_cost=0.005, w_prox=0.3, w_ep=100.0, omega=16.0, rho=1.9,
     px=(1.0, 4.0, 4.0, 4.0, 2.0, 2.0, 2.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0.1),
     pu=(5.0, 5.0, 5.0, 5.0),

@@ -34,6 +34,39 @@ def well_conditioned(cfg, inst, o, rel, kmax=None):
     return (amp <= AMP_MAX) & (o2["status"] == o["status"]) & (o2["scp_iters"] == o["scp_iters"])
 
 
+def fp32_deviation(cfg, inst, o, kmax=None):
+    """How far FP32 rounding alone moves each instance: the oracle's algorithm evaluated in
+    single precision against the FP64 oracle (scaled-absolute on x).  Oracle-only."""
+    f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=kmax)
+    px = np.array(cfg["px"])
+    with np.errstate(invalid="ignore"):
+        return np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2))
+
+
+def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
+    """FP32 GPU vs FP64 oracle.  Where a single-precision run of the oracle's own algorithm
+    stays within TOL_F32 / 10 of the FP64 result, the GPU must match to TOL_F32; elsewhere FP32
+    rounding by itself moves the result (the node-wise thrust projection makes some instances
+    sensitive), and the GPU error must stay within 20x of that plain-FP32 deviation.  Status
+    and iteration counts must agree."""
+    dev = fp32_deviation(cfg, inst, o, kmax)
+    fin = o["status"] != 2
+    ok = fin & (dev <= TOL_F32 / 10)
+    errs = _errors(cfg, g, o)
+    _report("%s (FP32-conditioned %d/%d)" % (tag, ok.sum(), ok.size), [e[ok] for e in errs])
+    for e in errs:
+        assert e[ok].max() <= TOL_F32
+    rest = fin & ~ok
+    if rest.any():
+        ratio = errs[0][rest] / np.maximum(dev[rest], TOL_F32)
+        print("%s: %d FP32-sensitive instances, GPU error / plain-FP32 deviation max %.2f"
+              % (tag, rest.sum(), ratio.max()))
+        assert ratio.max() <= 20.0
+    np.testing.assert_array_equal(g["status"][ok], o["status"][ok])
+    np.testing.assert_array_equal(g["scp_iters"], o["scp_iters"])
+    return ok
+
+
 def _valid(g, inst):
     assert np.all(np.isin(g["status"], [0, 1]))
     assert np.all(np.isfinite(g["x"])) and np.all(np.isfinite(g["u"]))
@@ -143,18 +176,15 @@ def test_few_iterations_fp32_tight():
         assert e.max() <= 2e-5
 
 
-def test_c4_sample_fp32_matches_oracle():
+@pytest.mark.parametrize("proj", [0, 31])
+def test_c4_sample_fp32_matches_oracle(proj):
     # K = 30 with dispersed inertia and thrust lever arm
-    cfg = I.solver_settings("C4")
-    inst = I.make_instances("C4", ids=np.arange(8) * 256)
+    cfg = I.solver_settings("C4", node_projections=proj)
+    inst = I.make_instances("C4", ids=np.arange(16) * 256)
     g = _gpu(cfg, inst, "f32")
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
-    ok = well_conditioned(cfg, inst, o, 1e-7)
-    errs = _errors(cfg, g, o)
-    _report("C4 fp32 sample (well-conditioned %d/8)" % ok.sum(), [e[ok] for e in errs])
-    assert ok.sum() >= 6
-    for e in errs:
-        assert e[ok].max() <= TOL_F32
+    ok = check_fp32_against_oracle(cfg, inst, g, o, "C4 fp32 proj=%d" % proj)
+    assert ok.sum() >= (12 if proj == 0 else 4)
     _valid(g, inst)
 
 

