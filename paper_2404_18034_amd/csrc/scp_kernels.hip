@@ -619,42 +619,49 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const int pmask = a.node_projections;
     // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
     // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
-    // Lanes 4-6 (velocity, never in a state set) carry the thrust set, group 5, so that the
-    // state sets and the thrust set are projected by one evaluation across the row.
-    int grp = 0, gw = 0, gb = 0;
+    // Each set is projected once, by its leader lane: glide slope by lane 1 (r), tilt by lane
+    // 9 (q2, q3), rate by lane 11 (w), and thrust by lane 4 (a velocity lane, in no state
+    // set); the leader receives the other members from lanes +1, +2 (thrust: from the control
+    // lanes 0, 4, 8) and the members read their component back.  Members that are fixed
+    // boundary values keep them.
+    int grp = 0, gw = 0;  // member group of this lane (1 mass, 2 glide, 3 tilt, 4 rate), slot
     if (isx && !fixed) {
         if (i == 0) grp = (pmask & 1) ? 1 : 0;
-        else if (i <= 3) { grp = (pmask & 2) ? 2 : 0; gb = 1; }
-        else if (i == 9 || i == 10) { grp = (pmask & 4) ? 3 : 0; gb = 9; }
-        else if (i >= 11 && i <= 13) { grp = (pmask & 8) ? 4 : 0; gb = 11; }
-        gw = i - gb;
+        else if (i <= 3) { grp = (pmask & 2) ? 2 : 0; gw = i - 1; }
+        else if (i == 9 || i == 10) { grp = (pmask & 4) ? 3 : 0; gw = i - 9; }
+        else if (i >= 11 && i <= 13) { grp = (pmask & 8) ? 4 : 0; gw = i - 11; }
     }
-    if (node && i >= 4 && i <= 6 && (pmask & 16)) grp = 5;
+    const int role = (i == 1 && (pmask & 2)) ? 2 : (i == 9 && (pmask & 4)) ? 3
+                   : (i == 11 && (pmask & 8)) ? 4 : (i == 4 && (pmask & 16)) ? 5 : 0;
     const R INF = R(INFINITY);
     const double tan_g = tan(double(p[15])), tan_d = tan(double(p[14]));
-    const R g_a = grp == 2 ? R(1.0 / tan_g) : (grp == 5 ? R(tan_d) : R(0));
-    const R g_inv = grp == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g)))
-                             : (grp == 5 ? R(1.0 / (1.0 + tan_d * tan_d)) : R(1));
-    const R g_rad = grp == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16])))))
-                             : (grp == 4 ? p[17] : (grp == 5 ? p[13] : INF));
-    const bool g_cone = grp == 2 || grp == 5;
+    const R g_a = role == 2 ? R(1.0 / tan_g) : (role == 5 ? R(tan_d) : R(0));
+    const R g_inv = role == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g)))
+                              : (role == 5 ? R(1.0 / (1.0 + tan_d * tan_d)) : R(1));
+    const R g_rad = role == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16])))))
+                              : (role == 4 ? p[17] : (role == 5 ? p[13] : INF));
+    const bool g_cone = role == 2 || role == 5;
     const R mdry = p[1];
     const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
     const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
     const R ubT0 = rowb<0>(ubq), ubT1 = rowb<4>(ubq), ubT2 = rowb<8>(ubq);  // reference thrust
-    // reference values of the group members (original units)
-    const R xbb1 = rowb<1>(xb), xbb2 = rowb<2>(xb), xbb3 = rowb<3>(xb);
-    const R xbb9 = rowb<9>(xb), xbb10 = rowb<10>(xb);
-    const R xbb11 = rowb<11>(xb), xbb12 = rowb<12>(xb), xbb13 = rowb<13>(xb);
-    const R gr0 = grp == 2 ? xbb1 : (grp == 3 ? xbb9 : xbb11);
-    const R gr1 = grp == 2 ? xbb2 : (grp == 3 ? xbb10 : xbb12);
-    const R gr2 = grp == 2 ? xbb3 : (grp == 3 ? R(0) : xbb13);
+    const bool thr = role == 5;
+    // leader inputs t_j = c_j + m_j * (member j, scaled): references and scales.  Every DPP
+    // exchange is evaluated by all lanes before any selection (a lane-dependent condition
+    // around it would mask out the lanes it reads from).
+    const R xb_p1 = dppmov<0x101>(xb), xb_p2 = dppmov<0x102>(xb);  // row_shl: lanes +1, +2
+    const R lc0 = thr ? ubT0 : xb;
+    const R lc1 = thr ? ubT1 : xb_p1;
+    const R lc2 = thr ? ubT2 : (role == 3 ? R(0) : xb_p2);
+    const R lm = thr ? pT : pxi;
+    const R lm2 = role == 3 ? R(0) : lm;
 
     int it = 1;
+    // fresh iterate of this step; waves beyond the last node keep these zeros
+    R xn = R(0), un = R(0);
+    R vx = R(0), vu = R(0);
+    R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
     for (; it <= jmax; ++it) {
-        R xn = R(0), un = R(0);
-        R vx = R(0), vu = R(0);
-        R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
         if (wact) {
         // ---- projected gradient step on the primal variables ----
         const R phm1 = sPhi[(k - 1) * DST + i];  // phi_{k-1}[i] (zero row above the first node)
@@ -674,22 +681,21 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         if (qi == 3) un = fmin(fmax(un, slo), shi);
         if (pmask) {
-            // state sets: gather the pre-projection values of this lane's group
-            const R v1 = rowb<1>(xn), v2 = rowb<2>(xn), v3 = rowb<3>(xn);
-            const R v9 = rowb<9>(xn), v10 = rowb<10>(xn);
-            const R v11 = rowb<11>(xn), v12 = rowb<12>(xn), v13 = rowb<13>(xn);
-            const bool thr = grp == 5;
-            const R u0 = rowb<0>(un), u1 = rowb<4>(un), u2 = rowb<8>(un);
-            R t0 = thr ? ubT0 + pT * u0 : gr0 + pxi * (grp == 2 ? v1 : (grp == 3 ? v9 : v11));
-            R t1 = thr ? ubT1 + pT * u1 : gr1 + pxi * (grp == 2 ? v2 : (grp == 3 ? v10 : v12));
-            R t2 = thr ? ubT2 + pT * u2
-                       : (grp == 3 ? R(0) : gr2 + pxi * (grp == 2 ? v3 : v13));
+            // leader inputs: members from lanes +1, +2 (row_shl); thrust from the control
+            // lanes 0, 4, 8 (row_shr:4, own, row_shl:4)
+            const R xn_p1 = dppmov<0x101>(xn), xn_p2 = dppmov<0x102>(xn);
+            const R un_m4 = dppmov<0x114>(un), un_p4 = dppmov<0x104>(un);
+            const R in0 = thr ? un_m4 : xn;
+            const R in1 = thr ? un : xn_p1;
+            const R in2 = thr ? un_p4 : xn_p2;
+            R t0 = lc0 + lm * in0, t1 = lc1 + lm * in1, t2 = lc2 + lm2 * in2;
             // glide-slope cone; tilt disk; rate ball; thrust: gimbal cone, then the ball
             // ||T|| <= T_max centred at its apex
             proj_cone_ball<R>(t0, t1, t2, g_cone, g_a, g_inv, g_rad);
-            const R o = gw == 0 ? t0 : (gw == 1 ? t1 : t2);
-            const R gref = gw == 0 ? gr0 : (gw == 1 ? gr1 : gr2);
-            if (grp >= 2 && grp <= 4) xn = (o - gref) * ipxi;
+            // members read their component from the leader (row_shr by their slot)
+            const R t1_m1 = dppmov<0x111>(t1), t2_m2 = dppmov<0x112>(t2);
+            const R o = gw == 0 ? t0 : (gw == 1 ? t1_m1 : t2_m2);
+            if (grp >= 2 && grp <= 4) xn = (o - xb) * ipxi;
             if (grp == 1) {
                 const R m = xb + pxi * xn;
                 xn = m < mdry ? (mdry - xb) * ipxi : xn;
