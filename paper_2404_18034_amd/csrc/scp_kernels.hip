@@ -345,11 +345,9 @@ __device__ __forceinline__ float rowdot15<float>(const float *c, float v, float 
     return acc;
 }
 
-// Square root and reciprocal for the projections: in FP32 the hardware instructions
-// (about 1 ulp) instead of the correctly rounded sequences; FP64 keeps IEEE arithmetic.
-__device__ __forceinline__ float proj_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
+// specialization below uses the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ double proj_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float proj_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double proj_rcp(double x) { return 1.0 / x; }
 
 // Node-wise convex sets, branch-free: project v = (t, z0, z1) onto the second-order cone
@@ -369,6 +367,28 @@ __device__ __forceinline__ void proj_cone_ball(R &t, R &z0, R &z1, bool cone, R 
     const R a0 = z0 * s1, a1 = z1 * s1;
     const R n = proj_sqrt(t1 * t1 + a0 * a0 + a1 * a1);
     const R bs = n > rad ? rad * proj_rcp(n) : R(1);
+    t = t1 * bs;
+    z0 = a0 * bs;
+    z1 = a1 * bs;
+}
+// FP32: one reciprocal square root per norm (v_rsq_f32) gives both the norm and its inverse,
+// and the ball test compares squares.
+template <>
+__device__ __forceinline__ void proj_cone_ball<float>(float &t, float &z0, float &z1, bool cone,
+                                                      float a, float inv1a2, float rad)
+{
+    const float s2 = z0 * z0 + z1 * z1;
+    const float rs = __builtin_amdgcn_rsqf(s2);
+    const float nz = s2 > 0.0f ? s2 * rs : 0.0f;
+    const bool inside = !cone || nz <= a * t;
+    const bool polar = a * nz <= -t;
+    const float tp = (t + a * nz) * inv1a2;
+    const float zs = s2 > 0.0f ? a * tp * rs : 0.0f;
+    const float t1 = inside ? t : (polar ? 0.0f : tp);
+    const float s1 = inside ? 1.0f : (polar ? 0.0f : zs);
+    const float a0 = z0 * s1, a1 = z1 * s1;
+    const float n2 = t1 * t1 + a0 * a0 + a1 * a1;
+    const float bs = n2 > rad * rad ? rad * __builtin_amdgcn_rsqf(n2) : 1.0f;
     t = t1 * bs;
     z0 = a0 * bs;
     z1 = a1 * bs;

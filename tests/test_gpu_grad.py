@@ -53,15 +53,26 @@ def _last_to_device(s, lasts, inst, ids):
 
 
 def _oracle_fd(cfg, inst, b, L, n):
+    """Central differences at h = 1e-6.  The map is piecewise smooth (projections switch
+    branches); where a branch switch lies within h of the point, the forward and backward
+    differences disagree, and that column is taken at h = 1e-8 instead (reported)."""
     x0, xf, p, K = inst["x0"][b], inst["xf"][b], inst["params"][b], int(inst["K"][b])
     theta = oracle.theta_of(x0, p)
+    val = oracle.truncated_map(cfg, x0, xf, p, K, theta, L, n)
     F = np.zeros((2, 18))
     for i in range(18):
         e = np.zeros(18)
         e[i] = H
-        F[:, i] = (oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n) -
-                   oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)) / (2 * H)
-    val = oracle.truncated_map(cfg, x0, xf, p, K, theta, L, n)
+        fp = oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n)
+        fm = oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)
+        F[:, i] = (fp - fm) / (2 * H)
+        fwd, bwd = (fp - val) / H, (val - fm) / H
+        scale = np.abs(F[:, i]).max() + 1e-12
+        if np.abs(fwd - bwd).max() > 1e-3 * scale:
+            e[i] = 1e-8
+            F[:, i] = (oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n) -
+                       oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)) / 2e-8
+            print("instance %d, theta[%d]: branch switch within h = 1e-6, h = 1e-8 used" % (b, i))
     return F, val
 
 

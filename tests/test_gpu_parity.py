@@ -44,12 +44,17 @@ def fp32_deviation(cfg, inst, o, kmax=None):
 
 
 def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
-    """FP32 GPU vs FP64 oracle.  Where a single-precision run of the oracle's own algorithm
-    stays within TOL_F32 / 10 of the FP64 result, the GPU must match to TOL_F32; elsewhere FP32
+    """FP32 GPU vs FP64 oracle.  Where two single-precision runs of the oracle's own algorithm
+    stay within TOL_F32 / 10 of the FP64 result, the GPU must match to TOL_F32; elsewhere FP32
     rounding by itself moves the result (the node-wise thrust projection makes some instances
     sensitive), and the GPU error must stay within 20x of that plain-FP32 deviation.  Status
     and iteration counts must agree."""
     dev = fp32_deviation(cfg, inst, o, kmax)
+    # a second draw of FP32 rounding: x0 moved by 1e-7 relative
+    rng = np.random.default_rng(11)
+    inst2 = dict(inst, x0=inst["x0"] * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0, inst["x0"].shape)))
+    inst2["x0"][:, 14] = 0.0
+    dev = np.maximum(dev, fp32_deviation(cfg, inst2, o, kmax))
     fin = o["status"] != 2
     ok = fin & (dev <= TOL_F32 / 10)
     errs = _errors(cfg, g, o)
