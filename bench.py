@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--mode", type=int, default=None,
                     help="dispatch mode (0 launches, 1 graph, 2 ordered, 3 persistent); "
                          "default: autotuned on the workload")
+    ap.add_argument("--occupancy", type=int, default=None, choices=[0, 4, 5],
+                    help="subproblem register-budget variant with --mode (default 0)")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -139,6 +141,8 @@ def main():
     cfg = I.solver_settings(wl)
     if args.mode is not None:
         cfg["mode"] = args.mode
+        if args.occupancy is not None:
+            cfg["occupancy"] = args.occupancy
     inst = I.make_instances(wl)
     B, K = cfgd["B"], max(cfgd["K"])
     solver = api.BatchSolver(cfg, dtype=args.dtype, k_max=K, max_batch=B, device=0)
@@ -167,7 +171,7 @@ def main():
 
     # per-kernel launch durations (HIP events on the library's stream), separate solves
     solver.profile(True)
-    per = {"discretize": [0.0, 0], "subproblem": [0.0, 0], "init": [0.0, 0]}
+    per = {"discretize": [0.0, 0], "prepare": [0.0, 0], "subproblem": [0.0, 0], "init": [0.0, 0]}
     nprof = max(1, min(args.steps, 5))
     for _ in range(nprof):
         solver.solve_into(prob, sol)

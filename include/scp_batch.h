@@ -86,9 +86,10 @@ typedef struct {
     int32_t grad_pipg_steps;    /* PIPG steps of the differentiated last iteration (0: the
                                    handle computes no gradients and carves no scratch)     */
     int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */
-    int32_t occupancy;          /* subproblem kernel variant: 0 = the compiler's register
-                                   budget (three waves per SIMD), 4 = limited to 128 VGPRs
-                                   for four waves per SIMD                                */
+    int32_t occupancy;          /* FP32 subproblem kernel variant: 0 = the compiler's
+                                   register budget, 4 or 5 = registers bounded for four or
+                                   five waves per SIMD (five lets four 5-wave workgroups
+                                   share a CU); FP64 always uses 0                        */
     int32_t grad_rk4_tangent;   /* how scp_batch_grad differentiates the discretization:
                                    0 = reverse (adjoint) sweep through the RK4 stages,
                                    1 = forward tangents along (alpha_mdot, T_max)          */
@@ -157,14 +158,16 @@ const char *scp_batch_create_error(void);
 /* Launch timing, for measurement tools.  With profiling enabled, every kernel launch of a
  * solve is bracketed by two HIP events recorded on the handle's stream (created here, once;
  * no device memory is allocated).  scp_batch_profile_read() waits for the last solve and
- * returns, per kernel class (0 initial guess, 1 discretization, 2 subproblem), the summed
- * launch durations in milliseconds (ms[3]) and the number of launches (launches[3]).
- * Reading without profiling enabled is SCP_ERR_STATE. */
+ * returns, per kernel class (0 initial guess, 1 discretization, 2 subproblem PIPG iteration,
+ * 3 preparation: convergence test of the reference and power iteration), the summed launch
+ * durations in milliseconds (ms[SCP_KERNEL_CLASSES]) and the number of launches
+ * (launches[SCP_KERNEL_CLASSES]).  Reading without profiling enabled is SCP_ERR_STATE. */
+#define SCP_KERNEL_CLASSES 4
 scp_status scp_batch_profile(scp_batch h, int enable);
 scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
 
-/* Autotuner.  Times the launch variants (mode, occupancy) = (1, 0), (2, 0), (3, 0), (1, 4),
- * (2, 4) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
+/* Autotuner.  Times the launch variants (mode, occupancy) = (1, 0), (2, 0), (3, 0), (1, 5),
+ * (2, 5) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
  * HIP events, solving `problem` into `solution` (whose contents are overwritten), and keeps
  * the fastest for later solves on this handle.  *variant_out receives its index and
  * ms_out[SCP_TUNE_VARIANTS] the measured milliseconds per variant (-1 where not timed).

@@ -24,7 +24,7 @@ EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
            "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
            "scp_batch_profile", "scp_batch_profile_read", "scp_batch_autotune",
            "scp_batch_mode", "scp_batch_solve_record", "scp_batch_grad", "scp_batch_destroy"]
-KERNEL_CLASSES = ("init", "discretize", "subproblem")
+KERNEL_CLASSES = ("init", "discretize", "subproblem", "prepare")  # SCP_KERNEL_CLASSES order
 
 
 class ScpError(RuntimeError):
@@ -34,7 +34,7 @@ class ScpError(RuntimeError):
 
 
 # launch variants timed by scp_batch_autotune: (dispatch mode, occupancy)
-TUNE_VARIANTS = ((1, 0), (2, 0), (3, 0), (1, 4), (2, 4))
+TUNE_VARIANTS = ((1, 0), (2, 0), (3, 0), (1, 5), (2, 5))
 
 
 class Settings(ctypes.Structure):
@@ -329,8 +329,8 @@ class BatchSolver:
 
     def profile_read(self):
         """{kernel class: (summed ms, launches)} of the last solve."""
-        ms = (ctypes.c_double * 3)()
-        n = (ctypes.c_int32 * 3)()
+        ms = (ctypes.c_double * len(KERNEL_CLASSES))()
+        n = (ctypes.c_int32 * len(KERNEL_CLASSES))()
         self._check(load().scp_batch_profile_read(self.handle, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
 

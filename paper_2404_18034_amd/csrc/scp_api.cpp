@@ -24,7 +24,7 @@ thread_local std::string g_create_error;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t blocks, what, dy, mup, mum, phi, th, step, pipg_total, queue, bucket, order;
+    size_t blocks, what, dy, mup, mum, phi, th, step, sigma, stepsz, pipg_total, queue, bucket, order;
     size_t dblk, dwhat, tape, gstat, pbar;  // gradient scratch (when grad_pipg_steps > 0)
     size_t total;
 };
@@ -42,7 +42,10 @@ bool settings_ok(const scp_settings *s, std::string &why)
     }
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
     if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
-    if (s->occupancy != 0 && s->occupancy != 4) { why = "occupancy must be 0 or 4"; return false; }
+    if (s->occupancy != 0 && s->occupancy != 4 && s->occupancy != 5) {
+        why = "occupancy must be 0, 4 or 5";
+        return false;
+    }
     if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
@@ -88,6 +91,8 @@ Layout layout_of(const scp_settings *s)
     L.phi = take(B * M * 16 * rs);
     L.th = take(B * K * rs);
     L.step = take(B * 8);
+    L.sigma = take(B * 8);
+    L.stepsz = take(B * 2 * rs);
     L.pipg_total = take(B * 4);
     L.queue = take((size_t)(s->scp_iters_max + 2) * 4);
     L.bucket = take((K + 1) * 4);
@@ -197,6 +202,15 @@ scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_
         g_create_error = std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950";
         return SCP_ERR_DEVICE;
     }
+    {
+        const size_t need = scp::qp_smem_bytes(settings->k_max, settings->dtype == SCP_F64 ? 8 : 4);
+        if (need > (size_t)prop.sharedMemPerBlock) {
+            g_create_error = "subproblem workgroup needs " + std::to_string(need) +
+                             " bytes of LDS, the device allows " +
+                             std::to_string((size_t)prop.sharedMemPerBlock);
+            return SCP_ERR_UNSUPPORTED;
+        }
+    }
     hipPointerAttribute_t attr;
     e = hipPointerGetAttributes(&attr, workspace);
     if (e != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != device) {
@@ -283,6 +297,8 @@ static scp::Workspace workspace_of(scp_batch h)
     W.phi = h->ws + h->L.phi;
     W.th = h->ws + h->L.th;
     W.step = reinterpret_cast<double *>(h->ws + h->L.step);
+    W.sigma = reinterpret_cast<double *>(h->ws + h->L.sigma);
+    W.stepsz = h->ws + h->L.stepsz;
     W.pipg_total = reinterpret_cast<int32_t *>(h->ws + h->L.pipg_total);
     W.queue = reinterpret_cast<int32_t *>(h->ws + h->L.queue);
     W.bucket = reinterpret_cast<int32_t *>(h->ws + h->L.bucket);
@@ -454,7 +470,7 @@ scp_status scp_batch_profile(scp_batch h, int enable)
         return SCP_OK;
     }
     if (h->profiling) return SCP_OK;
-    const int cap = 1 + 2 * (h->st.scp_iters_max + 1);
+    const int cap = 1 + 3 * (h->st.scp_iters_max + 1);
     h->events.assign(2 * cap, nullptr);
     h->kinds.assign(cap, -1);
     for (auto &ev : h->events) {
@@ -473,7 +489,7 @@ scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches)
 {
     if (!h || !ms || !launches) return SCP_ERR_ARG;
     h->err.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < SCP_KERNEL_CLASSES; ++k) {
         ms[k] = 0.0;
         launches[k] = 0;
     }
@@ -487,7 +503,7 @@ scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches)
         e = hipEventElapsedTime(&t, h->events[2 * i], h->events[2 * i + 1]);
         if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
         const int k = h->kinds[i];
-        if (k >= 0 && k < 3) {
+        if (k >= 0 && k < SCP_KERNEL_CLASSES) {
             ms[k] += t;
             launches[k] += 1;
         }
@@ -513,7 +529,7 @@ static std::string tune_key(scp_batch h, int batch)
 }
 
 static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2};
-static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 4, 4};
+static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 5, 5};
 
 static int cache_lookup(const char *path, const std::string &key)
 {

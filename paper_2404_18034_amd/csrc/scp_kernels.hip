@@ -42,6 +42,10 @@ struct Args {
     double *defect_inf, *ctcs_viol, *objective;
     R *blocks, *what, *mup, *mum, *phi, *th;
     double *dy, *step;
+    double *sigma;    // [B] buffered power-iteration estimate of the current subproblem
+    R *stepsz;        // [B][2] PIPG step sizes (alpha, beta) of the current subproblem
+    // PIPG weights in the working precision (kernel arguments, so scalar registers)
+    R rho_r, omr_r, wprox_r, wep_r;
     int32_t *pipg_total;
     int32_t *queue;   // [scp_iters_max + 2] work-queue heads (persistent form)
     int32_t *bucket;  // [kmax + 1] counting-sort buckets
@@ -394,6 +398,89 @@ __device__ __forceinline__ void proj_cone_ball<float>(float &t, float &z0, float
     z1 = a1 * bs;
 }
 
+// Column i of A^-_k for the transposed product.  FP32: a per-lane LDS slot of 20 floats
+// (80 bytes), read back whole before each product as four 16-byte loads (at that stride eight
+// consecutive lanes cover all 32 banks once); keeping these 15 values out of registers is what
+// lets four 5-wave workgroups share a CU.  FP64: registers.
+template <typename R> struct ColStore;
+template <>
+struct ColStore<float> {
+    static constexpr int LDS_STRIDE = 20, N = 16;
+    float *slot;
+    __device__ __forceinline__ void put(int q, float v) { slot[q] = v; }
+    __device__ __forceinline__ void get(float (&c)[N]) const
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(slot);
+        float4 *o = reinterpret_cast<float4 *>(c);
+        for (int n = 0; n < 4; ++n) o[n] = p[n];
+    }
+};
+template <>
+struct ColStore<double> {
+    static constexpr int LDS_STRIDE = 0, N = NX;
+    double *unused;
+    double c[NX];
+    __device__ __forceinline__ void put(int q, double v) { c[q] = v; }
+    __device__ __forceinline__ void get(double (&o)[N]) const
+    {
+        for (int q = 0; q < NX; ++q) o[q] = c[q];
+    }
+};
+
+// Exchange arrays of the PIPG iteration for a workgroup of at most MAXT lanes, one value per
+// lane (row stride 16), so that every access of the iteration is this lane's slot or the
+// slot one row up or down, at a compile-time offset from a single address register:
+// phi and theta (rows -1 .. ROWS-1, row -1 zero), the extrapolated primal values
+// 2x^ - x~ and 2u^ - u~ (rows 0 .. ROWS, the row after the last workgroup row zero).
+template <typename R, int MAXT>
+struct QpLds {
+    static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
+    static constexpr int PHI = 0, TH = SLOTS, VX = 2 * SLOTS, VU = 3 * SLOTS;
+    // previous fresh iterate (x^, u^, mu+, mu-, phi, theta), this lane's slot only
+    static constexpr int PX = 4 * SLOTS, PU = 5 * SLOTS, PMP = 6 * SLOTS, PMM = 7 * SLOTS,
+                         PPH = 8 * SLOTS, PTH = 9 * SLOTS;
+    static constexpr int ARRAYS = 10;
+    static constexpr size_t BYTES = (ARRAYS * SLOTS * sizeof(R) + 15) / 16 * 16;
+};
+// workgroup size bound of the subproblem kernel variant that runs k_max nodes
+__host__ __device__ inline int qp_maxt(int kmax)
+{
+    const int threads = (kmax + 3) / 4 * 64;
+    return threads <= 320 ? 320 : (threads <= 640 ? 640 : 1024);
+}
+// clamp to [lo, hi] (lo <= hi), one median-of-three in FP32
+__device__ __forceinline__ float clampbox(float v, float lo, float hi)
+{
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
+}
+__device__ __forceinline__ double clampbox(double v, double lo, double hi)
+{
+    return fmin(fmax(v, lo), hi);
+}
+// maximum over the 16 lanes of a row, on every lane (max is exact in any order)
+template <typename R>
+__device__ __forceinline__ R row_max(R v)
+{
+    v = fmax(v, dppmov<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = fmax(v, dppmov<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = fmax(v, dppmov<0x141>(v));  // row_half_mirror
+    v = fmax(v, dppmov<0x140>(v));  // row_mirror
+    return v;
+}
+// bit patterns of non-negative values, ordered as unsigned integers like the values
+__device__ __forceinline__ unsigned int max_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ unsigned long long max_bits(double v)
+{
+    return (unsigned long long)__double_as_longlong(v);
+}
+template <typename R>
+__device__ __forceinline__ double from_max_bits(unsigned int b) { return double(__uint_as_float(b)); }
+template <typename R>
+__device__ __forceinline__ double from_max_bits(unsigned long long b)
+{
+    return __longlong_as_double((long long)b);
+}
+
 // ------------------------------------------------------------------------------------------
 // Subproblem kernel: one workgroup per instance, 16 lanes (one DPP row) per node.
 //   lane i of row k:  state variable (k, i) for i < 15 (primal step), dynamics row (k, i)
@@ -402,32 +489,27 @@ __device__ __forceinline__ void proj_cone_ball<float>(float &t, float &z0, float
 // The block products inside an interval use row broadcasts of register values (DPP);
 // only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// Preparation kernel, one workgroup per instance in the subproblem kernel's lane layout: the
+// convergence test of the current reference (an instance that has finished gets its outputs
+// and final status here), then the customized power iteration that bounds the spectral norm
+// of the subproblem's constraint operator; the buffered estimate goes to the workspace.  It
+// is a kernel of its own so that its FP64 temporaries do not count against the register
+// budget of the PIPG iteration.
+// ------------------------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
-                                                unsigned char *smem_raw)
+__device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsigned char *smem_raw)
 {
     if (b >= a.B) return;
     if (a.status[b] >= 0) return;  // uniform over the workgroup
     const int K = a.K[b], M = K - 1, kmax = a.kmax;
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
-    // waves whose four rows all lie beyond the instance's last node skip the arithmetic
-    // (they only take part in the barriers and reductions)
     const bool wact = ((t >> 6) << 2) < K;
-
-    // LDS carve (doubles first for alignment)
-    double *red = reinterpret_cast<double *>(smem_raw);          // [16 waves * 8]
+    double *red = reinterpret_cast<double *>(smem_raw);           // [16 waves * 8]
     double *dZ = red + 128;                                       // [kmax][VST]
     double *dPhi = dZ + kmax * VST;                               // [kmax][DST]
     double *dTh = dPhi + kmax * DST;                              // [kmax]
-    // staging of neighbour values, one row per workgroup row (KR of them) plus a zero row:
-    // row -1 of sPhi/sTh (phi_0, theta_0 of the first node) and row KR of sVx/sVu, so that
-    // rows k - 1 and k + 1 are read without bounds tests
-    const int KR = (kmax + 3) / 4 * 4;
-    R *sPhi = reinterpret_cast<R *>(dTh + kmax) + DST;            // rows -1..KR-1 of [DST]
-    R *sTh = sPhi + KR * DST + 1;                                 // rows -1..KR-1
-    R *sVx = sTh + KR;                                            // rows 0..KR of [DST]
-    R *sVu = sVx + (KR + 1) * DST;                                // rows 0..KR of [4]
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -480,11 +562,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
     }
 
-    // -------------------- load the subproblem into registers --------------------
+    // -------------------- load the subproblem's blocks --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
     R colA[NX], rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
-    // (forward product); rowBq: row i of B^+_{k-1} (control gradient of node k)
+    // (forward product); rowBq: row i of B^+_{k-1} (control part of the transposed product)
     for (int q = 0; q < NX; ++q) {
         colA[q] = dual ? blk[(long)k * BLK + i * CST + q] : R(0);
         rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
@@ -494,35 +576,6 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
         rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
                                              : R(0);
-    }
-
-    // boundary values, bounds, reference values
-    const R xb = isx ? a.x[xoff + i] : R(0);
-    const int qi = i >> 2;  // control component of this lane (lanes 4q..4q+3 hold u_q)
-    const R ubq = node ? a.u[uoff + qi] : R(0);
-    const R ub3 = node ? a.u[uoff + 3] : R(0);
-    bool fixed = false;
-    R fixv = R(0);
-    if (isx) {
-        if (k == 0) {
-            fixed = true;
-            const double zi = i < IY ? double(a.x0[(long)b * NX + i]) : 0.0;
-            fixv = R((zi - double(xb)) / a.px[i]);
-        } else if (k == K - 1 && final_fixed(i)) {
-            fixed = true;
-            fixv = R((double(a.xf[(long)b * NXF + i - 1]) - double(xb)) / a.px[i]);
-        }
-    }
-    const R slo = R((double(p[18]) - double(ub3)) / a.pu[3]);
-    const R shi = R((double(p[19]) - double(ub3)) / a.pu[3]);
-    R wk = R(0), epsk = R(0);
-    if (dual) {
-        wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
-        if (i == IY) {
-            const double y0 = double(a.x[((long)b * kmax + k) * NX + IY]);
-            const double y1 = double(a.x[((long)b * kmax + k + 1) * NX + IY]);
-            epsk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
-        }
     }
 
     // -------------------- customized power iteration (FP64) --------------------
@@ -590,45 +643,149 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         sigma = (1.0 + a.power_buff) * sstar;
     }
-    const double alpha_d = 2.0 / (a.w_prox + sqrt(a.w_prox * a.w_prox + 4.0 * a.omega * sigma));
-    const R alpha = R(alpha_d), beta = R(a.omega * alpha_d), rho = R(a.rho);
-    const R omr = R(1) - rho;
-    const R wprox = R(a.w_prox), wep = R(a.w_ep);
+    if (t == 0) {
+        a.sigma[b] = sigma;
+        // PIPG step sizes from the buffered estimate
+        const double alpha = 2.0 / (a.w_prox + sqrt(a.w_prox * a.w_prox + 4.0 * a.omega * sigma));
+        a.stepsz[2 * b] = R(alpha);
+        a.stepsz[2 * b + 1] = R(a.omega * alpha);
+    }
+}
+
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) prepare_kernel(Args<R> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    prepare_body<R>(a, blockIdx.x, smem_raw);
+}
+
+template <typename R, int MAXT>
+__device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
+                                                unsigned char *smem_raw)
+{
+    if (b >= a.B) return;
+    if (a.status[b] >= 0) return;  // uniform over the workgroup
+    const int K = a.K[b], M = K - 1, kmax = a.kmax;
+    const int t = threadIdx.x;
+    const int k = t >> 4, i = t & 15;
+    // waves whose four rows all lie beyond the instance's last node skip the arithmetic
+    // (they only take part in the barriers)
+    const bool wact = ((t >> 6) << 2) < K;
+
+    // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
+    using Lds = QpLds<R, MAXT>;
+    const int KR = (kmax + 3) / 4 * 4;
+    double *red = reinterpret_cast<double *>(smem_raw + Lds::BYTES);  // [16 waves * 8]
+    // stopping-test maxima: two sets of six bit patterns (32-bit for FP32, 64-bit for FP64)
+    using Bits = decltype(max_bits(R(0)));
+    Bits *chk = reinterpret_cast<Bits *>(red + 128);               // [2][8]
+    R *myCol = reinterpret_cast<R *>(red + 144) + t * ColStore<R>::LDS_STRIDE;  // FP32: [KR * 16][20]
+
+    const bool node = k < K;               // row holds a node
+    const bool isx = node && i < NX;       // lane holds a state variable
+    const bool dual = k < M && i < NX;     // lane holds a dynamics row
+    const long xoff = ((long)b * kmax + (node ? k : 0)) * NX;
+    const long uoff = ((long)b * kmax + (node ? k : 0)) * NU;
+    const R *p = a.params + (long)b * NP;
+
+    // -------------------- load the subproblem into registers --------------------
+    const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
+    R rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    ColStore<R> colA{myCol};
+    // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
+    // (forward product); rowBq: row i of B^+_{k-1} (control gradient of node k)
+    for (int q = 0; q < NX; ++q) {
+        colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
+        rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
+    }
+    for (int q = 0; q < NU; ++q) {
+        rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
+        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
+        rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
+                                             : R(0);
+    }
+
+    const double sigma = a.sigma[b];  // buffered spectral estimate (preparation kernel)
+
+    // boundary values, bounds, reference values
+    const R xb = isx ? a.x[xoff + i] : R(0);
+    const int qi = i >> 2;  // control component of this lane (lanes 4q..4q+3 hold u_q)
+    const R ubq = node ? a.u[uoff + qi] : R(0);
+    const R ub3 = node ? a.u[uoff + 3] : R(0);
+    bool fixed = false;
+    R fixv = R(0);
+    if (isx) {
+        if (k == 0) {
+            fixed = true;
+            const double zi = i < IY ? double(a.x0[(long)b * NX + i]) : 0.0;
+            fixv = R((zi - double(xb)) / a.px[i]);
+        } else if (k == K - 1 && final_fixed(i)) {
+            fixed = true;
+            fixv = R((double(a.xf[(long)b * NXF + i - 1]) - double(xb)) / a.px[i]);
+        }
+    }
+    const R slo = R((double(p[18]) - double(ub3)) / a.pu[3]);
+    const R shi = R((double(p[19]) - double(ub3)) / a.pu[3]);
+    R wk = R(0), epsk = R(0);
+    if (dual) {
+        wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
+        if (i == IY) {
+            const double y0 = double(a.x[((long)b * kmax + k) * NX + IY]);
+            const double y1 = double(a.x[((long)b * kmax + k + 1) * NX + IY]);
+            epsk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
+        }
+    }
+
+    // workgroup-uniform step sizes (from the preparation kernel) and weights: scalar registers
+    const R alpha = a.stepsz[2 * b], beta = a.stepsz[2 * b + 1];
+    const R rho = a.rho_r, omr = a.omr_r, wprox = a.wprox_r, wep = a.wep_r;
     const R cost = (isx && k == K - 1 && i == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
 
     // -------------------- PIPG_custom --------------------
     // warm start: x^, u^ = 0; mu+-, phi, theta from the previous subproblem
     // fresh iterates (x^, u^, mu, phi, theta) double as the previous iterate of the stopping
-    // test; the extrapolated ones are x~, u~, nu, varphi, vartheta
-    R xt = R(0), xh = R(0);
-    R ut = R(0), uh = R(0);  // control component qi of node k
-    R vphi = R(0), ph = R(0);
-    R nup = R(0), num = R(0), mup = R(0), mum = R(0);
-    R vth = R(0), th = R(0);
+    // test; the extrapolated ones are x~, u~, nu, varphi, vartheta.  Lanes that hold no
+    // dynamics row start at zero and, with zero blocks and zero neighbour values, stay there.
+    R xt = R(0), ut = R(0);  // ut: control component qi of node k
+    R vphi = R(0), nup = R(0), num = R(0);
+    R vth = R(0);  // theta_k on lane IY, zero on the other lanes
     const long doff = ((long)b * (kmax - 1) + (dual ? k : 0)) * DST + i;
     if (dual) {
-        mup = nup = a.mup[doff];
-        mum = num = a.mum[doff];
-        ph = vphi = a.phi[doff];
-        if (i == IY) th = vth = a.th[(long)b * kmax + k];
+        nup = a.mup[doff];
+        num = a.mum[doff];
+        vphi = a.phi[doff];
+        if (i == IY) vth = a.th[(long)b * kmax + k];
     }
-    sPhi[k * DST + i] = vphi;
-    if (i == IY) sTh[k] = vth;
-    if (k == 0) {
-        sPhi[i - DST] = R(0);
-        sVx[KR * DST + i] = R(0);
-        if (i == 0) sTh[-1] = R(0);
-        if (i < NU) sVu[KR * NU + i] = R(0);
+    // this lane's exchange slots; row -1 of phi/theta and row KR of the extrapolated primal
+    // values are zero rows.  The fresh iterate of the step before a stopping test, and of the
+    // last step, goes to this lane's previous-iterate slots; they start with the warm start.
+    R *sl = reinterpret_cast<R *>(smem_raw) + t;
+    sl[Lds::PX] = R(0);
+    sl[Lds::PU] = R(0);
+    sl[Lds::PMP] = nup;
+    sl[Lds::PMM] = num;
+    sl[Lds::PPH] = vphi;
+    sl[Lds::PTH] = vth;
+    sl[Lds::PHI + 16] = vphi;
+    sl[Lds::TH + 16] = vth;
+    sl[Lds::VX] = R(0);
+    sl[Lds::VU] = R(0);
+    if (t < 16) {
+        reinterpret_cast<uint64_t *>(chk)[t] = 0;
+        sl[Lds::PHI] = R(0);
+        sl[Lds::TH] = R(0);
+        sl[Lds::VX + KR * 16] = R(0);
+        sl[Lds::VU + KR * 16] = R(0);
     }
     if (a.rec_x) {
         if (isx) a.rec_x[xoff + i] = xb;
         if (node && i < NU) a.rec_u[uoff + i] = a.u[uoff + i];
         if (dual) {
             const long ro = ((long)b * (kmax - 1) + k) * NX + i;
-            a.rec_mup[ro] = mup;
-            a.rec_mum[ro] = mum;
-            a.rec_phi[ro] = ph;
-            if (i == IY) a.rec_th[(long)b * (kmax - 1) + k] = th;
+            a.rec_mup[ro] = nup;
+            a.rec_mum[ro] = num;
+            a.rec_phi[ro] = vphi;
+            if (i == IY) a.rec_th[(long)b * (kmax - 1) + k] = vth;
         }
         if (t == 0) a.rec_sigma[b] = sigma;
     }
@@ -668,38 +825,49 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const bool thr = role == 5;
     // leader inputs t_j = c_j + m_j * (member j, scaled): references and scales.  Every DPP
     // exchange is evaluated by all lanes before any selection (a lane-dependent condition
-    // around it would mask out the lanes it reads from).
+    // around it would mask out the lanes it reads from).  lc0 is also the reference a member
+    // subtracts when it reads its component back (the thrust leader is in no state set).
     const R xb_p1 = dppmov<0x101>(xb), xb_p2 = dppmov<0x102>(xb);  // row_shl: lanes +1, +2
     const R lc0 = thr ? ubT0 : xb;
     const R lc1 = thr ? ubT1 : xb_p1;
     const R lc2 = thr ? ubT2 : (role == 3 ? R(0) : xb_p2);
     const R lm = thr ? pT : pxi;
     const R lm2 = role == 3 ? R(0) : lm;
+    // box applied to the fresh iterate after the set projections: fixed boundary values
+    // (lo = hi), the dry-mass bound, zero on lanes without a state variable; the dilation
+    // bounds on the s lanes, zero on rows without a node
+    R xlo = -INF, xhi = INF, ulo = -INF, uhi = INF;
+    if (!isx) xlo = xhi = R(0);
+    else if (fixed) xlo = xhi = fixv;
+    else if (grp == 1) xlo = (mdry - xb) * ipxi;
+    if (!node) ulo = uhi = R(0);
+    else if (qi == 3) { ulo = slo; uhi = shi; }
+    const bool thlane = dual && i == IY;  // lane of the CTCS multiplier theta_k
 
-    int it = 1;
-    // fresh iterate of this step; waves beyond the last node keep these zeros
-    R xn = R(0), un = R(0);
-    R vx = R(0), vu = R(0);
-    R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
-    for (; it <= jmax; ++it) {
+    int iters = 0;
+    for (int it = 1; it <= jmax; ++it) {
+        // fresh iterate of this step; waves beyond the last node keep these zeros
+        R xn = R(0), un = R(0), vx = R(0), vu = R(0);
         if (wact) {
         // ---- projected gradient step on the primal variables ----
-        const R phm1 = sPhi[(k - 1) * DST + i];  // phi_{k-1}[i] (zero row above the first node)
-        const R thm1 = sTh[k - 1];               // theta_{k-1}
-        const R thk = rowb<IY>(vth);                                          // theta_k
+        const R phm1 = sl[Lds::PHI];  // phi_{k-1}[i] (zero row above the first node)
+        const R thm1 = sl[Lds::TH];   // theta_{k-1} on lane IY
         R g = wprox * xt + cost;
-        g = rowdot15<R>(colA, vphi, g);  // (A^-_k)^T phi_k, column i
+        {
+            R c[ColStore<R>::N];
+            colA.get(c);
+            g = rowdot15<R>(c, vphi, g);  // (A^-_k)^T phi_k, column i
+        }
         g -= phm1;
-        if (i == IY) g += (k < M ? -thk : R(0)) + thm1;
+        g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
         xn = xt - alpha * g;
         // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
         {
             R gq[NU];
             for (int q = 0; q < NU; ++q) gq[q] = rowBm[q] * vphi + rowBq[q] * phm1;
-            const R g = wprox * ut + row_reduce_scatter4<R>(gq, i);
-            un = ut - alpha * g;
+            const R gu = wprox * ut + row_reduce_scatter4<R>(gq, i);
+            un = ut - alpha * gu;
         }
-        if (qi == 3) un = fmin(fmax(un, slo), shi);
         if (pmask) {
             // leader inputs: members from lanes +1, +2 (row_shl); thrust from the control
             // lanes 0, 4, 8 (row_shr:4, own, row_shl:4)
@@ -715,28 +883,23 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             // members read their component from the leader (row_shr by their slot)
             const R t1_m1 = dppmov<0x111>(t1), t2_m2 = dppmov<0x112>(t2);
             const R o = gw == 0 ? t0 : (gw == 1 ? t1_m1 : t2_m2);
-            if (grp >= 2 && grp <= 4) xn = (o - xb) * ipxi;
-            if (grp == 1) {
-                const R m = xb + pxi * xn;
-                xn = m < mdry ? (mdry - xb) * ipxi : xn;
-            }
+            if (grp >= 2 && grp <= 4) xn = (o - lc0) * ipxi;
             if (pmask & 16) {
                 const R T0 = rowb<4>(t0), T1 = rowb<4>(t1), T2 = rowb<4>(t2);
                 if (qi < 3) un = ((qi == 0 ? T0 : (qi == 1 ? T1 : T2)) - ubq) * ipT;
             }
         }
-        if (fixed) xn = fixv;
-        if (!isx) xn = R(0);
+        xn = clampbox(xn, xlo, xhi);
+        un = clampbox(un, ulo, uhi);
         vx = R(2) * xn - xt;
         xt = omr * xt + rho * xn;
         vu = R(2) * un - ut;
         ut = omr * ut + rho * un;
-        if (node) {
-            sVx[k * DST + i] = vx;
-            if ((i & 3) == 0) sVu[k * NU + qi] = vu;
-        }
+        sl[Lds::VX] = vx;
+        sl[Lds::VU] = vu;
         }  // wact
         __syncthreads();
+        R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
         if (wact) {
         // ---- dual (proportional-integral) step ----
         mupn = nup - alpha * (wep + vphi);
@@ -744,80 +907,73 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
         R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
-        const R vnext = sVx[(k + 1) * DST + i];  // used by the dynamics rows k < K - 1 only
+        const R vnext = sl[Lds::VX + 16];   // zero beyond the last node
         r -= vnext;
-        r = rowdot4q<R>(rowBm, vu, r);  // B^-_k (2u^ - u~)_k
-        for (int q = 0; q < NU; ++q) {
-            const R vun = sVu[(k + 1) * NU + q];
-            r += rowBp[q] * vun;
-        }
+        r = rowdot4q<R>(rowBm, vu, r);                  // B^-_k (2u^ - u~)_k
+        r = rowdot4q<R>(rowBp, sl[Lds::VU + 16], r);   // B^+_k (2u^ - u~)_{k+1}
         r += (R(2) * mupn - nup) - (R(2) * mumn - num);
         r += wk;
         phn = vphi + beta * r;
         thn = vth + beta * (vnext - vx - epsk);
-        thn = thn > R(0) ? thn : R(0);
-        if (!dual) {
-            phn = mupn = mumn = thn = R(0);
-        }
-        if (i != IY) thn = R(0);
+        thn = (thlane && thn > R(0)) ? thn : R(0);
         vphi = omr * vphi + rho * phn;
         nup = omr * nup + rho * mupn;
         num = omr * num + rho * mumn;
         vth = omr * vth + rho * thn;
-        sPhi[k * DST + i] = vphi;
-        if (i == IY) sTh[k] = vth;
+        sl[Lds::PHI + 16] = vphi;
+        sl[Lds::TH + 16] = vth;
         }  // wact
-        bool done = false;
-        if (check > 0 && it % check == 0) {
-            // infinity norms of (x, u, mu+, mu-) and of (phi, theta) at j+1 and j
-            double nz[6] = {0, 0, 0, 0, 0, 0};
-            if (isx) {
-                nz[0] = fabs(double(xn));
-                nz[1] = fabs(double(xh));
-                nz[2] = fabs(double(xn) - double(xh));
-            }
-            if (node && (i & 3) == 0) {
-                nz[0] = fmax(nz[0], fabs(double(un)));
-                nz[1] = fmax(nz[1], fabs(double(uh)));
-                nz[2] = fmax(nz[2], fabs(double(un) - double(uh)));
-            }
-            if (dual) {
-                nz[0] = fmax(nz[0], fmax(fabs(double(mupn)), fabs(double(mumn))));
-                nz[1] = fmax(nz[1], fmax(fabs(double(mup)), fabs(double(mum))));
-                nz[2] = fmax(nz[2], fmax(fabs(double(mupn) - double(mup)),
-                                         fabs(double(mumn) - double(mum))));
-                nz[3] = fabs(double(phn));
-                nz[4] = fabs(double(ph));
-                nz[5] = fabs(double(phn) - double(ph));
-                if (i == IY) {
-                    nz[3] = fmax(nz[3], fabs(double(thn)));
-                    nz[4] = fmax(nz[4], fabs(double(th)));
-                    nz[5] = fmax(nz[5], fabs(double(thn) - double(th)));
-                }
-            }
-            block_reduce<6, true>(nz, red);
-            done = nz[2] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(nz[0], nz[1]) &&
-                   nz[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(nz[3], nz[4]);
+        // stopping test every `check` steps: infinity norms of (x, u, mu+, mu-) and of
+        // (phi, theta) at j+1 and j and of their differences.  Lanes without a variable hold
+        // zeros and the four lanes of a control hold identical values, so every lane enters
+        // unmasked.  Row maxima by DPP, then one LDS atomic max per row on the bit patterns
+        // (monotone for non-negative values); the slot set alternates between tests, the
+        // other set is cleared for the next one.
+        const bool test = check > 0 && it % check == 0;
+        const int cset = test ? ((it / check) & 1) : 0;
+        if (test) {
+            const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
+            const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
+            R m[6];
+            m[0] = fmax(fmax(fabs(xn), fabs(un)), fmax(fabs(mupn), fabs(mumn)));
+            m[1] = fmax(fmax(fabs(xh), fabs(uh)), fmax(fabs(mup), fabs(mum)));
+            m[2] = fmax(fmax(fabs(xn - xh), fabs(un - uh)), fmax(fabs(mupn - mup), fabs(mumn - mum)));
+            m[3] = fmax(fabs(phn), fabs(thn));
+            m[4] = fmax(fabs(ph), fabs(th));
+            m[5] = fmax(fabs(phn - ph), fabs(thn - th));
+            for (int q = 0; q < 6; ++q) m[q] = row_max<R>(m[q]);
+            if (i == 0)
+                for (int q = 0; q < 6; ++q) atomicMax(&chk[8 * cset + q], max_bits(m[q]));
+            if (t == 0)
+                for (int q = 0; q < 6; ++q) chk[8 * (cset ^ 1) + q] = 0;
         }
-        xh = xn;
-        uh = un;
-        mup = mupn;
-        mum = mumn;
-        ph = phn;
-        th = thn;
+        if (test || it == jmax || (check > 0 && (it + 1) % check == 0)) {
+            sl[Lds::PX] = xn;
+            sl[Lds::PU] = un;
+            sl[Lds::PMP] = mupn;
+            sl[Lds::PMM] = mumn;
+            sl[Lds::PPH] = phn;
+            sl[Lds::PTH] = thn;
+        }
         __syncthreads();
-        if (done) {
-            ++it;
-            break;
+        iters = it;
+        if (test) {
+            double n[6];
+            for (int q = 0; q < 6; ++q) n[q] = from_max_bits<R>(chk[8 * cset + q]);
+            if (n[2] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[0], n[1]) &&
+                n[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[3], n[4]))
+                break;
         }
     }
-    const int iters = it - 1;
 
     // -------------------- reference update and warm start --------------------
+    // the subproblem's solution: the fresh iterate of the last step
+    const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
+    const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
     double st[1] = {0.0};
     if (isx) {
         st[0] = fabs(double(xh));
-        a.x[xoff + i] = R(double(xb) + a.px[i] * double(xh));
+        a.x[xoff + i] = R(double(a.x[xoff + i]) + a.px[i] * double(xh));
     }
     if (node && (i & 3) == 0) {
         st[0] = fmax(st[0], fabs(double(uh)));
@@ -848,7 +1004,7 @@ subproblem_kernel(Args<R> a)
     // the hardware issues workgroups as earlier ones retire, so the longest instances start
     // first and the short ones fill in behind them
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]) : blockIdx.x;
-    subproblem_body<R>(a, b, smem_raw);
+    subproblem_body<R, MAXT>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
@@ -864,7 +1020,7 @@ __global__ void __launch_bounds__(MAXT) subproblem_persistent(Args<R> a)
     __syncthreads();
     int idx = s_next;
     while (idx < a.B) {
-        subproblem_body<R>(a, __builtin_amdgcn_readfirstlane(a.order[idx]), smem_raw);
+        subproblem_body<R, MAXT>(a, __builtin_amdgcn_readfirstlane(a.order[idx]), smem_raw);
         __syncthreads();
         if (threadIdx.x == 0) s_next = atomicAdd(&a.queue[a.j], 1);
         __syncthreads();
@@ -906,11 +1062,44 @@ __global__ void order_scatter(Args<R> a)
 // ------------------------------------------------------------------------------------------
 int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
-static size_t qp_smem_bytes(int kmax, size_t rsize)
+size_t qp_smem_bytes(int kmax, size_t rsize)
 {
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
-    return sizeof(double) * (128 + kmax * VST + kmax * DST + kmax) +
-           rsize * ((KR + 1) * DST + (KR + 1) + (KR + 1) * DST + (KR + 1) * NU);
+    const int maxt = qp_maxt(kmax);
+    const size_t stage = rsize == 4 ? (maxt == 320 ? QpLds<float, 320>::BYTES
+                                                   : (maxt == 640 ? QpLds<float, 640>::BYTES
+                                                                  : QpLds<float, 1024>::BYTES))
+                                    : (maxt == 320 ? QpLds<double, 320>::BYTES
+                                                   : (maxt == 640 ? QpLds<double, 640>::BYTES
+                                                                  : QpLds<double, 1024>::BYTES));
+    const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
+    return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
+}
+// dynamic LDS bytes of the preparation kernel: reduction scratch and power-iteration vectors
+static size_t prep_smem_bytes(int kmax)
+{
+    return sizeof(double) * (128 + (size_t)kmax * (VST + DST + 1));
+}
+
+// Subproblem launch with the register-budget variant: occupancy 4 or 5 bounds the kernel to
+// that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
+template <typename R, int MAXT>
+static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
+                              const Args<R> &a)
+{
+    if constexpr (sizeof(R) == 4) {
+        if (occupancy == 5) {
+            subproblem_kernel<R, MAXT, 5><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            return;
+        }
+        if constexpr (MAXT < 1024) {
+            if (occupancy == 4) {
+                subproblem_kernel<R, MAXT, 4><<<dim3(B), dim3(threads), smem, stream>>>(a);
+                return;
+            }
+        }
+    }
+    subproblem_kernel<R, MAXT, 1><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
 
 template <typename R>
@@ -965,6 +1154,12 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.th = static_cast<R *>(ws.th);
     a.dy = ws.dy;
     a.step = ws.step;
+    a.sigma = ws.sigma;
+    a.stepsz = static_cast<R *>(ws.stepsz);
+    a.rho_r = R(cfg.rho);
+    a.omr_r = R(1) - R(cfg.rho);
+    a.wprox_r = R(cfg.w_prox);
+    a.wep_r = R(cfg.w_ep);
     a.pipg_total = ws.pipg_total;
     a.queue = ws.queue;
     a.bucket = ws.bucket;
@@ -997,7 +1192,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     }
     const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
     const int qthreads = qp_block_threads(cfg.kmax);
+    const int maxt = qp_maxt(cfg.kmax);
     const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
+    const size_t psmem = prep_smem_bytes(cfg.kmax);
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
     if (persistent || cfg.ordered) {
@@ -1016,19 +1213,30 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
             a, need_blocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(1, false)) != hipSuccess) return e;
+        if ((e = mark(3, true)) != hipSuccess) return e;
+        if (maxt == 320)
+            prepare_kernel<R, 320><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
+        else if (maxt == 640)
+            prepare_kernel<R, 640><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
+        else
+            prepare_kernel<R, 1024><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = mark(3, false)) != hipSuccess) return e;
+        if (j > cfg.scp_iters_max) break;  // the last test has set every remaining status
         if ((e = mark(2, true)) != hipSuccess) return e;
         if (persistent) {
-            if (qthreads <= 640)
+            if (maxt == 320)
+                subproblem_persistent<R, 320><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+            else if (maxt == 640)
                 subproblem_persistent<R, 640><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
             else
                 subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
-        } else if (qthreads <= 640) {
-            if (cfg.occupancy == 4)
-                subproblem_kernel<R, 640, 4><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
-            else
-                subproblem_kernel<R, 640, 1><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+        } else if (maxt == 320) {
+            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+        } else if (maxt == 640) {
+            launch_subproblem<R, 640>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else {
-            subproblem_kernel<R, 1024, 1><<<dim3(cfg.B), dim3(qthreads), smem, stream>>>(a);
+            launch_subproblem<R, 1024>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(2, false)) != hipSuccess) return e;
@@ -1082,23 +1290,26 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
 }  // namespace scp
 
 namespace scp {
+template <typename R, int MAXT>
+static hipError_t persistent_blocks(int *n, int kmax)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, subproblem_persistent<R, MAXT>,
+                                                        qp_block_threads(kmax),
+                                                        qp_smem_bytes(kmax, sizeof(R)));
+}
 int qp_blocks_per_cu(int dtype, int kmax)
 {
-    const int threads = qp_block_threads(kmax);
+    const int maxt = qp_maxt(kmax);
     int n = 0;
     hipError_t e;
     if (dtype == 1)
-        e = threads <= 640
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<double, 640>,
-                                                               threads, qp_smem_bytes(kmax, 8))
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<double, 1024>,
-                                                               threads, qp_smem_bytes(kmax, 8));
+        e = maxt == 320 ? persistent_blocks<double, 320>(&n, kmax)
+                        : (maxt == 640 ? persistent_blocks<double, 640>(&n, kmax)
+                                       : persistent_blocks<double, 1024>(&n, kmax));
     else
-        e = threads <= 640
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<float, 640>,
-                                                               threads, qp_smem_bytes(kmax, 4))
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, subproblem_persistent<float, 1024>,
-                                                               threads, qp_smem_bytes(kmax, 4));
+        e = maxt == 320 ? persistent_blocks<float, 320>(&n, kmax)
+                        : (maxt == 640 ? persistent_blocks<float, 640>(&n, kmax)
+                                       : persistent_blocks<float, 1024>(&n, kmax));
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 }  // namespace scp

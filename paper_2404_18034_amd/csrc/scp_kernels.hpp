@@ -17,6 +17,8 @@ struct Workspace {
     void *phi;          // R  [B][kmax-1][16]      warm start dual of the dynamics
     void *th;           // R  [B][kmax]            warm start dual of the CTCS rows
     double *step;       // f64 [B]                  scaled step of the last subproblem
+    double *sigma;      // f64 [B]                  buffered spectral estimate of the subproblem
+    void *stepsz;       // R  [B][2]                PIPG step sizes (alpha, beta) of the subproblem
     int32_t *pipg_total;// i32 [B]
     int32_t *queue;     // i32 [scp_iters_max + 2]  work-queue heads (persistent form)
     int32_t *bucket;    // i32 [kmax + 1]           node-count buckets
@@ -30,7 +32,7 @@ struct Config {
     int early_exit, node_projections;
     int persistent_blocks;  // 0: one workgroup per instance; > 0: persistent grid size
     int ordered;            // 1: workgroups take instances by node count, descending
-    int occupancy;          // 4: subproblem variant limited to four waves per SIMD
+    int occupancy;          // 4 / 5: FP32 subproblem variant bounded to 4 / 5 waves per SIMD
     int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
@@ -70,7 +72,8 @@ struct GradWorkspace {
 
 // Optional per-launch timing: when `events` is non-null, launch i is bracketed by
 // events[2i] and events[2i+1] (recorded on `stream`) and kinds[i] receives its kernel class
-// (0 init, 1 discretize, 2 subproblem); *n_launches receives the number of launches.
+// (0 init, 1 discretize, 2 subproblem PIPG, 3 preparation: convergence test and power
+// iteration); *n_launches receives the number of launches.
 struct LaunchTimer {
     hipEvent_t *events;
     int *kinds;
@@ -108,6 +111,8 @@ size_t grad_smem_bytes(int dtype, int kmax);
 
 // Workgroup size of the subproblem kernel for node count kmax.
 int qp_block_threads(int kmax);
+// dynamic LDS bytes of one subproblem workgroup (rsize = 4 for FP32, 8 for FP64)
+size_t qp_smem_bytes(int kmax, size_t rsize);
 
 // Resident workgroups per compute unit of the persistent subproblem kernel (occupancy query).
 int qp_blocks_per_cu(int dtype, int kmax);

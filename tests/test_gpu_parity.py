@@ -270,7 +270,7 @@ def test_invalid_arguments_raise():
     s.close()
 
 
-@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (2, 4)])
+@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (0, 5), (2, 5)])
 def test_dispatch_modes_match_plain_launches(mode, occupancy):
     # graph replay, K-ordered dispatch and the persistent work queue compute the same thing as
     # plain launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
@@ -318,3 +318,25 @@ def test_autotune_picks_a_mode_and_keeps_results(tmp_path):
     for k in ref:
         np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k])
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_node_counts_up_to_50_short_horizon(dtype):
+    # node counts above 40 take the 1,024-lane workgroup variant; with K = 2 and K = 12 in the
+    # same batch most of its waves sit beyond the last node of those instances
+    cfg = I.solver_settings("C2", node_projections=31, scp_iters_max=2, pipg_iters_max=200,
+                            early_exit=0)
+    inst = I.make_instances("C2", B=6)
+    inst["K"] = np.array([41, 50, 44, 12, 47, 2], dtype=np.int32)
+    print("case: K up to 50, %s, k_max 50" % dtype, flush=True)
+    g = _gpu(cfg, inst, dtype, k_max=50)
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=50)
+    if dtype == "f64":
+        errs = _errors(cfg, g, o)
+        _report("K<=50 fp64 2 subproblems", errs)
+        for e in errs:
+            assert e.max() <= TOL_F64
+        for k in ("status", "scp_iters", "pipg_iters"):
+            np.testing.assert_array_equal(g[k], o[k])
+    else:
+        check_fp32_against_oracle(cfg, inst, g, o, "K<=50 fp32 2 subproblems", kmax=50)
