@@ -481,14 +481,49 @@ __device__ __forceinline__ double from_max_bits(unsigned long long b)
     return __longlong_as_double((long long)b);
 }
 
-// ------------------------------------------------------------------------------------------
-// Subproblem kernel: one workgroup per instance, 16 lanes (one DPP row) per node.
-//   lane i of row k:  state variable (k, i) for i < 15 (primal step), dynamics row (k, i)
-//                     of interval k for i < 15, k < K-1 (dual step); the four controls of
-//                     node k are held, bitwise identical, by all 16 lanes of the row.
-// The block products inside an interval use row broadcasts of register values (DPP);
-// only the values a row needs from its neighbouring rows pass through LDS.
-// ------------------------------------------------------------------------------------------
+template <int S, typename C, int... J>
+__device__ __forceinline__ void pw_rowdot_impl(const C *c, double v, double &acc,
+                                               std::integer_sequence<int, J...>)
+{
+    ((acc = fma(double(c[J]), rowb<S * J>(v), acc)), ...);
+}
+// LDS of the preparation kernel for a workgroup of at most MAXT lanes: per-lane FP64 slots
+// of the power iterate (x part Z and u part U, rows 0 .. ROWS, the row after the last
+// workgroup row zero) and of phi and theta (rows -1 .. ROWS-1, row -1 zero), then the
+// reduction scratch.
+template <int MAXT>
+struct PrepLds {
+    static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
+    static constexpr int Z = 0, U = SLOTS, P = 2 * SLOTS, T = 3 * SLOTS, RED = 4 * SLOTS;
+    static constexpr size_t BYTES = (RED + 128) * sizeof(double);
+};
+// sum_j c[j] * (lane S*j of this row's value of v), FP64, in the order j = 0, 1, ...
+template <int N, int S, typename C>
+__device__ __forceinline__ double pw_rowdot(const C *c, double v, double acc)
+{
+    pw_rowdot_impl<S>(c, v, acc, std::make_integer_sequence<int, N>{});
+    return acc;
+}
+// marks the values of c as redefined at this point (no instruction is emitted), so that a
+// conversion of them is not hoisted out of the enclosing loop
+template <typename T, int N>
+__device__ __forceinline__ void keep_narrow(T (&c)[N])
+{
+    for (int n = 0; n < N; ++n) asm volatile("" : "+v"(c[n]));
+}
+// sum over the 64 lanes of a wave on every lane: row sums (symmetric exchanges), then the
+// four row sums added in row order
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = row_allreduce<double>(v);
+    auto lane = [&](int l) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+        return __hiloint2double(hi, lo);
+    };
+    return ((lane(0) + lane(16)) + lane(32)) + lane(48);
+}
+
 // ------------------------------------------------------------------------------------------
 // Preparation kernel, one workgroup per instance in the subproblem kernel's lane layout: the
 // convergence test of the current reference (an instance that has finished gets its outputs
@@ -497,7 +532,7 @@ __device__ __forceinline__ double from_max_bits(unsigned long long b)
 // is a kernel of its own so that its FP64 temporaries do not count against the register
 // budget of the PIPG iteration.
 // ------------------------------------------------------------------------------------------
-template <typename R>
+template <typename R, int MAXT>
 __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsigned char *smem_raw)
 {
     if (b >= a.B) return;
@@ -506,10 +541,9 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
     const bool wact = ((t >> 6) << 2) < K;
-    double *red = reinterpret_cast<double *>(smem_raw);           // [16 waves * 8]
-    double *dZ = red + 128;                                       // [kmax][VST]
-    double *dPhi = dZ + kmax * VST;                               // [kmax][DST]
-    double *dTh = dPhi + kmax * DST;                              // [kmax]
+    using Lds = PrepLds<MAXT>;
+    double *sl = reinterpret_cast<double *>(smem_raw) + t;       // this lane's exchange slots
+    double *red = reinterpret_cast<double *>(smem_raw) + Lds::RED;  // [16 waves * 8]
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -564,11 +598,12 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
 
     // -------------------- load the subproblem's blocks --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
-    R colA[NX], rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    R rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    ColStore<R> colA{reinterpret_cast<R *>(smem_raw + Lds::BYTES) + t * ColStore<R>::LDS_STRIDE};
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
     // (forward product); rowBq: row i of B^+_{k-1} (control part of the transposed product)
     for (int q = 0; q < NX; ++q) {
-        colA[q] = dual ? blk[(long)k * BLK + i * CST + q] : R(0);
+        colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
         rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
     }
     for (int q = 0; q < NU; ++q) {
@@ -579,70 +614,89 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     }
 
     // -------------------- customized power iteration (FP64) --------------------
-    // z = (x, u, mu+, mu-) starts at all ones.  x on lane i of row k, u of node k on lanes
-    // 0..3 of row k, mu+- of row (k, i) on the dual lanes.
+    // z = (x, u, mu+, mu-) starts at all ones: x_k on lane i of row k, u_k[q] on lanes
+    // 4q..4q+3 of row k, mu+- of dynamics row (k, i) on the dual lanes.  Each step forms
+    // phi = H z / sigma (dynamics rows; theta for the CTCS rows) and z' = H^T phi, where
+    // mu+' = phi and mu-' = -phi; the block products use row broadcasts of the FP64 iterate,
+    // the neighbouring rows pass through this lane's LDS slots.  Two barriers per step.
+    const int KR = (kmax + 3) / 4 * 4;
+    const bool thlane = dual && i == IY;
+    double zx = isx ? 1.0 : 0.0, zu = node ? 1.0 : 0.0;
+    double dmu = 0.0;  // mu+ - mu- of this dynamics row
     double sigma;
     {
-        const bool isu = node && i < NU;
-        double zx = 1.0, zu = 1.0, mp = 1.0, mm = 1.0;
-        double acc[1] = {(isx ? 1.0 : 0.0) + (isu ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
+        double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NU) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
         block_reduce<1, false>(acc, red);
         sigma = sqrt(acc[0]);
-        double sstar = sigma;
-        for (int it = 1; it <= a.power_iters_max; ++it) {
-            if (isx) dZ[k * VST + i] = zx;
-            if (isu) dZ[k * VST + NX + i] = zu;
-            __syncthreads();
-            double ph = 0.0;
-            if (wact && dual) {
-                double r = 0.0;
-                for (int j = 0; j < NX; ++j) r += double(rowA[j]) * dZ[k * VST + j];
-                r -= dZ[(k + 1) * VST + i];
-                for (int j = 0; j < NU; ++j) {
-                    r += double(rowBm[j]) * dZ[k * VST + NX + j];
-                    r += double(rowBp[j]) * dZ[(k + 1) * VST + NX + j];
-                }
-                r += mp - mm;
-                ph = r / sigma;
-                dPhi[k * DST + i] = ph;
-                if (i == IY) dTh[k] = (dZ[(k + 1) * VST + IY] - dZ[k * VST + IY]) / sigma;
-            }
-            __syncthreads();
-            if (isx) {
-                double r = 0.0;
-                if (k < M)
-                    for (int q = 0; q < NX; ++q) r += double(colA[q]) * dPhi[k * DST + q];
-                if (k > 0) r -= dPhi[(k - 1) * DST + i];
-                if (i == IY) {
-                    if (k < M) r -= dTh[k];
-                    if (k > 0) r += dTh[k - 1];
-                }
-                zx = r;
-            }
-            if (wact) {
-                // control part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
-                const double phk = dual ? dPhi[k * DST + i] : 0.0;
-                const double phm = (k > 0 && k <= M && i < NX) ? dPhi[(k - 1) * DST + i] : 0.0;
-                double zq[NU];
-                for (int q = 0; q < NU; ++q)
-                    zq[q] = row_allreduce<double>(double(rowBm[q]) * phk + double(rowBq[q]) * phm);
-                zu = i == 0 ? zq[0] : (i == 1 ? zq[1] : (i == 2 ? zq[2] : zq[3]));
-            }
-            if (dual) {
-                mp = ph;
-                mm = -ph;
-            }
-            double sq[1] = {(isx ? zx * zx : 0.0) + (isu ? zu * zu : 0.0) +
-                            (dual ? mp * mp + mm * mm : 0.0)};
-            block_reduce<1, false>(sq, red);
-            sstar = sqrt(sq[0]);
-            if (fabs(sstar - sigma) <= a.power_eps_abs + a.power_eps_rel * fmax(sstar, sigma))
-                break;
-            else if (it < a.power_iters_max)
-                sigma = sstar;
-        }
-        sigma = (1.0 + a.power_buff) * sstar;
     }
+    sl[Lds::Z] = zx;
+    sl[Lds::U] = zu;
+    if (t < 16) {
+        sl[Lds::Z + KR * 16] = 0.0;  // row after the last workgroup row
+        sl[Lds::U + KR * 16] = 0.0;
+        sl[Lds::P] = 0.0;            // row -1
+        sl[Lds::T] = 0.0;
+    }
+    __syncthreads();
+    double sstar = sigma;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int it = 1; it <= a.power_iters_max; ++it) {
+        // FP32 blocks are widened where they are used: widening them once, outside the
+        // loop, would take twice their registers (the empty asm marks them as redefined)
+        if constexpr (sizeof(R) == 4) {
+            keep_narrow(rowA);
+            keep_narrow(rowBm);
+            keep_narrow(rowBp);
+            keep_narrow(rowBq);
+        }
+        double ph = 0.0, thv = 0.0;
+        if (wact) {
+            // A^-_k z_k - z_{k+1} + B^-_k u_k + B^+_k u_{k+1} + (mu+ - mu-), divided by sigma
+            const double zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
+            double r = pw_rowdot<NX, 1>(rowA, zx, 0.0);
+            r -= zxn;
+            r = pw_rowdot<NU, 4>(rowBm, zu, r);
+            r = pw_rowdot<NU, 4>(rowBp, zun, r);
+            r += dmu;
+            ph = dual ? r / sigma : 0.0;
+            thv = thlane ? (zxn - zx) / sigma : 0.0;
+        }
+        sl[Lds::P + 16] = ph;
+        sl[Lds::T + 16] = thv;
+        __syncthreads();
+        double q2 = 0.0;
+        if (wact) {
+            const double phm = sl[Lds::P], thm = sl[Lds::T];  // row k-1 (zero above node 0)
+            // x part: (A^-_k)^T phi_k - phi_{k-1}, and theta_{k-1} - theta_k on the y lane
+            R c[ColStore<R>::N];
+            colA.get(c);
+            double r = pw_rowdot<NX, 1>(c, ph, 0.0);
+            r -= phm;
+            r -= thv;
+            r += thm;
+            zx = isx ? r : 0.0;
+            // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
+            double gq[NU];
+            for (int q = 0; q < NU; ++q) gq[q] = double(rowBm[q]) * ph + double(rowBq[q]) * phm;
+            const double zq = row_reduce_scatter4<double>(gq, i);
+            zu = node ? zq : 0.0;
+            dmu = ph + ph;
+            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : 0.0) + (ph * ph + ph * ph);
+        }
+        sl[Lds::Z] = zx;
+        sl[Lds::U] = zu;
+        const double wsum = wave_sum(q2);
+        if ((t & 63) == 0) red[t >> 6] = wsum;
+        __syncthreads();
+        double s2 = red[0];
+        for (int w = 1; w < nw; ++w) s2 += red[w];
+        sstar = sqrt(s2);
+        if (fabs(sstar - sigma) <= a.power_eps_abs + a.power_eps_rel * fmax(sstar, sigma))
+            break;
+        else if (it < a.power_iters_max)
+            sigma = sstar;
+    }
+    sigma = (1.0 + a.power_buff) * sstar;
     if (t == 0) {
         a.sigma[b] = sigma;
         // PIPG step sizes from the buffered estimate
@@ -652,13 +706,23 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     }
 }
 
+// FP32: registers bounded for five waves per SIMD (four 5-wave workgroups per CU)
 template <typename R, int MAXT>
-__global__ void __launch_bounds__(MAXT) prepare_kernel(Args<R> a)
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
+prepare_kernel(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prepare_body<R>(a, blockIdx.x, smem_raw);
+    prepare_body<R, MAXT>(a, blockIdx.x, smem_raw);
 }
 
+// ------------------------------------------------------------------------------------------
+// Subproblem kernel: one workgroup per instance, 16 lanes (one DPP row) per node.
+//   lane i of row k:  state variable (k, i) for i < 15 (primal step), dynamics row (k, i)
+//                     of interval k for i < 15, k < K-1 (dual step); the four controls of
+//                     node k are held, bitwise identical, by all 16 lanes of the row.
+// The block products inside an interval use row broadcasts of register values (DPP);
+// only the values a row needs from its neighbouring rows pass through LDS.
+// ------------------------------------------------------------------------------------------
 template <typename R, int MAXT>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
@@ -1075,10 +1139,14 @@ size_t qp_smem_bytes(int kmax, size_t rsize)
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
     return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
 }
-// dynamic LDS bytes of the preparation kernel: reduction scratch and power-iteration vectors
-static size_t prep_smem_bytes(int kmax)
+// dynamic LDS bytes of the preparation kernel
+static size_t prep_smem_bytes(int kmax, size_t rsize)
 {
-    return sizeof(double) * (128 + (size_t)kmax * (VST + DST + 1));
+    const int maxt = qp_maxt(kmax);
+    const size_t KR = (size_t)(kmax + 3) / 4 * 4;
+    const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
+    return (maxt == 320 ? PrepLds<320>::BYTES : (maxt == 640 ? PrepLds<640>::BYTES : PrepLds<1024>::BYTES)) +
+           rsize * KR * 16 * col;
 }
 
 // Subproblem launch with the register-budget variant: occupancy 4 or 5 bounds the kernel to
@@ -1194,7 +1262,7 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
     const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
-    const size_t psmem = prep_smem_bytes(cfg.kmax);
+    const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R));
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
     if (persistent || cfg.ordered) {
