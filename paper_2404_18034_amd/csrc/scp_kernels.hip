@@ -45,7 +45,7 @@ struct Args {
     double *sigma;    // [B] buffered power-iteration estimate of the current subproblem
     R *stepsz;        // [B][2] PIPG step sizes (alpha, beta) of the current subproblem
     // PIPG weights in the working precision (kernel arguments, so scalar registers)
-    R rho_r, omr_r, wprox_r, wep_r;
+    R rho_r, wprox_r, wep_r;
     int32_t *pipg_total;
     int32_t *queue;   // [scp_iters_max + 2] work-queue heads (persistent form)
     int32_t *bucket;  // [kmax + 1] counting-sort buckets
@@ -283,6 +283,28 @@ __device__ __forceinline__ R row_reduce_scatter4(const R (&v)[NU], int i)
     w = w + dppmov<0x4E>(w);              // quad_perm [2,3,0,1]
     return w;
 }
+// Select-free form of the same scatter: lane i supplies its four addends in the exchange
+// order v[s] = addend of component xperm(i, s), where with b3, b2 the bits 3 and 2 of i
+//   xperm(i, 0) = 2 b3 + b2,  xperm(i, 1) = 2 b3 + 1 - b2,
+//   xperm(i, 2) = 2 (1 - b3) + 1 - b2,  xperm(i, 3) = 2 (1 - b3) + b2,
+// so that the row_mirror partner (bits 3..0 inverted) sends exactly the components this lane
+// keeps, and the row_half_mirror partner (bits 2..0 inverted) likewise; lane i receives the
+// row sum of component i >> 2.
+__host__ __device__ constexpr int xperm(int i, int s)
+{
+    const int b3 = (i >> 3) & 1, b2 = (i >> 2) & 1;
+    return s == 0 ? 2 * b3 + b2 : s == 1 ? 2 * b3 + 1 - b2 : s == 2 ? 2 * (1 - b3) + 1 - b2 : 2 * (1 - b3) + b2;
+}
+template <typename R>
+__device__ __forceinline__ R row_reduce_scatter4x(const R (&v)[NU])
+{
+    const R a0 = v[0] + dppmov<0x140>(v[2]);  // row_mirror
+    const R a1 = v[1] + dppmov<0x140>(v[3]);
+    R w = a0 + dppmov<0x141>(a1);             // row_half_mirror
+    w = w + dppmov<0xB1>(w);                  // quad_perm [1,0,3,2]
+    w = w + dppmov<0x4E>(w);                  // quad_perm [2,3,0,1]
+    return w;
+}
 // sum_q c[q] * (value of lane 4q of this row), q = 0..3
 template <typename R>
 __device__ __forceinline__ R rowdot4q(const R *c, R v, R acc)
@@ -375,27 +397,27 @@ __device__ __forceinline__ void proj_cone_ball(R &t, R &z0, R &z1, bool cone, R 
     z0 = a0 * bs;
     z1 = a1 * bs;
 }
-// FP32: one reciprocal square root per norm (v_rsq_f32) gives both the norm and its inverse,
-// and the ball test compares squares.
+// FP32: one reciprocal square root per norm (v_rsq_f32) gives both the norm and its inverse.
+// A bias of 1e-30 under the first root keeps it finite at z = 0 (its relative effect on a norm
+// is below 1e-30 / ||z||^2).  Outside the cone the projected t is (t + a ||z||) / (1 + a^2),
+// clamped at zero, which also covers the polar cone; the ball scale is min(1, rad / ||.||).
 template <>
 __device__ __forceinline__ void proj_cone_ball<float>(float &t, float &z0, float &z1, bool cone,
                                                       float a, float inv1a2, float rad)
 {
-    const float s2 = z0 * z0 + z1 * z1;
+    const float s2 = fmaf(z0, z0, fmaf(z1, z1, 1e-30f));
     const float rs = __builtin_amdgcn_rsqf(s2);
-    const float nz = s2 > 0.0f ? s2 * rs : 0.0f;
+    const float nz = s2 * rs;
     const bool inside = !cone || nz <= a * t;
-    const bool polar = a * nz <= -t;
-    const float tp = (t + a * nz) * inv1a2;
-    const float zs = s2 > 0.0f ? a * tp * rs : 0.0f;
-    const float t1 = inside ? t : (polar ? 0.0f : tp);
-    const float s1 = inside ? 1.0f : (polar ? 0.0f : zs);
-    const float a0 = z0 * s1, a1 = z1 * s1;
-    const float n2 = t1 * t1 + a0 * a0 + a1 * a1;
-    const float bs = n2 > rad * rad ? rad * __builtin_amdgcn_rsqf(n2) : 1.0f;
+    const float tp = fmaxf((t + a * nz) * inv1a2, 0.0f);
+    const float t1 = inside ? t : tp;
+    const float s1 = inside ? 1.0f : a * tp * rs;
+    const float n2 = fmaf(t1, t1, (s1 * s1) * s2);
+    const float bs = fminf(1.0f, rad * __builtin_amdgcn_rsqf(n2));
+    const float sb = s1 * bs;
     t = t1 * bs;
-    z0 = a0 * bs;
-    z1 = a1 * bs;
+    z0 = z0 * sb;
+    z1 = z1 * sb;
 }
 
 // Column i of A^-_k for the transposed product.  FP32: a per-lane LDS slot of 20 floats
@@ -768,6 +790,15 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
                                              : R(0);
     }
+    // coefficients of the control gradient in this lane's exchange order (see
+    // row_reduce_scatter4x): slot s holds control component xperm(i, s)
+    R rowBmX[NU], rowBqX[NU];
+    for (int s = 0; s < NU; ++s) {
+        const int q = xperm(i, s);
+        rowBmX[s] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
+        rowBqX[s] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
+                                              : R(0);
+    }
 
     const double sigma = a.sigma[b];  // buffered spectral estimate (preparation kernel)
 
@@ -802,7 +833,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // workgroup-uniform step sizes (from the preparation kernel) and weights: scalar registers
     const R alpha = a.stepsz[2 * b], beta = a.stepsz[2 * b + 1];
-    const R rho = a.rho_r, omr = a.omr_r, wprox = a.wprox_r, wep = a.wep_r;
+    const R rho = a.rho_r, wprox = a.wprox_r, wep = a.wep_r;
     const R cost = (isx && k == K - 1 && i == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
 
     // -------------------- PIPG_custom --------------------
@@ -907,11 +938,18 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     if (!node) ulo = uhi = R(0);
     else if (qi == 3) { ulo = slo; uhi = shi; }
     const bool thlane = dual && i == IY;  // lane of the CTCS multiplier theta_k
+    const R thcap = thlane ? INF : R(0);   // theta in [0, thcap]
 
     int iters = 0;
+    int since = 0;  // steps since the last stopping test
+    int cset = 0;   // stopping-test slot set of the next test
     for (int it = 1; it <= jmax; ++it) {
-        // fresh iterate of this step; waves beyond the last node keep these zeros
-        R xn = R(0), un = R(0), vx = R(0), vu = R(0);
+        ++since;
+        const bool test = check > 0 && since == check;
+        const bool before_test = check > 1 && since == check - 1;
+        // fresh iterate of this step (waves beyond the last node compute nothing and store
+        // nothing: their slots keep the zeros they started with)
+        R xn, un, vx, vu;
         if (wact) {
         // ---- projected gradient step on the primal variables ----
         const R phm1 = sl[Lds::PHI];  // phi_{k-1}[i] (zero row above the first node)
@@ -925,11 +963,12 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         g -= phm1;
         g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
         xn = xt - alpha * g;
-        // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i]
+        // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i],
+        // with the coefficients in this lane's exchange order
         {
             R gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = rowBm[q] * vphi + rowBq[q] * phm1;
-            const R gu = wprox * ut + row_reduce_scatter4<R>(gq, i);
+            for (int q = 0; q < NU; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
+            const R gu = wprox * ut + row_reduce_scatter4x<R>(gq);
             un = ut - alpha * gu;
         }
         if (pmask) {
@@ -955,46 +994,42 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         xn = clampbox(xn, xlo, xhi);
         un = clampbox(un, ulo, uhi);
+        // extrapolation 2z^ - z~ and relaxation z~ += rho (z^ - z~), in place
         vx = R(2) * xn - xt;
-        xt = omr * xt + rho * xn;
+        xt += rho * (xn - xt);
         vu = R(2) * un - ut;
-        ut = omr * ut + rho * un;
+        ut += rho * (un - ut);
         sl[Lds::VX] = vx;
         sl[Lds::VU] = vu;
         }  // wact
         __syncthreads();
-        R mupn = R(0), mumn = R(0), phn = R(0), thn = R(0);
         if (wact) {
         // ---- dual (proportional-integral) step ----
-        mupn = nup - alpha * (wep + vphi);
-        mumn = num - alpha * (wep - vphi);
+        R mupn = nup - alpha * (wep + vphi);
+        R mumn = num - alpha * (wep - vphi);
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
-        R r = rowdot15<R>(rowA, vx, R(0));  // A^-_k (2x^ - x~)_k
-        const R vnext = sl[Lds::VX + 16];   // zero beyond the last node
+        R r = rowdot15<R>(rowA, vx, wk);   // w^_k + A^-_k (2x^ - x~)_k
+        const R vnext = sl[Lds::VX + 16];  // zero beyond the last node
         r -= vnext;
         r = rowdot4q<R>(rowBm, vu, r);                  // B^-_k (2u^ - u~)_k
         r = rowdot4q<R>(rowBp, sl[Lds::VU + 16], r);   // B^+_k (2u^ - u~)_{k+1}
         r += (R(2) * mupn - nup) - (R(2) * mumn - num);
-        r += wk;
-        phn = vphi + beta * r;
-        thn = vth + beta * (vnext - vx - epsk);
-        thn = (thlane && thn > R(0)) ? thn : R(0);
-        vphi = omr * vphi + rho * phn;
-        nup = omr * nup + rho * mupn;
-        num = omr * num + rho * mumn;
-        vth = omr * vth + rho * thn;
+        const R phn = vphi + beta * r;
+        // theta: max(0, .) on the CTCS lane, zero on the others
+        const R thn = clampbox(vth + beta * ((vnext - vx) - epsk), R(0), thcap);
+        vphi += rho * (phn - vphi);
+        nup += rho * (mupn - nup);
+        num += rho * (mumn - num);
+        vth += rho * (thn - vth);
         sl[Lds::PHI + 16] = vphi;
         sl[Lds::TH + 16] = vth;
-        }  // wact
         // stopping test every `check` steps: infinity norms of (x, u, mu+, mu-) and of
         // (phi, theta) at j+1 and j and of their differences.  Lanes without a variable hold
         // zeros and the four lanes of a control hold identical values, so every lane enters
         // unmasked.  Row maxima by DPP, then one LDS atomic max per row on the bit patterns
         // (monotone for non-negative values); the slot set alternates between tests, the
         // other set is cleared for the next one.
-        const bool test = check > 0 && it % check == 0;
-        const int cset = test ? ((it / check) & 1) : 0;
         if (test) {
             const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
             const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
@@ -1011,7 +1046,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             if (t == 0)
                 for (int q = 0; q < 6; ++q) chk[8 * (cset ^ 1) + q] = 0;
         }
-        if (test || it == jmax || (check > 0 && (it + 1) % check == 0)) {
+        if (test || before_test || it == jmax) {
             sl[Lds::PX] = xn;
             sl[Lds::PU] = un;
             sl[Lds::PMP] = mupn;
@@ -1019,11 +1054,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             sl[Lds::PPH] = phn;
             sl[Lds::PTH] = thn;
         }
+        }  // wact
         __syncthreads();
         iters = it;
         if (test) {
             double n[6];
             for (int q = 0; q < 6; ++q) n[q] = from_max_bits<R>(chk[8 * cset + q]);
+            since = 0;
+            cset ^= 1;
             if (n[2] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[0], n[1]) &&
                 n[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[3], n[4]))
                 break;
@@ -1225,7 +1263,6 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.sigma = ws.sigma;
     a.stepsz = static_cast<R *>(ws.stepsz);
     a.rho_r = R(cfg.rho);
-    a.omr_r = R(1) - R(cfg.rho);
     a.wprox_r = R(cfg.w_prox);
     a.wep_r = R(cfg.w_ep);
     a.pipg_total = ws.pipg_total;
