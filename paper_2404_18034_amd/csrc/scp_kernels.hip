@@ -954,6 +954,15 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         // ---- projected gradient step on the primal variables ----
         const R phm1 = sl[Lds::PHI];  // phi_{k-1}[i] (zero row above the first node)
         const R thm1 = sl[Lds::TH];   // theta_{k-1} on lane IY
+        // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i],
+        // with the coefficients in this lane's exchange order (computed while the column of
+        // A^-_k is on its way from LDS)
+        {
+            R gq[NU];
+            for (int q = 0; q < NU; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
+            const R gu = wprox * ut + row_reduce_scatter4x<R>(gq);
+            un = ut - alpha * gu;
+        }
         R g = wprox * xt + cost;
         {
             R c[ColStore<R>::N];
@@ -963,14 +972,6 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         g -= phm1;
         g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
         xn = xt - alpha * g;
-        // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i],
-        // with the coefficients in this lane's exchange order
-        {
-            R gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
-            const R gu = wprox * ut + row_reduce_scatter4x<R>(gq);
-            un = ut - alpha * gu;
-        }
         if (pmask) {
             // leader inputs: members from lanes +1, +2 (row_shl); thrust from the control
             // lanes 0, 4, 8 (row_shr:4, own, row_shl:4)
@@ -1005,16 +1006,18 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         __syncthreads();
         if (wact) {
         // ---- dual (proportional-integral) step ----
+        const R vnext = sl[Lds::VX + 16];   // 2x^ - x~ of node k+1 (zero beyond the last node)
+        const R vunext = sl[Lds::VU + 16];  // 2u^ - u~ of node k+1
         R mupn = nup - alpha * (wep + vphi);
         R mumn = num - alpha * (wep - vphi);
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
         R r = rowdot15<R>(rowA, vx, wk);   // w^_k + A^-_k (2x^ - x~)_k
-        const R vnext = sl[Lds::VX + 16];  // zero beyond the last node
         r -= vnext;
-        r = rowdot4q<R>(rowBm, vu, r);                  // B^-_k (2u^ - u~)_k
-        r = rowdot4q<R>(rowBp, sl[Lds::VU + 16], r);   // B^+_k (2u^ - u~)_{k+1}
-        r += (R(2) * mupn - nup) - (R(2) * mumn - num);
+        r = rowdot4q<R>(rowBm, vu, r);      // B^-_k (2u^ - u~)_k
+        r = rowdot4q<R>(rowBp, vunext, r);  // B^+_k (2u^ - u~)_{k+1}
+        // (2 mu+^ - nu+) - (2 mu-^ - nu-)
+        r += R(2) * (mupn - mumn) - (nup - num);
         const R phn = vphi + beta * r;
         // theta: max(0, .) on the CTCS lane, zero on the others
         const R thn = clampbox(vth + beta * ((vnext - vx) - epsk), R(0), thcap);
