@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--mode", type=int, default=None,
                     help="dispatch mode (0 launches, 1 graph, 2 ordered, 3 persistent); "
                          "default: autotuned on the workload")
-    ap.add_argument("--occupancy", type=int, default=None, choices=[0, 4, 5],
+    ap.add_argument("--occupancy", type=int, default=None, choices=[0, 4, 5, 6],
                     help="subproblem register-budget variant with --mode (default 0)")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")

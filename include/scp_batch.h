@@ -87,9 +87,8 @@ typedef struct {
                                    handle computes no gradients and carves no scratch)     */
     int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */
     int32_t occupancy;          /* FP32 subproblem kernel variant: 0 = the compiler's
-                                   register budget, 4 or 5 = registers bounded for four or
-                                   five waves per SIMD (five lets four 5-wave workgroups
-                                   share a CU); FP64 always uses 0                        */
+                                   register budget, 4, 5 or 6 = registers bounded for that
+                                   many waves per SIMD; FP64 always uses 0                */
     int32_t grad_rk4_tangent;   /* how scp_batch_grad differentiates the discretization:
                                    0 = reverse (adjoint) sweep through the RK4 stages,
                                    1 = forward tangents along (alpha_mdot, T_max)          */
@@ -167,14 +166,14 @@ scp_status scp_batch_profile(scp_batch h, int enable);
 scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
 
 /* Autotuner.  Times the launch variants (mode, occupancy) = (1, 0), (2, 0), (3, 0), (1, 5),
- * (2, 5) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
+ * (2, 5), (1, 6), (2, 6) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
  * HIP events, solving `problem` into `solution` (whose contents are overwritten), and keeps
  * the fastest for later solves on this handle.  *variant_out receives its index and
  * ms_out[SCP_TUNE_VARIANTS] the measured milliseconds per variant (-1 where not timed).
  * With a non-NULL cache_path, a JSON-lines file keyed by (GPU arch, k_max, dtype,
  * early_exit, node_projections, batch) is consulted first -- a hit skips the timing -- and
  * the new result is appended.  Synchronizes the handle's stream. */
-#define SCP_TUNE_VARIANTS 5
+#define SCP_TUNE_VARIANTS 7
 scp_status scp_batch_autotune(scp_batch h, const scp_problem *problem, scp_solution *solution,
                               const char *cache_path, int32_t *variant_out, double *ms_out);
 

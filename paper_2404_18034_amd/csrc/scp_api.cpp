@@ -42,8 +42,8 @@ bool settings_ok(const scp_settings *s, std::string &why)
     }
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
     if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
-    if (s->occupancy != 0 && s->occupancy != 4 && s->occupancy != 5) {
-        why = "occupancy must be 0, 4 or 5";
+    if (s->occupancy != 0 && (s->occupancy < 4 || s->occupancy > 6)) {
+        why = "occupancy must be 0, 4, 5 or 6";
         return false;
     }
     if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
@@ -528,8 +528,8 @@ static std::string tune_key(scp_batch h, int batch)
     return k.str();
 }
 
-static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2};
-static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 5, 5};
+static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2, 1, 2};
+static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 5, 5, 6, 6};
 
 static int cache_lookup(const char *path, const std::string &key)
 {

@@ -371,6 +371,54 @@ __device__ __forceinline__ float rowdot15<float>(const float *c, float v, float 
     return acc;
 }
 
+// sum_{j<N} c[j] * (value of lane J0 + j of this row), in the order j = 0, 1, ...
+template <typename R, int J0, int N, int... J>
+__device__ __forceinline__ R rowdot_part_impl(const R *c, R v, R acc, std::integer_sequence<int, J...>)
+{
+    ((acc = acc + c[J] * rowb<J0 + J>(v)), ...);
+    return acc;
+}
+template <typename R, int J0, int N>
+__device__ __forceinline__ R rowdot_part(const R *c, R v, R acc)
+{
+    return rowdot_part_impl<R, J0, N>(c, v, acc, std::make_integer_sequence<int, N>{});
+}
+// FP32: lanes 0..7 and 8..14, one v_fmac_f32 with a DPP row_newbcast source each
+template <>
+__device__ __forceinline__ float rowdot_part<float, 0, 8>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ float rowdot_part<float, 8, 7>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %6 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %7 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]));
+    return acc;
+}
+
 // Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
 // specialization below uses the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ double proj_sqrt(double x) { return sqrt(x); }
@@ -436,6 +484,21 @@ struct ColStore<float> {
         float4 *o = reinterpret_cast<float4 *>(c);
         for (int n = 0; n < 4; ++n) o[n] = p[n];
     }
+    // entries 0..7 and 8..15 (the last is padding)
+    __device__ __forceinline__ void get_lo(float (&c)[8]) const
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(slot);
+        float4 *o = reinterpret_cast<float4 *>(c);
+        o[0] = p[0];
+        o[1] = p[1];
+    }
+    __device__ __forceinline__ void get_hi(float (&c)[8]) const
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(slot);
+        float4 *o = reinterpret_cast<float4 *>(c);
+        o[0] = p[2];
+        o[1] = p[3];
+    }
 };
 template <>
 struct ColStore<double> {
@@ -446,6 +509,15 @@ struct ColStore<double> {
     __device__ __forceinline__ void get(double (&o)[N]) const
     {
         for (int q = 0; q < NX; ++q) o[q] = c[q];
+    }
+    __device__ __forceinline__ void get_lo(double (&o)[8]) const
+    {
+        for (int q = 0; q < 8; ++q) o[q] = c[q];
+    }
+    __device__ __forceinline__ void get_hi(double (&o)[8]) const
+    {
+        for (int q = 0; q < 7; ++q) o[q] = c[8 + q];
+        o[7] = 0.0;
     }
 };
 
@@ -916,18 +988,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const R mdry = p[1];
     const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
     const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
-    const R ubT0 = rowb<0>(ubq), ubT1 = rowb<4>(ubq), ubT2 = rowb<8>(ubq);  // reference thrust
-    const bool thr = role == 5;
-    // leader inputs t_j = c_j + m_j * (member j, scaled): references and scales.  Every DPP
-    // exchange is evaluated by all lanes before any selection (a lane-dependent condition
-    // around it would mask out the lanes it reads from).  lc0 is also the reference a member
-    // subtracts when it reads its component back (the thrust leader is in no state set).
-    const R xb_p1 = dppmov<0x101>(xb), xb_p2 = dppmov<0x102>(xb);  // row_shl: lanes +1, +2
-    const R lc0 = thr ? ubT0 : xb;
-    const R lc1 = thr ? ubT1 : xb_p1;
-    const R lc2 = thr ? ubT2 : (role == 3 ? R(0) : xb_p2);
-    const R lm = thr ? pT : pxi;
-    const R lm2 = role == 3 ? R(0) : lm;
+    const bool thr = role == 5, tilt = role == 3;
     // box applied to the fresh iterate after the set projections: fixed boundary values
     // (lo = hi), the dry-mass bound, zero on lanes without a state variable; the dilation
     // bounds on the s lanes, zero on rows without a node
@@ -937,8 +998,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     else if (grp == 1) xlo = (mdry - xb) * ipxi;
     if (!node) ulo = uhi = R(0);
     else if (qi == 3) { ulo = slo; uhi = shi; }
-    const bool thlane = dual && i == IY;  // lane of the CTCS multiplier theta_k
-    const R thcap = thlane ? INF : R(0);   // theta in [0, thcap]
+    // theta lives on the CTCS lane of the dynamics rows; elsewhere an infinite epsilon keeps
+    // max(0, .) of its update at zero
+    if (!(dual && i == IY)) epsk = INF;
 
     int iters = 0;
     int since = 0;  // steps since the last stopping test
@@ -963,31 +1025,40 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             const R gu = wprox * ut + row_reduce_scatter4x<R>(gq);
             un = ut - alpha * gu;
         }
+        // (A^-_k)^T phi_k, column i, in two halves of the column (fewer live registers)
         R g = wprox * xt + cost;
         {
-            R c[ColStore<R>::N];
-            colA.get(c);
-            g = rowdot15<R>(c, vphi, g);  // (A^-_k)^T phi_k, column i
+            R c[8];
+            colA.get_lo(c);
+            g = rowdot_part<R, 0, 8>(c, vphi, g);
+        }
+        {
+            R c[8];
+            colA.get_hi(c);
+            g = rowdot_part<R, 8, 7>(c, vphi, g);
         }
         g -= phm1;
         g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
         xn = xt - alpha * g;
         if (pmask) {
-            // leader inputs: members from lanes +1, +2 (row_shl); thrust from the control
-            // lanes 0, 4, 8 (row_shr:4, own, row_shl:4)
-            const R xn_p1 = dppmov<0x101>(xn), xn_p2 = dppmov<0x102>(xn);
-            const R un_m4 = dppmov<0x114>(un), un_p4 = dppmov<0x104>(un);
-            const R in0 = thr ? un_m4 : xn;
-            const R in1 = thr ? un : xn_p1;
-            const R in2 = thr ? un_p4 : xn_p2;
-            R t0 = lc0 + lm * in0, t1 = lc1 + lm * in1, t2 = lc2 + lm2 * in2;
+            // every lane forms its unscaled value (state x = x_ref + p_x x^, control
+            // u = u_ref + p_u u^); the leader gathers its members: state sets from lanes +1,
+            // +2 (row_shl), thrust from the control lanes 0, 4, 8 (row_shr:4, own, row_shl:4).
+            // Every DPP exchange is evaluated by all lanes before any selection (a
+            // lane-dependent condition around it would mask out the lanes it reads from).
+            const R xs = xb + pxi * xn, us = ubq + pT * un;
+            const R xs_p1 = dppmov<0x101>(xs), xs_p2 = dppmov<0x102>(xs);
+            const R us_m4 = dppmov<0x114>(us), us_p4 = dppmov<0x104>(us);
+            R t0 = thr ? us_m4 : xs;
+            R t1 = thr ? us : xs_p1;
+            R t2 = thr ? us_p4 : (tilt ? R(0) : xs_p2);
             // glide-slope cone; tilt disk; rate ball; thrust: gimbal cone, then the ball
             // ||T|| <= T_max centred at its apex
             proj_cone_ball<R>(t0, t1, t2, g_cone, g_a, g_inv, g_rad);
             // members read their component from the leader (row_shr by their slot)
             const R t1_m1 = dppmov<0x111>(t1), t2_m2 = dppmov<0x112>(t2);
             const R o = gw == 0 ? t0 : (gw == 1 ? t1_m1 : t2_m2);
-            if (grp >= 2 && grp <= 4) xn = (o - lc0) * ipxi;
+            if (grp >= 2 && grp <= 4) xn = (o - xb) * ipxi;
             if (pmask & 16) {
                 const R T0 = rowb<4>(t0), T1 = rowb<4>(t1), T2 = rowb<4>(t2);
                 if (qi < 3) un = ((qi == 0 ? T0 : (qi == 1 ? T1 : T2)) - ubq) * ipT;
@@ -1020,7 +1091,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         r += R(2) * (mupn - mumn) - (nup - num);
         const R phn = vphi + beta * r;
         // theta: max(0, .) on the CTCS lane, zero on the others
-        const R thn = clampbox(vth + beta * ((vnext - vx) - epsk), R(0), thcap);
+        const R thn = fmax(vth + beta * ((vnext - vx) - epsk), R(0));
         vphi += rho * (phn - vphi);
         nup += rho * (mupn - nup);
         num += rho * (mumn - num);
@@ -1190,13 +1261,17 @@ static size_t prep_smem_bytes(int kmax, size_t rsize)
            rsize * KR * 16 * col;
 }
 
-// Subproblem launch with the register-budget variant: occupancy 4 or 5 bounds the kernel to
-// that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
+// Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
+// to that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
 template <typename R, int MAXT>
 static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
                               const Args<R> &a)
 {
     if constexpr (sizeof(R) == 4) {
+        if (occupancy == 6) {
+            subproblem_kernel<R, MAXT, 6><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            return;
+        }
         if (occupancy == 5) {
             subproblem_kernel<R, MAXT, 5><<<dim3(B), dim3(threads), smem, stream>>>(a);
             return;

@@ -107,3 +107,13 @@ def test_gradient_settings_validated(lib):
     assert api.workspace_bytes(bad) == 0
     bad = api.make_settings(dict(cfg, grad_ckpt_every=201), "f32", 20, 64)
     assert api.workspace_bytes(bad) == 0
+
+
+def test_tuning_variant_count_matches_header():
+    import re
+    from paper_2404_18034_amd import api
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "scp_batch.h")).read()
+    n = int(re.search(r"#define SCP_TUNE_VARIANTS (\d+)", hdr).group(1))
+    assert n == len(api.TUNE_VARIANTS)
+    k = int(re.search(r"#define SCP_KERNEL_CLASSES (\d+)", hdr).group(1))
+    assert k == len(api.KERNEL_CLASSES)

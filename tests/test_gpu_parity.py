@@ -264,7 +264,7 @@ def test_invalid_arguments_raise():
     s.close()
 
 
-@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (0, 5), (2, 5)])
+@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (0, 5), (2, 5), (0, 6)])
 def test_dispatch_modes_match_plain_launches(mode, occupancy):
     # graph replay, K-ordered dispatch and the persistent work queue compute the same thing as
     # plain launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
