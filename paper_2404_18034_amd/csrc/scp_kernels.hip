@@ -605,6 +605,76 @@ __device__ __forceinline__ void keep_narrow(T (&c)[N])
 {
     for (int n = 0; n < N; ++n) asm volatile("" : "+v"(c[n]));
 }
+// FP64 chain: acc += double(c[j]) * (lane 1*j of v) for j = 0..14, one conversion and one
+// v_fmac_f64_dpp (DPP row_newbcast on the FP64 source) per term
+__device__ __forceinline__ double pw_chain15(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_cvt_f64_f32 %[t0], %[c0]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c1]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c2]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c3]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c4]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c5]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c6]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c7]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c8]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c9]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c10]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c11]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c12]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c13]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c14]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+        : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]), [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]), [c11] "v"(c[11]), [c12] "v"(c[12]), [c13] "v"(c[13]), [c14] "v"(c[14]));
+    return acc;
+}
+// FP64 chain: acc += double(c[j]) * (lane 4*j of v) for j = 0..3, one conversion and one
+// v_fmac_f64_dpp (DPP row_newbcast on the FP64 source) per term
+__device__ __forceinline__ double pw_chain4q(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_cvt_f64_f32 %[t0], %[c0]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c1]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t0], %[c2]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_cvt_f64_f32 %[t1], %[c3]\n\t"
+        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+        : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double pw_rowdot<NX, 1, float>(const float *c, double v, double acc)
+{
+    return pw_chain15(c, v, acc);
+}
+template <>
+__device__ __forceinline__ double pw_rowdot<NU, 4, float>(const float *c, double v, double acc)
+{
+    return pw_chain4q(c, v, acc);
+}
 // sum over the 64 lanes of a wave on every lane: row sums (symmetric exchanges), then the
 // four row sums added in row order
 __device__ __forceinline__ double wave_sum(double v)
