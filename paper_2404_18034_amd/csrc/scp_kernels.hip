@@ -887,7 +887,7 @@ prepare_kernel(Args<R> a)
 // The block products inside an interval use row broadcasts of register values (DPP);
 // only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
-template <typename R, int MAXT>
+template <typename R, int MAXT, bool FAIR = false>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
 {
@@ -1077,6 +1077,17 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     int cset = 0;   // stopping-test slot set of the next test
     for (int it = 1; it <= jmax; ++it) {
         ++since;
+        if constexpr (FAIR) {
+            // rotate the wave priority every 8 steps: the workgroups sharing a CU then take
+            // turns at the head of the issue order instead of the oldest one running ahead and
+            // the last one finishing alone
+            switch ((it >> 3) & 3) {
+            case 0: __builtin_amdgcn_s_setprio(0); break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            case 2: __builtin_amdgcn_s_setprio(1); break;
+            default: __builtin_amdgcn_s_setprio(3); break;
+            }
+        }
         const bool test = check > 0 && since == check;
         const bool before_test = check > 1 && since == check - 1;
         // fresh iterate of this step (waves beyond the last node compute nothing and store
@@ -1250,7 +1261,8 @@ subproblem_kernel(Args<R> a)
     // the hardware issues workgroups as earlier ones retire, so the longest instances start
     // first and the short ones fill in behind them
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]) : blockIdx.x;
-    subproblem_body<R, MAXT>(a, b, smem_raw);
+    // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
+    subproblem_body<R, MAXT, (WPE >= 6)>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
