@@ -1078,10 +1078,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     for (int it = 1; it <= jmax; ++it) {
         ++since;
         if constexpr (FAIR) {
-            // rotate the wave priority every 8 steps: the workgroups sharing a CU then take
+            // rotate the wave priority every 16 steps: the workgroups sharing a CU then take
             // turns at the head of the issue order instead of the oldest one running ahead and
             // the last one finishing alone
-            switch ((it >> 3) & 3) {
+            switch ((it >> 4) & 3) {
             case 0: __builtin_amdgcn_s_setprio(0); break;
             case 1: __builtin_amdgcn_s_setprio(2); break;
             case 2: __builtin_amdgcn_s_setprio(1); break;
