@@ -575,115 +575,31 @@ __device__ __forceinline__ double from_max_bits(unsigned long long b)
     return __longlong_as_double((long long)b);
 }
 
-template <int S, typename C, int... J>
-__device__ __forceinline__ void pw_rowdot_impl(const C *c, double v, double &acc,
-                                               std::integer_sequence<int, J...>)
-{
-    ((acc = fma(double(c[J]), rowb<S * J>(v), acc)), ...);
-}
-// LDS of the preparation kernel for a workgroup of at most MAXT lanes: per-lane FP64 slots
-// of the power iterate (x part Z and u part U, rows 0 .. ROWS, the row after the last
-// workgroup row zero) and of phi and theta (rows -1 .. ROWS-1, row -1 zero), then the
-// reduction scratch.
-template <int MAXT>
+// LDS of the preparation kernel for a workgroup of at most MAXT lanes: per-lane slots, in the
+// working precision, of the power iterate (x part Z and u part U, rows 0 .. ROWS, the row
+// after the last workgroup row zero) and of phi and theta (rows -1 .. ROWS-1, row -1 zero),
+// then the FP64 reduction scratch.
+template <typename R, int MAXT>
 struct PrepLds {
     static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
-    static constexpr int Z = 0, U = SLOTS, P = 2 * SLOTS, T = 3 * SLOTS, RED = 4 * SLOTS;
-    static constexpr size_t BYTES = (RED + 128) * sizeof(double);
+    static constexpr int Z = 0, U = SLOTS, P = 2 * SLOTS, T = 3 * SLOTS;
+    static constexpr size_t RED_BYTES = (4 * SLOTS * sizeof(R) + 15) / 16 * 16;
+    static constexpr size_t BYTES = RED_BYTES + 128 * sizeof(double);
 };
-// sum_j c[j] * (lane S*j of this row's value of v), FP64, in the order j = 0, 1, ...
-template <int N, int S, typename C>
-__device__ __forceinline__ double pw_rowdot(const C *c, double v, double acc)
+// sum over the 64 lanes of a wave, on every lane: row sums in the working precision
+// (symmetric exchanges), then the four row sums added in FP64 in row order
+template <typename R>
+__device__ __forceinline__ double wave_sum(R v)
 {
-    pw_rowdot_impl<S>(c, v, acc, std::make_integer_sequence<int, N>{});
-    return acc;
-}
-// marks the values of c as redefined at this point (no instruction is emitted), so that a
-// conversion of them is not hoisted out of the enclosing loop
-template <typename T, int N>
-__device__ __forceinline__ void keep_narrow(T (&c)[N])
-{
-    for (int n = 0; n < N; ++n) asm volatile("" : "+v"(c[n]));
-}
-// FP64 chain: acc += double(c[j]) * (lane 1*j of v) for j = 0..14, one conversion and one
-// v_fmac_f64_dpp (DPP row_newbcast on the FP64 source) per term
-__device__ __forceinline__ double pw_chain15(const float *c, double v, double acc)
-{
-    double t0, t1;
-    asm volatile(
-        "s_nop 4\n\t"
-        "v_cvt_f64_f32 %[t0], %[c0]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c1]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c2]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c3]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c4]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c5]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c6]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c7]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c8]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c9]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c10]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c11]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c12]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c13]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c14]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
-        : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
-        : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]), [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]), [c11] "v"(c[11]), [c12] "v"(c[12]), [c13] "v"(c[13]), [c14] "v"(c[14]));
-    return acc;
-}
-// FP64 chain: acc += double(c[j]) * (lane 4*j of v) for j = 0..3, one conversion and one
-// v_fmac_f64_dpp (DPP row_newbcast on the FP64 source) per term
-__device__ __forceinline__ double pw_chain4q(const float *c, double v, double acc)
-{
-    double t0, t1;
-    asm volatile(
-        "s_nop 4\n\t"
-        "v_cvt_f64_f32 %[t0], %[c0]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c1]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t0], %[c2]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t0] row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_cvt_f64_f32 %[t1], %[c3]\n\t"
-        "v_fmac_f64_dpp %[acc], %[v], %[t1] row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-        : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
-        : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]));
-    return acc;
-}
-template <>
-__device__ __forceinline__ double pw_rowdot<NX, 1, float>(const float *c, double v, double acc)
-{
-    return pw_chain15(c, v, acc);
-}
-template <>
-__device__ __forceinline__ double pw_rowdot<NU, 4, float>(const float *c, double v, double acc)
-{
-    return pw_chain4q(c, v, acc);
-}
-// sum over the 64 lanes of a wave on every lane: row sums (symmetric exchanges), then the
-// four row sums added in row order
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v = row_allreduce<double>(v);
-    auto lane = [&](int l) {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-        return __hiloint2double(hi, lo);
+    v = row_allreduce<R>(v);
+    auto lane = [&](int l) -> double {
+        if constexpr (sizeof(R) == 4) {
+            return double(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)));
+        } else {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+            return __hiloint2double(hi, lo);
+        }
     };
     return ((lane(0) + lane(16)) + lane(32)) + lane(48);
 }
@@ -693,8 +609,8 @@ __device__ __forceinline__ double wave_sum(double v)
 // convergence test of the current reference (an instance that has finished gets its outputs
 // and final status here), then the customized power iteration that bounds the spectral norm
 // of the subproblem's constraint operator; the buffered estimate goes to the workspace.  It
-// is a kernel of its own so that its FP64 temporaries do not count against the register
-// budget of the PIPG iteration.
+// is a kernel of its own so that its registers (the FP64 reductions of the test, the
+// power-iteration blocks) do not count against the register budget of the PIPG iteration.
 // ------------------------------------------------------------------------------------------
 template <typename R, int MAXT>
 __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsigned char *smem_raw)
@@ -705,9 +621,9 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
     const bool wact = ((t >> 6) << 2) < K;
-    using Lds = PrepLds<MAXT>;
-    double *sl = reinterpret_cast<double *>(smem_raw) + t;       // this lane's exchange slots
-    double *red = reinterpret_cast<double *>(smem_raw) + Lds::RED;  // [16 waves * 8]
+    using Lds = PrepLds<R, MAXT>;
+    R *sl = reinterpret_cast<R *>(smem_raw) + t;                            // exchange slots
+    double *red = reinterpret_cast<double *>(smem_raw + Lds::RED_BYTES);  // [16 waves * 8]
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -777,16 +693,19 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
                                              : R(0);
     }
 
-    // -------------------- customized power iteration (FP64) --------------------
+    // -------------------- customized power iteration --------------------
     // z = (x, u, mu+, mu-) starts at all ones: x_k on lane i of row k, u_k[q] on lanes
     // 4q..4q+3 of row k, mu+- of dynamics row (k, i) on the dual lanes.  Each step forms
     // phi = H z / sigma (dynamics rows; theta for the CTCS rows) and z' = H^T phi, where
-    // mu+' = phi and mu-' = -phi; the block products use row broadcasts of the FP64 iterate,
-    // the neighbouring rows pass through this lane's LDS slots.  Two barriers per step.
+    // mu+' = phi and mu-' = -phi; the block products use row broadcasts of the iterate, the
+    // neighbouring rows pass through this lane's LDS slots.  Two barriers per step.  The
+    // iterate and the products are in the working precision (FP32: 1/sigma is rounded once
+    // per step and multiplied); the squared norm is summed over each row in the working
+    // precision and over the rows in FP64; sigma and the stopping test are FP64.
     const int KR = (kmax + 3) / 4 * 4;
     const bool thlane = dual && i == IY;
-    double zx = isx ? 1.0 : 0.0, zu = node ? 1.0 : 0.0;
-    double dmu = 0.0;  // mu+ - mu- of this dynamics row
+    R zx = isx ? R(1) : R(0), zu = node ? R(1) : R(0);
+    R dmu = R(0);  // mu+ - mu- of this dynamics row
     double sigma;
     {
         double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NU) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
@@ -796,60 +715,66 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     sl[Lds::Z] = zx;
     sl[Lds::U] = zu;
     if (t < 16) {
-        sl[Lds::Z + KR * 16] = 0.0;  // row after the last workgroup row
-        sl[Lds::U + KR * 16] = 0.0;
-        sl[Lds::P] = 0.0;            // row -1
-        sl[Lds::T] = 0.0;
+        sl[Lds::Z + KR * 16] = R(0);  // row after the last workgroup row
+        sl[Lds::U + KR * 16] = R(0);
+        sl[Lds::P] = R(0);            // row -1
+        sl[Lds::T] = R(0);
     }
     __syncthreads();
     double sstar = sigma;
     const int nw = (blockDim.x + 63) >> 6;
     for (int it = 1; it <= a.power_iters_max; ++it) {
-        // FP32 blocks are widened where they are used: widening them once, outside the
-        // loop, would take twice their registers (the empty asm marks them as redefined)
-        if constexpr (sizeof(R) == 4) {
-            keep_narrow(rowA);
-            keep_narrow(rowBm);
-            keep_narrow(rowBp);
-            keep_narrow(rowBq);
-        }
-        double ph = 0.0, thv = 0.0;
+        R ph = R(0), thv = R(0);
         if (wact) {
             // A^-_k z_k - z_{k+1} + B^-_k u_k + B^+_k u_{k+1} + (mu+ - mu-), divided by sigma
-            const double zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
-            double r = pw_rowdot<NX, 1>(rowA, zx, 0.0);
+            const R zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
+            R r = rowdot15<R>(rowA, zx, R(0));
             r -= zxn;
-            r = pw_rowdot<NU, 4>(rowBm, zu, r);
-            r = pw_rowdot<NU, 4>(rowBp, zun, r);
+            r = rowdot4q<R>(rowBm, zu, r);
+            r = rowdot4q<R>(rowBp, zun, r);
             r += dmu;
-            ph = dual ? r / sigma : 0.0;
-            thv = thlane ? (zxn - zx) / sigma : 0.0;
+            if constexpr (sizeof(R) == 8) {
+                ph = dual ? r / sigma : 0.0;
+                thv = thlane ? (zxn - zx) / sigma : 0.0;
+            } else {
+                const R isg = R(1.0 / sigma);
+                ph = dual ? r * isg : R(0);
+                thv = thlane ? (zxn - zx) * isg : R(0);
+            }
         }
         sl[Lds::P + 16] = ph;
         sl[Lds::T + 16] = thv;
         __syncthreads();
-        double q2 = 0.0;
+        R q2 = R(0);
         if (wact) {
-            const double phm = sl[Lds::P], thm = sl[Lds::T];  // row k-1 (zero above node 0)
+            const R phm = sl[Lds::P], thm = sl[Lds::T];  // row k-1 (zero above node 0)
             // x part: (A^-_k)^T phi_k - phi_{k-1}, and theta_{k-1} - theta_k on the y lane
-            R c[ColStore<R>::N];
-            colA.get(c);
-            double r = pw_rowdot<NX, 1>(c, ph, 0.0);
+            R r;
+            {
+                R c[8];
+                colA.get_lo(c);
+                r = rowdot_part<R, 0, 8>(c, ph, R(0));
+            }
+            {
+                R c[8];
+                colA.get_hi(c);
+                r = rowdot_part<R, 8, 7>(c, ph, r);
+            }
             r -= phm;
             r -= thv;
             r += thm;
-            zx = isx ? r : 0.0;
+            zx = isx ? r : R(0);
             // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
-            double gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = double(rowBm[q]) * ph + double(rowBq[q]) * phm;
-            const double zq = row_reduce_scatter4<double>(gq, i);
-            zu = node ? zq : 0.0;
+            R gq[NU];
+            for (int q = 0; q < NU; ++q) gq[q] = rowBm[q] * ph + rowBq[q] * phm;
+            const R zq = row_reduce_scatter4<R>(gq, i);
+            zu = node ? zq : R(0);
             dmu = ph + ph;
-            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : 0.0) + (ph * ph + ph * ph);
+            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : R(0)) + (ph * ph + ph * ph);
         }
         sl[Lds::Z] = zx;
         sl[Lds::U] = zu;
-        const double wsum = wave_sum(q2);
+        const double wsum = wave_sum<R>(q2);
         if ((t & 63) == 0) red[t >> 6] = wsum;
         __syncthreads();
         double s2 = red[0];
@@ -1339,8 +1264,13 @@ static size_t prep_smem_bytes(int kmax, size_t rsize)
     const int maxt = qp_maxt(kmax);
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
-    return (maxt == 320 ? PrepLds<320>::BYTES : (maxt == 640 ? PrepLds<640>::BYTES : PrepLds<1024>::BYTES)) +
-           rsize * KR * 16 * col;
+    const size_t stage = rsize == 4 ? (maxt == 320 ? PrepLds<float, 320>::BYTES
+                                                   : (maxt == 640 ? PrepLds<float, 640>::BYTES
+                                                                  : PrepLds<float, 1024>::BYTES))
+                                    : (maxt == 320 ? PrepLds<double, 320>::BYTES
+                                                   : (maxt == 640 ? PrepLds<double, 640>::BYTES
+                                                                  : PrepLds<double, 1024>::BYTES));
+    return stage + rsize * KR * 16 * col;
 }
 
 // Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
