@@ -305,6 +305,42 @@ __device__ __forceinline__ R row_reduce_scatter4x(const R (&v)[NU])
     w = w + dppmov<0x4E>(w);                  // quad_perm [2,3,0,1]
     return w;
 }
+// Interleaved control layout of the subproblem kernel: component c of the node's controls on
+// lanes c, c+4, c+8 and c+12 of its row; the copy on lanes 4..7 is the one that is read.
+// Reduce-scatter onto it: lane i receives the row sum of component i & 3.  Lane i supplies its
+// four addends in the order v[s] = addend of component xpermi(i, s), where with b0, b1 the
+// bits 0 and 1 of i
+//   xpermi(i, 0) = b0 + 2 b1,  xpermi(i, 1) = b0 + 2 (1 - b1),
+//   xpermi(i, 2) = (1 - b0) + 2 b1,  xpermi(i, 3) = (1 - b0) + 2 (1 - b1),
+// so that the partner across bit 0 sends exactly the two components this lane keeps and the
+// partner across bit 1 the one it keeps after that; the four quads are then summed by row
+// rotations by 4 and by 8 (the copies may differ in the last bit).
+__host__ __device__ constexpr int xpermi(int i, int s)
+{
+    const int b0 = i & 1, b1 = (i >> 1) & 1;
+    return s == 0 ? b0 + 2 * b1 : s == 1 ? b0 + 2 * (1 - b1) : s == 2 ? (1 - b0) + 2 * b1 : (1 - b0) + 2 * (1 - b1);
+}
+template <typename R>
+__device__ __forceinline__ R row_reduce_scatter4i(const R (&v)[NU])
+{
+    const R a0 = v[0] + dppmov<0xB1>(v[2]);  // quad_perm [1,0,3,2]
+    const R a1 = v[1] + dppmov<0xB1>(v[3]);
+    R w = a0 + dppmov<0x4E>(a1);             // quad_perm [2,3,0,1]
+    w = w + dppmov<0x124>(w);                // row_ror:4
+    w = w + dppmov<0x128>(w);                // row_ror:8
+    return w;
+}
+// sum_q c[q] * (value of lane 4 + q of this row), q = 0..3: a control product in the
+// interleaved layout
+template <typename R>
+__device__ __forceinline__ R rowdot4c(const R *c, R v, R acc)
+{
+    acc = acc + c[0] * rowb<4>(v);
+    acc = acc + c[1] * rowb<5>(v);
+    acc = acc + c[2] * rowb<6>(v);
+    acc = acc + c[3] * rowb<7>(v);
+    return acc;
+}
 // sum_q c[q] * (value of lane 4q of this row), q = 0..3
 template <typename R>
 __device__ __forceinline__ R rowdot4q(const R *c, R v, R acc)
@@ -340,6 +376,19 @@ __device__ __forceinline__ float rowdot4q<float>(const float *c, float v, float 
         "v_fmac_f32_dpp %0, %1, %3 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %4 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %5 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ float rowdot4c<float>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
         : "+v"(acc)
         : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
     return acc;
@@ -843,10 +892,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // -------------------- load the subproblem into registers --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
-    R rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    R rowA[NX], rowBm[NU], rowBp[NU];
     ColStore<R> colA{myCol};
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
-    // (forward product); rowBq: row i of B^+_{k-1} (control gradient of node k)
+    // (forward product)
     for (int q = 0; q < NX; ++q) {
         colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
         rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
@@ -854,14 +903,12 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     for (int q = 0; q < NU; ++q) {
         rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
         rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
-        rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
-                                             : R(0);
     }
-    // coefficients of the control gradient in this lane's exchange order (see
-    // row_reduce_scatter4x): slot s holds control component xperm(i, s)
+    // coefficients of the control gradient (row i of B^-_k and of B^+_{k-1}) in this lane's
+    // exchange order (see row_reduce_scatter4i): slot s holds control component xpermi(i, s)
     R rowBmX[NU], rowBqX[NU];
     for (int s = 0; s < NU; ++s) {
-        const int q = xperm(i, s);
+        const int q = xpermi(i, s);
         rowBmX[s] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
         rowBqX[s] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
                                               : R(0);
@@ -871,7 +918,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // boundary values, bounds, reference values
     const R xb = isx ? a.x[xoff + i] : R(0);
-    const int qi = i >> 2;  // control component of this lane (lanes 4q..4q+3 hold u_q)
+    // control component of this lane (interleaved: lanes q, q+4, q+8, q+12 hold u_q; the
+    // copy on lanes 4..7 is the one the products, the projections and the outputs use)
+    const int qi = i & 3;
     const R ubq = node ? a.u[uoff + qi] : R(0);
     const R ub3 = node ? a.u[uoff + 3] : R(0);
     bool fixed = false;
@@ -959,10 +1008,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
     // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
     // Each set is projected once, by its leader lane: glide slope by lane 1 (r), tilt by lane
-    // 9 (q2, q3), rate by lane 11 (w), and thrust by lane 4 (a velocity lane, in no state
-    // set); the leader receives the other members from lanes +1, +2 (thrust: from the control
-    // lanes 0, 4, 8) and the members read their component back.  Members that are fixed
-    // boundary values keep them.
+    // 9 (q2, q3), rate by lane 11 (w), and thrust by lane 4, which with lanes 5 and 6 holds
+    // the read copy of T (velocity lanes, in no state set, stand in for it during the
+    // projection).  Each leader receives its members from lanes +1, +2 and the members read
+    // their component back.  Members that are fixed boundary values keep them.
     int grp = 0, gw = 0;  // member group of this lane (1 mass, 2 glide, 3 tilt, 4 rate), slot
     if (isx && !fixed) {
         if (i == 0) grp = (pmask & 1) ? 1 : 0;
@@ -970,6 +1019,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         else if (i == 9 || i == 10) { grp = (pmask & 4) ? 3 : 0; gw = i - 9; }
         else if (i >= 11 && i <= 13) { grp = (pmask & 8) ? 4 : 0; gw = i - 11; }
     }
+    const bool tmem = node && (pmask & 16) && i >= 4 && i <= 6;  // thrust member, slot i - 4
+    if (tmem) gw = i - 4;
     const int role = (i == 1 && (pmask & 2)) ? 2 : (i == 9 && (pmask & 4)) ? 3
                    : (i == 11 && (pmask & 8)) ? 4 : (i == 4 && (pmask & 16)) ? 5 : 0;
     const R INF = R(INFINITY);
@@ -981,9 +1032,13 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                               : (role == 4 ? p[17] : (role == 5 ? p[13] : INF));
     const bool g_cone = role == 2 || role == 5;
     const R mdry = p[1];
-    const R pxi = R(a.px[isx ? i : 0]), ipxi = R(1.0 / a.px[isx ? i : 0]);
-    const R pT = R(a.pu[0]), ipT = R(1.0 / a.pu[0]);
-    const bool thr = role == 5, tilt = role == 3;
+    const R ipxi = R(1.0 / a.px[isx ? i : 0]);
+    const bool tilt = role == 3;
+    // affine map between this lane's scaled iterate and the physical value the projections
+    // act on: x = x_ref + p_x x^ (state lanes), T = u_ref + p_u u^ (thrust lanes 4..6)
+    const R mb = tmem ? ubq : xb;
+    const R msc = tmem ? R(a.pu[qi]) : R(a.px[isx ? i : 0]);
+    const R imsc = tmem ? R(1.0 / a.pu[qi]) : ipxi;
     // box applied to the fresh iterate after the set projections: fixed boundary values
     // (lo = hi), the dry-mass bound, zero on lanes without a state variable; the dilation
     // bounds on the s lanes, zero on rows without a node
@@ -1028,7 +1083,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         {
             R gq[NU];
             for (int q = 0; q < NU; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
-            const R gu = wprox * ut + row_reduce_scatter4x<R>(gq);
+            const R gu = wprox * ut + row_reduce_scatter4i<R>(gq);
             un = ut - alpha * gu;
         }
         // (A^-_k)^T phi_k, column i, in two halves of the column (fewer live registers)
@@ -1047,28 +1102,24 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
         xn = xt - alpha * g;
         if (pmask) {
-            // every lane forms its unscaled value (state x = x_ref + p_x x^, control
-            // u = u_ref + p_u u^); the leader gathers its members: state sets from lanes +1,
-            // +2 (row_shl), thrust from the control lanes 0, 4, 8 (row_shr:4, own, row_shl:4).
-            // Every DPP exchange is evaluated by all lanes before any selection (a
-            // lane-dependent condition around it would mask out the lanes it reads from).
-            const R xs = xb + pxi * xn, us = ubq + pT * un;
-            const R xs_p1 = dppmov<0x101>(xs), xs_p2 = dppmov<0x102>(xs);
-            const R us_m4 = dppmov<0x114>(us), us_p4 = dppmov<0x104>(us);
-            R t0 = thr ? us_m4 : xs;
-            R t1 = thr ? us : xs_p1;
-            R t2 = thr ? us_p4 : (tilt ? R(0) : xs_p2);
+            // every lane forms its physical value (the thrust lanes 4..6 that of their control
+            // component, the others that of their state variable); each leader gathers its
+            // set from itself and lanes +1, +2 (row_shl).  Every DPP exchange is evaluated by
+            // all lanes before any selection (a lane-dependent condition around it would mask
+            // out the lanes it reads from).
+            const R s0 = mb + msc * (tmem ? un : xn);
+            const R s1 = dppmov<0x101>(s0), s2 = dppmov<0x102>(s0);
+            R t0 = s0, t1 = s1;
+            R t2 = tilt ? R(0) : s2;
             // glide-slope cone; tilt disk; rate ball; thrust: gimbal cone, then the ball
             // ||T|| <= T_max centred at its apex
             proj_cone_ball<R>(t0, t1, t2, g_cone, g_a, g_inv, g_rad);
             // members read their component from the leader (row_shr by their slot)
             const R t1_m1 = dppmov<0x111>(t1), t2_m2 = dppmov<0x112>(t2);
             const R o = gw == 0 ? t0 : (gw == 1 ? t1_m1 : t2_m2);
-            if (grp >= 2 && grp <= 4) xn = (o - xb) * ipxi;
-            if (pmask & 16) {
-                const R T0 = rowb<4>(t0), T1 = rowb<4>(t1), T2 = rowb<4>(t2);
-                if (qi < 3) un = ((qi == 0 ? T0 : (qi == 1 ? T1 : T2)) - ubq) * ipT;
-            }
+            const R v = (o - mb) * imsc;
+            if (grp >= 2 && grp <= 4) xn = v;
+            if (tmem) un = v;
         }
         xn = clampbox(xn, xlo, xhi);
         un = clampbox(un, ulo, uhi);
@@ -1091,8 +1142,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         mumn = mumn > R(0) ? mumn : R(0);
         R r = rowdot15<R>(rowA, vx, wk);   // w^_k + A^-_k (2x^ - x~)_k
         r -= vnext;
-        r = rowdot4q<R>(rowBm, vu, r);      // B^-_k (2u^ - u~)_k
-        r = rowdot4q<R>(rowBp, vunext, r);  // B^+_k (2u^ - u~)_{k+1}
+        r = rowdot4c<R>(rowBm, vu, r);      // B^-_k (2u^ - u~)_k
+        r = rowdot4c<R>(rowBp, vunext, r);  // B^+_k (2u^ - u~)_{k+1}
         // (2 mu+^ - nu+) - (2 mu-^ - nu-)
         r += R(2) * (mupn - mumn) - (nup - num);
         const R phn = vphi + beta * r;
@@ -1106,17 +1157,19 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         sl[Lds::TH + 16] = vth;
         // stopping test every `check` steps: infinity norms of (x, u, mu+, mu-) and of
         // (phi, theta) at j+1 and j and of their differences.  Lanes without a variable hold
-        // zeros and the four lanes of a control hold identical values, so every lane enters
-        // unmasked.  Row maxima by DPP, then one LDS atomic max per row on the bit patterns
-        // (monotone for non-negative values); the slot set alternates between tests, the
-        // other set is cleared for the next one.
+        // zeros; the controls enter from their read copy (lanes 4..7) only, the other copies
+        // are not projected.  Row maxima by DPP, then one LDS atomic max per row on the bit
+        // patterns (monotone for non-negative values); the slot set alternates between tests,
+        // the other set is cleared for the next one.
         if (test) {
-            const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
+            const bool ucopy = (i >> 2) == 1;
+            const R xh = sl[Lds::PX], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
+            const R uh = ucopy ? sl[Lds::PU] : R(0), unr = ucopy ? un : R(0);
             const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
             R m[6];
-            m[0] = fmax(fmax(fabs(xn), fabs(un)), fmax(fabs(mupn), fabs(mumn)));
+            m[0] = fmax(fmax(fabs(xn), fabs(unr)), fmax(fabs(mupn), fabs(mumn)));
             m[1] = fmax(fmax(fabs(xh), fabs(uh)), fmax(fabs(mup), fabs(mum)));
-            m[2] = fmax(fmax(fabs(xn - xh), fabs(un - uh)), fmax(fabs(mupn - mup), fabs(mumn - mum)));
+            m[2] = fmax(fmax(fabs(xn - xh), fabs(unr - uh)), fmax(fabs(mupn - mup), fabs(mumn - mum)));
             m[3] = fmax(fabs(phn), fabs(thn));
             m[4] = fmax(fabs(ph), fabs(th));
             m[5] = fmax(fabs(phn - ph), fabs(thn - th));
@@ -1157,7 +1210,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         st[0] = fabs(double(xh));
         a.x[xoff + i] = R(double(a.x[xoff + i]) + a.px[i] * double(xh));
     }
-    if (node && (i & 3) == 0) {
+    if (node && (i >> 2) == 1) {  // the read copy of the controls
         st[0] = fmax(st[0], fabs(double(uh)));
         a.u[uoff + qi] = R(double(ubq) + a.pu[qi] * double(uh));
     }
