@@ -56,10 +56,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per subproblem launch from the committed hardware-counter summary, or None
-    when there is none or the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(workload):
+    """HBM bytes per subproblem launch from the committed hardware-counter summary (taken on
+    the 1,024-instance Monte Carlo), or None for another workload, when there is no summary, or
+    when the kernel sources changed since the counters were taken."""
+    if workload != "C1" or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     with open(TRAFFIC_FILE) as f:
@@ -187,7 +188,7 @@ def main():
     achieved = flops_per_solve / (sub_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    traffic=measured_traffic(), kernel="subproblem_kernel",
+                    traffic=measured_traffic(wl), kernel="subproblem_kernel",
                     avg_launch_ms=round(sub_ms / max(sub_launches, 1), 4),
                     kernel_ms_per_step={k: round(v[0] / nprof, 3) for k, v in per.items()})
 
