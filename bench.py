@@ -29,7 +29,10 @@ WORKLOAD_NAMES = {
     "C2": "uneven Monte Carlo 16,384 x K in {10,20,30}, early exit (SCP 1e-4, PIPG 1e-5), "
           "widened dispersions (seed 2)",
     "C4": "throughput 65,536 x K=30, 15 SCP x 1,000 PIPG iterations, J and r_T dispersed (seed 4)",
+    "F1": "paper's Monte Carlo: 256 runs, r0 ~ U(6,9) x U(3,6) x U(1,2), K=30, at most 25 SCP x "
+          "2,500 PIPG iterations, SCP early exit (seed 5)",
 }
+SWEEP_SIZES = (1, 4, 16, 64, 256, 1024, 4096, 16384, 65536)
 
 
 def pipg_flops_per_iter(K):
@@ -99,15 +102,70 @@ def cpu_baseline(cfg, inst, n_sample, threads, kmax):
                                    wall_s=round(dt1, 2), converged=conv1))
 
 
+def sweep(args):
+    """Batch-size sweep on the paper's Monte Carlo distribution (the analog of its CPU/GPU
+    solve-time comparison): GPU time of one batched solve of B runs (ids 0..B-1), against the
+    oracle on the host cores, measured on a few runs and extrapolated linearly in B (a serial
+    solver's time is linear in the number of runs).  One JSON line per batch size."""
+    import torch
+    import oracle
+    from paper_2404_18034_amd import api
+    from paper_2404_18034_amd import instances as I
+
+    cfg = I.solver_settings("F1")
+    cfg["mode"], cfg["occupancy"] = 1, 5
+    probe = I.make_instances("F1", ids=range(64))
+    oracle.build()
+    cpu = {}
+    for th, n in ((1, 4), (16, 64)):
+        sub = {k: v[:n] for k, v in probe.items()}
+        t = time.perf_counter()
+        oracle.solve(cfg, sub["x0"], sub["xf"], sub["params"], sub["K"], kmax=30, nthreads=th)
+        cpu[th] = (time.perf_counter() - t) / n
+    print(json.dumps({"sweep": "oracle", "s_per_run_1_thread": round(cpu[1], 4),
+                      "s_per_run_16_threads": round(cpu[16], 5)}), flush=True)
+    bmax = max(SWEEP_SIZES)
+    solver = api.BatchSolver(cfg, dtype="f32", k_max=30, max_batch=bmax, device=0)
+    sol = solver.alloc_solution(bmax)
+    crossover = None
+    for B in SWEEP_SIZES:
+        inst = I.make_instances("F1", ids=range(B))
+        prob = solver.to_device(inst)
+        solver.solve_into(prob, sol)  # warm-up (graph capture for this argument set)
+        torch.cuda.synchronize()
+        reps = 3 if B <= 4096 else 1
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            solver.solve_into(prob, sol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        gpu = sorted(ts)[len(ts) // 2]
+        conv = int(np.sum(sol["status"][:B].cpu().numpy() == 0))
+        if crossover is None and gpu < B * cpu[1]:
+            crossover = B
+        print(json.dumps({"sweep": "F1", "batch": B, "gpu_s": round(gpu, 5),
+                          "oracle_1_thread_s": round(B * cpu[1], 4),
+                          "oracle_16_threads_s": round(B * cpu[16], 4),
+                          "converged": conv, "gpu_runs_per_s": round(B / gpu, 1)}), flush=True)
+    print(json.dumps({"sweep": "summary", "first_batch_where_gpu_beats_serial_oracle": crossover,
+                      "mode": [1, 5]}), flush=True)
+    solver.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1"],
                     help="C1 (default): the 1,024-instance Monte Carlo the metric is quoted on; "
-                         "C2 (16,384 uneven K, early exit) and C4 (65,536 x K=30) for reference")
+                         "C2 (16,384 uneven K, early exit), C4 (65,536 x K=30) and F1 (the "
+                         "paper's 256-run Monte Carlo) for reference")
+    ap.add_argument("--sweep", action="store_true",
+                    help="batch-size sweep 1..65,536 on the paper's Monte Carlo distribution "
+                         "against the oracle on the host (one JSON line per size)")
     ap.add_argument("--mode", type=int, default=None,
                     help="dispatch mode (0 launches, 1 graph, 2 ordered, 3 persistent); "
                          "default: autotuned on the workload")
@@ -123,6 +181,9 @@ def main():
         print("bench.py measures one GPU only (instances are independent; a multi-GPU run would "
               "shard the batch with no exchange). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        sweep(args)
+        return
 
     import torch
     from paper_2404_18034_amd import api

@@ -36,37 +36,58 @@ def well_conditioned(cfg, inst, o, rel, kmax=None):
 
 def fp32_deviation(cfg, inst, o, kmax=None):
     """How far FP32 rounding alone moves each instance: the oracle's algorithm evaluated in
-    single precision against the FP64 oracle (scaled-absolute on x).  Oracle-only."""
+    single precision against the FP64 oracle, scaled-absolute on x and on u (the controls can
+    be far more sensitive than the states).  Oracle-only."""
     f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=kmax)
-    px = np.array(cfg["px"])
+    px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
     with np.errstate(invalid="ignore"):
-        return np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2))
+        return (np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2)),
+                np.max(np.abs(f["u"] - o["u"]) / pu, axis=(1, 2)))
+
+
+FP32_DRAWS = 8
 
 
 def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
-    """FP32 GPU vs FP64 oracle.  Where two single-precision runs of the oracle's own algorithm
-    stay within TOL_F32 / 10 of the FP64 result, the GPU must match to TOL_F32; elsewhere FP32
-    rounding by itself moves the result (the node-wise thrust projection makes some instances
-    sensitive), and the GPU error must stay within 20x of that plain-FP32 deviation.  Status
-    and iteration counts must agree."""
-    dev = fp32_deviation(cfg, inst, o, kmax)
-    # a second draw of FP32 rounding: x0 moved by 1e-7 relative
+    """FP32 GPU vs FP64 oracle, one certificate per output, from FP32_DRAWS single-precision
+    runs of the oracle's own algorithm (on the inputs, and with x0 moved by 1e-7 relative: other
+    draws of FP32 rounding).  States and final mass: where every draw stays within TOL_F32 / 10
+    of the FP64 states, the GPU must match to TOL_F32; elsewhere FP32 rounding by itself moves
+    the states (the node-wise thrust projection makes some instances sensitive) and the GPU
+    error must stay within 20x of the plain-FP32 deviation.  Controls: the plain-FP32 scatter
+    of the controls has a heavy tail (on the paper's Monte Carlo, ten draws move controls that
+    two draws place within 1e-5 by up to 9e-5; eight draws are taken), so every instance is held to
+    max(TOL_F32, 20x its plain-FP32 control deviation), and the final time (the integral of the
+    dilation control) to TOL_F32 where the controls are certified.  Status and iteration counts
+    must agree."""
+    dx, du = fp32_deviation(cfg, inst, o, kmax)
     rng = np.random.default_rng(11)
-    inst2 = dict(inst, x0=inst["x0"] * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0, inst["x0"].shape)))
-    inst2["x0"][:, 14] = 0.0
-    dev = np.maximum(dev, fp32_deviation(cfg, inst2, o, kmax))
+    for _ in range(FP32_DRAWS - 1):
+        inst2 = dict(inst, x0=inst["x0"] * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0,
+                                                                       inst["x0"].shape)))
+        inst2["x0"][:, 14] = 0.0
+        dx2, du2 = fp32_deviation(cfg, inst2, o, kmax)
+        dx, du = np.maximum(dx, dx2), np.maximum(du, du2)
     fin = o["status"] != 2
-    ok = fin & (dev <= TOL_F32 / 10)
-    errs = _errors(cfg, g, o)
-    _report("%s (FP32-conditioned %d/%d)" % (tag, ok.sum(), ok.size), [e[ok] for e in errs])
-    for e in errs:
-        assert e[ok].max() <= TOL_F32
+    ok = fin & (dx <= TOL_F32 / 10)
+    oku = fin & (du <= TOL_F32 / 10)
+    ex, eu, etf, emf = _errors(cfg, g, o)
+    print("%s (FP32-conditioned: states %d/%d, controls %d/%d) x %.2e u %.2e t_f %.2e m_f %.2e"
+          % (tag, ok.sum(), ok.size, oku.sum(), oku.size, ex[ok].max(), eu[oku].max(),
+             etf[oku].max(), emf[ok].max()), flush=True)
+    for e, sel in ((ex, ok), (emf, ok), (etf, oku)):
+        assert e[sel].max() <= TOL_F32
     rest = fin & ~ok
     if rest.any():
-        ratio = errs[0][rest] / np.maximum(dev[rest], TOL_F32)
-        print("%s: %d FP32-sensitive instances, GPU error / plain-FP32 deviation max %.2f"
+        ratio = ex[rest] / np.maximum(dx[rest], TOL_F32)
+        print("%s: %d FP32-sensitive instances (states), GPU error / plain-FP32 deviation max %.2f"
               % (tag, rest.sum(), ratio.max()))
         assert ratio.max() <= 20.0
+    bar = np.maximum(TOL_F32, 20.0 * du)
+    w = int(np.argmax(np.where(fin, eu / bar, -1.0)))
+    print("%s: controls, GPU error / max(TOL, 20x plain-FP32 deviation) max %.2f (instance %d: "
+          "error %.2e, plain deviation %.2e)" % (tag, eu[w] / bar[w], w, eu[w], du[w]))
+    assert np.all(eu[fin] <= bar[fin])
     np.testing.assert_array_equal(g["status"][ok], o["status"][ok])
     np.testing.assert_array_equal(g["scp_iters"], o["scp_iters"])
     return ok
@@ -161,7 +182,7 @@ def test_c1_fp32_sample_matches_oracle(proj):
     g = _gpu(cfg, inst, "f32")
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
     ok = check_fp32_against_oracle(cfg, inst, g, o, "C1 fp32 proj=%d" % proj)
-    assert ok.mean() >= 0.75
+    assert ok.mean() >= (1.0 if proj == 0 else 0.6)
     assert np.all(flags_agree(cfg, g, o)[ok])
     assert np.all(g["scp_iters"] == 15) and np.all(g["pipg_iters"] == 15000)
     _valid(g, inst)
@@ -334,3 +355,31 @@ def test_node_counts_up_to_50_short_horizon(dtype):
             np.testing.assert_array_equal(g[k], o[k])
     else:
         check_fp32_against_oracle(cfg, inst, g, o, "K<=50 fp32 2 subproblems", kmax=50)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_paper_monte_carlo_256_runs(dtype):
+    # the paper's own Monte Carlo (256 runs, r(0) ~ U(6,9) x U(3,6) x U(1,2), at most 25 SCP
+    # iterations of 2,500 PIPG iterations): every run converges on the GPU as in the oracle,
+    # with the oracle's SCP iteration counts and trajectories
+    print("case: paper's Monte Carlo, 256 runs, %s" % dtype, flush=True)
+    cfg = I.solver_settings("F1")
+    inst = I.make_instances("F1")
+    g = _gpu(cfg, inst, dtype, k_max=30)
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
+    print("SCP iterations, GPU:", np.bincount(g["scp_iters"], minlength=26).tolist())
+    print("SCP iterations, oracle:", np.bincount(o["scp_iters"], minlength=26).tolist())
+    assert np.all(g["status"] == 0) and np.all(g["scp_iters"] <= 25)
+    np.testing.assert_array_equal(g["pipg_iters"], 2500 * g["scp_iters"])
+    if dtype == "f64":
+        ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
+        print("well conditioned: %d / %d" % (ok.sum(), ok.size))
+        assert ok.mean() >= 0.9
+        errs = _errors(cfg, g, o)
+        _report("F1 fp64 (well-conditioned)", [e[ok] for e in errs])
+        for e in errs:
+            assert e[ok].max() <= TOL_F64
+        for k in ("status", "scp_iters", "pipg_iters"):
+            np.testing.assert_array_equal(g[k][ok], o[k][ok])
+    else:
+        check_fp32_against_oracle(cfg, inst, g, o, "F1 fp32", kmax=30)

@@ -1,8 +1,9 @@
 """Per-output error of the FP32 path against the FP64 oracle (precision policy: FP32 bulk,
 FP64 state in RK4, power iteration, reductions and CTCS), on the throughput workload's
-256-instance sample (instance ids 256*i).  Every output is reported.  x, u, t_f, m_f are held
-to the FP32 tolerance on the instances that FP32 rounding by itself does not move (two
-single-precision runs of the oracle's own algorithm stay within a tenth of the tolerance);
+256-instance sample (instance ids 256*i).  Every output is reported.  x and m_f (u and t_f)
+are held to the FP32 tolerance on the instances whose states (controls) FP32 rounding by
+itself does not move (two single-precision runs of the oracle's own algorithm stay within a
+tenth of the tolerance);
 over the rest of the sample the GPU's error distribution (median, 90th percentile) must be
 that of a plain FP32 evaluation within a factor 10.  Iteration counts must agree exactly
 (fixed-work solve), status on the FP32-conditioned instances."""
@@ -20,9 +21,10 @@ TOL_F32 = 1e-4
 
 def _plain_fp32_deviation(cfg, inst, o):
     """Deviation from the FP64 oracle of single-precision runs of the oracle's algorithm: one on
-    the given inputs, one with x0 moved by 1e-7 relative (a second draw of FP32 rounding)."""
-    px = np.array(cfg["px"])
-    devs = []
+    the given inputs, one with x0 moved by 1e-7 relative (a second draw of FP32 rounding).
+    Returns the larger of the two on x and on u, and the first run's on x."""
+    px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
+    devs, devu = [], []
     rng = np.random.default_rng(11)
     for rel in (0.0, 1e-7):
         x0 = inst["x0"] * (1.0 + rel * rng.uniform(-1.0, 1.0, inst["x0"].shape))
@@ -30,7 +32,8 @@ def _plain_fp32_deviation(cfg, inst, o):
         f = oracle.solve_f32(cfg, x0, inst["xf"], inst["params"], inst["K"], kmax=30)
         with np.errstate(invalid="ignore"):
             devs.append(np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2)))
-    return np.maximum(devs[0], devs[1]), devs[0]
+            devu.append(np.max(np.abs(f["u"] - o["u"]) / pu, axis=(1, 2)))
+    return np.maximum(devs[0], devs[1]), np.maximum(devu[0], devu[1]), devs[0]
 
 
 def test_throughput_sample_error_report():
@@ -39,10 +42,12 @@ def test_throughput_sample_error_report():
     inst = I.make_instances("C4", ids=ids)
     g = api.solve(cfg, inst, dtype="f32", k_max=30)
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
-    dev, dev0 = _plain_fp32_deviation(cfg, inst, o)
+    dev, devu, dev0 = _plain_fp32_deviation(cfg, inst, o)
     px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
     fin = (o["status"] != 2) & (g["status"] != 2)
     ok = fin & (dev <= TOL_F32 / 10)
+    oku = fin & (devu <= TOL_F32 / 10)
+    cert = {"x (scaled abs)": ok, "u (scaled abs)": oku, "t_f (rel)": oku, "m_f (rel)": ok}
     rows = {
         "x (scaled abs)": np.max(np.abs(g["x"] - o["x"]) / px, axis=(1, 2)),
         "u (scaled abs)": np.max(np.abs(g["u"] - o["u"]) / pu, axis=(1, 2)),
@@ -52,13 +57,14 @@ def test_throughput_sample_error_report():
         "defect_inf (abs)": np.abs(g["defect_inf"] - o["defect_inf"]),
         "ctcs_viol (abs)": np.abs(g["ctcs_viol"] - o["ctcs_viol"]),
     }
-    print("\nFP32 GPU vs FP64 oracle, throughput sample: %d instances, %d finite, %d "
-          "FP32-conditioned (two plain single-precision runs within %.0e)"
-          % (ids.size, fin.sum(), ok.sum(), TOL_F32 / 10))
+    print("\nFP32 GPU vs FP64 oracle, throughput sample: %d instances, %d finite, FP32-conditioned "
+          "%d (states) and %d (controls): two plain single-precision runs within %.0e"
+          % (ids.size, fin.sum(), ok.sum(), oku.sum(), TOL_F32 / 10))
     print("%-18s %11s %11s %11s %11s" % ("output", "median", "p90", "max(cond)", "max"))
     for name, e in rows.items():
+        c = cert.get(name, ok)
         print("%-18s %11.3e %11.3e %11.3e %11.3e" % (name, np.median(e[fin]),
-                                                    np.quantile(e[fin], 0.9), e[ok].max(),
+                                                    np.quantile(e[fin], 0.9), e[c].max(),
                                                     e[fin].max()))
     print("%-18s %11.3e %11.3e %11s %11.3e" % ("plain FP32 x", np.median(dev0[fin]),
                                                np.quantile(dev0[fin], 0.9), "",
@@ -67,8 +73,9 @@ def test_throughput_sample_error_report():
         print("%-18s agree on %d / %d" % (name, np.sum(g[name] == o[name]), ids.size))
     # where FP32 rounding does not move the result, the GPU matches the FP64 oracle
     assert ok.sum() >= 16
+    assert oku.sum() >= 16
     for name in ("x (scaled abs)", "u (scaled abs)", "t_f (rel)", "m_f (rel)"):
-        assert rows[name][ok].max() <= TOL_F32, name
+        assert rows[name][cert[name]].max() <= TOL_F32, name
     # elsewhere its deviation is that of a plain FP32 evaluation of the same algorithm
     ex = rows["x (scaled abs)"][fin]
     assert np.median(ex) <= 10 * max(np.median(dev0[fin]), TOL_F32 / 10)
