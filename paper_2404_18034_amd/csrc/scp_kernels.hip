@@ -283,28 +283,6 @@ __device__ __forceinline__ R row_reduce_scatter4(const R (&v)[NU], int i)
     w = w + dppmov<0x4E>(w);              // quad_perm [2,3,0,1]
     return w;
 }
-// Select-free form of the same scatter: lane i supplies its four addends in the exchange
-// order v[s] = addend of component xperm(i, s), where with b3, b2 the bits 3 and 2 of i
-//   xperm(i, 0) = 2 b3 + b2,  xperm(i, 1) = 2 b3 + 1 - b2,
-//   xperm(i, 2) = 2 (1 - b3) + 1 - b2,  xperm(i, 3) = 2 (1 - b3) + b2,
-// so that the row_mirror partner (bits 3..0 inverted) sends exactly the components this lane
-// keeps, and the row_half_mirror partner (bits 2..0 inverted) likewise; lane i receives the
-// row sum of component i >> 2.
-__host__ __device__ constexpr int xperm(int i, int s)
-{
-    const int b3 = (i >> 3) & 1, b2 = (i >> 2) & 1;
-    return s == 0 ? 2 * b3 + b2 : s == 1 ? 2 * b3 + 1 - b2 : s == 2 ? 2 * (1 - b3) + 1 - b2 : 2 * (1 - b3) + b2;
-}
-template <typename R>
-__device__ __forceinline__ R row_reduce_scatter4x(const R (&v)[NU])
-{
-    const R a0 = v[0] + dppmov<0x140>(v[2]);  // row_mirror
-    const R a1 = v[1] + dppmov<0x140>(v[3]);
-    R w = a0 + dppmov<0x141>(a1);             // row_half_mirror
-    w = w + dppmov<0xB1>(w);                  // quad_perm [1,0,3,2]
-    w = w + dppmov<0x4E>(w);                  // quad_perm [2,3,0,1]
-    return w;
-}
 // Interleaved control layout of the subproblem kernel: component c of the node's controls on
 // lanes c, c+4, c+8 and c+12 of its row; the copy on lanes 4..7 is the one that is read.
 // Reduce-scatter onto it: lane i receives the row sum of component i & 3.  Lane i supplies its
