@@ -218,6 +218,22 @@ scp_status scp_batch_solve_record(scp_batch h, const scp_problem *problem,
 scp_status scp_batch_grad(scp_batch h, const scp_problem *problem, const scp_lastiter *last,
                           const void *cotangent, void *grad, void *value);
 
+/* Parallel multi-start (named in the paper's Conclusion as future work: several initial
+ * guesses per problem are solved in parallel and the converged trajectory of lowest cost is
+ * kept).  `solution` holds a batch solved by this handle of problems * starts instances in
+ * which the starts of problem p are instances p*starts .. p*starts + starts - 1 (they differ
+ * only in their initial guess, e.g. the dilation guess s_init in params).  For each problem:
+ *   best  int32 [problems]  the start with status 0 and the smallest objective (ties: the
+ *                           smallest start index), or -1 when no start converged;
+ *   out   a solution of `problems` instances (this handle's dtype and k_max) that receives
+ *         that start's results -- start 0's when none converged, so out->status says why.
+ * problems * starts must not exceed max_batch; out and best may not overlap the solution or
+ * each other (SCP_ERR_ARG); every array is device memory, 16-byte aligned (best: 4); with
+ * problems = 0 nothing is read or written.  Reads nothing but `solution`, so it may follow
+ * the solve on the same stream.  Asynchronous on the handle's stream. */
+scp_status scp_batch_select_best(scp_batch h, const scp_solution *solution, int32_t problems,
+                                 int32_t starts, int32_t *best, scp_solution *out);
+
 /* Release the handle (not the caller's workspace).  Synchronizes its stream first. */
 scp_status scp_batch_destroy(scp_batch h);
 

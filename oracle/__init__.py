@@ -303,6 +303,22 @@ def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None):
     return {k: (a.astype(np.float64) if a.dtype == np.float32 else a) for k, a in out.items()}
 
 
+def select_best(status, objective, problems, starts):
+    """Multi-start choice (the paper's Conclusion: several initial guesses per problem, the
+    converged trajectory of lowest cost kept): for problem p, whose starts are rows
+    p*starts .. p*starts + starts - 1, the start j with status 0 and the smallest objective,
+    the first such j on ties, or -1 when no start converged.  Plain loops."""
+    best = []
+    for p in range(problems):
+        pick, cost = -1, None
+        for j in range(starts):
+            r = p * starts + j
+            if int(status[r]) == 0 and (pick < 0 or float(objective[r]) < cost):
+                pick, cost = j, float(objective[r])
+        best.append(pick)
+    return np.array(best, dtype=np.int32)
+
+
 def solve_trace(cfg, x0, xf, p, K, trace_n=64):
     st = make_settings(cfg)
     x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)

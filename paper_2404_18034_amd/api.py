@@ -23,7 +23,8 @@ STATUS = {0: "SCP_OK", 1: "SCP_ERR_ARG", 2: "SCP_ERR_SHAPE", 3: "SCP_ERR_DTYPE",
 EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
            "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
            "scp_batch_profile", "scp_batch_profile_read", "scp_batch_autotune",
-           "scp_batch_mode", "scp_batch_solve_record", "scp_batch_grad", "scp_batch_destroy"]
+           "scp_batch_mode", "scp_batch_solve_record", "scp_batch_grad",
+           "scp_batch_select_best", "scp_batch_destroy"]
 KERNEL_CLASSES = ("init", "discretize", "subproblem", "prepare")  # SCP_KERNEL_CLASSES order
 
 
@@ -119,6 +120,10 @@ def load():
                                      ctypes.POINTER(LastIter), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]
         L.scp_batch_grad.restype = ctypes.c_int
+        L.scp_batch_select_best.argtypes = [ctypes.c_void_p, ctypes.POINTER(Solution),
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(Solution)]
+        L.scp_batch_select_best.restype = ctypes.c_int
         L.scp_batch_destroy.argtypes = [ctypes.c_void_p]
         L.scp_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -339,6 +344,33 @@ class BatchSolver:
         sol = self.alloc_solution(B)
         return self.solve_into(prob, sol)
 
+    def select_best_into(self, sol, problems, starts, best, out):
+        """Enqueue the multi-start selection (scp_batch_select_best): `sol` holds
+        problems * starts solved instances, the starts of problem p consecutive; best
+        (int32 [problems]) and `out` (a solution of `problems` instances) are written."""
+        problems, starts = int(problems), int(starts)
+        n = problems * starts
+        for k, v in sol.items():
+            if v.shape[0] < n:
+                raise ScpError(2, "solution array %s holds fewer than problems * starts rows" % k)
+        for k, v in out.items():
+            if v.shape[0] < problems:
+                raise ScpError(2, "out array %s holds fewer than `problems` rows" % k)
+        if best.dtype != self.torch.int32 or best.shape[0] < problems or not best.is_contiguous():
+            raise ScpError(2, "best must be a contiguous int32 tensor of at least `problems` rows")
+        names = ("x", "u", "t_f", "m_f", "status", "scp_iters", "pipg_iters", "defect_inf",
+                 "ctcs_viol", "objective")
+        s = Solution(*[sol[k].data_ptr() for k in names])
+        o = Solution(*[out[k].data_ptr() for k in names])
+        self._check(load().scp_batch_select_best(self.handle, ctypes.byref(s), problems, starts,
+                                                 best.data_ptr(), ctypes.byref(o)))
+        return best, out
+
+    def select_best(self, sol, problems, starts):
+        best = self.torch.empty(int(problems), dtype=self.torch.int32,
+                                device="cuda:%d" % self.device)
+        return self.select_best_into(sol, problems, starts, best, self.alloc_solution(problems))
+
 
 def solve(cfg, inst, dtype="f32", k_max=None, device=0):
     """One-shot convenience: numpy problem dict in, dict of numpy arrays out."""
@@ -351,6 +383,29 @@ def solve(cfg, inst, dtype="f32", k_max=None, device=0):
         sol = s.solve(s.to_device(inst))
         torch.cuda.synchronize(device)
         return {k: v.cpu().numpy() for k, v in sol.items()}
+    finally:
+        s.close()
+
+
+def solve_multistart(cfg, inst, s_init, dtype="f32", k_max=None, device=0):
+    """Multi-start one-shot: every problem of `inst` is solved once per initial dilation guess
+    in `s_init` (all starts in one batch, see instances.multistart) and the converged start of
+    lowest cost is kept.  Returns (numpy solution dict of the problems, best start per problem
+    or -1, numpy solution dict of every start)."""
+    import torch
+    from . import instances
+    starts = len(s_init)
+    rep = instances.multistart(inst, s_init)
+    K = np.asarray(rep["K"])
+    k_max = int(K.max()) if k_max is None else int(k_max)
+    P = int(np.asarray(inst["K"]).shape[0])
+    s = BatchSolver(cfg, dtype=dtype, k_max=k_max, max_batch=max(P * starts, 1), device=device)
+    try:
+        sol = s.solve(s.to_device(rep))
+        best, out = s.select_best(sol, P, starts)
+        torch.cuda.synchronize(device)
+        return ({k: v.cpu().numpy() for k, v in out.items()}, best.cpu().numpy(),
+                {k: v.cpu().numpy() for k, v in sol.items()})
     finally:
         s.close()
 

@@ -625,6 +625,66 @@ scp_status scp_batch_mode(scp_batch h, int32_t *mode_out, int32_t *occupancy_out
     return SCP_OK;
 }
 
+scp_status scp_batch_select_best(scp_batch h, const scp_solution *sol, int32_t problems,
+                                 int32_t starts, int32_t *best, scp_solution *out)
+{
+    if (!h) return SCP_ERR_ARG;
+    h->err.clear();
+    if (!sol || !out) return fail(h, SCP_ERR_ARG, "solution or out is NULL");
+    if (problems < 0 || starts < 1)
+        return fail(h, SCP_ERR_SHAPE, "problems must be >= 0 and starts >= 1");
+    if ((int64_t)problems * starts > h->st.max_batch)
+        return fail(h, SCP_ERR_SHAPE, "problems * starts must be <= max_batch");
+    if (problems == 0) return SCP_OK;
+    if (!best) return fail(h, SCP_ERR_ARG, "best is NULL");
+    const size_t rs = h->st.dtype == SCP_F64 ? 8 : 4, km = (size_t)h->st.k_max;
+    // every array with its extent in bytes per instance, for the solved batch and for out
+    struct Arr { const void *p; size_t per; };
+    const Arr in_a[] = {{sol->x, km * 15 * rs}, {sol->u, km * 4 * rs}, {sol->t_f, rs},
+                        {sol->m_f, rs}, {sol->status, 4}, {sol->scp_iters, 4},
+                        {sol->pipg_iters, 4}, {sol->defect_inf, 8}, {sol->ctcs_viol, 8},
+                        {sol->objective, 8}};
+    const Arr out_a[] = {{out->x, km * 15 * rs}, {out->u, km * 4 * rs}, {out->t_f, rs},
+                         {out->m_f, rs}, {out->status, 4}, {out->scp_iters, 4},
+                         {out->pipg_iters, 4}, {out->defect_inf, 8}, {out->ctcs_viol, 8},
+                         {out->objective, 8}, {best, 4}};
+    for (const Arr &a : in_a)
+        if (!a.p || !aligned16(a.p)) return fail(h, SCP_ERR_ARG, "solution arrays must be non-NULL and 16-byte aligned");
+    for (const Arr &a : out_a)
+        if (!a.p || (a.p != best && !aligned16(a.p)))
+            return fail(h, SCP_ERR_ARG, "out arrays must be non-NULL and 16-byte aligned");
+    // the outputs (and best) may overlap neither the solved batch nor each other
+    const size_t n_in = (size_t)problems * (size_t)starts, n_out = (size_t)problems;
+    auto overlap = [](const void *a, size_t na, const void *b, size_t nb) {
+        const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+        return x < y + nb && y < x + na;
+    };
+    for (size_t i = 0; i < sizeof(out_a) / sizeof(out_a[0]); ++i) {
+        for (const Arr &a : in_a)
+            if (overlap(out_a[i].p, out_a[i].per * n_out, a.p, a.per * n_in))
+                return fail(h, SCP_ERR_ARG, "out and best must not overlap the solution");
+        for (size_t j = 0; j < i; ++j)
+            if (overlap(out_a[i].p, out_a[i].per * n_out, out_a[j].p, out_a[j].per * n_out))
+                return fail(h, SCP_ERR_ARG, "out arrays and best must not overlap each other");
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != h->device) {
+        e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    const scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
+                          sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
+    const scp::Solution O{out->x, out->u, out->t_f, out->m_f, out->status, out->scp_iters,
+                          out->pipg_iters, out->defect_inf, out->ctcs_viol, out->objective};
+    e = scp::launch_select_best(h->st.dtype == SCP_F64 ? 1 : 0, h->st.k_max, S, O, problems,
+                                starts, best, h->stream);
+    if (cur != h->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SCP_OK;
+}
+
 scp_status scp_batch_destroy(scp_batch h)
 {
     if (!h) return SCP_ERR_ARG;

@@ -1513,6 +1513,61 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
     return discretize_at_typed<float>(cfg, x, u, prob, status, ws, stream);
 }
 
+// ------------------------------------------------------------------------------------------
+// Multi-start selection (the paper's Conclusion: several initial guesses per problem, solved
+// in parallel, the converged trajectory of lowest cost kept).  One 64-lane workgroup per
+// problem: every lane scans the problem's starts (the same loads, so every lane reaches the
+// same choice without an exchange), lane 0 writes the choice and the scalar outputs, and the
+// workgroup copies the chosen trajectory.
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(64) select_best_kernel(Solution in, Solution out, int problems,
+                                                          int starts, int kmax, int32_t *best)
+{
+    const int p = blockIdx.x;
+    if (p >= problems) return;
+    int pick = -1;
+    double cost = 0.0;
+    for (int j = 0; j < starts; ++j) {
+        const long s = (long)p * starts + j;
+        if (in.status[s] == 0 && (pick < 0 || in.objective[s] < cost)) {
+            pick = j;
+            cost = in.objective[s];
+        }
+    }
+    const long src = (long)p * starts + (pick < 0 ? 0 : pick);
+    if (threadIdx.x == 0) {
+        best[p] = pick;
+        static_cast<R *>(out.t_f)[p] = static_cast<const R *>(in.t_f)[src];
+        static_cast<R *>(out.m_f)[p] = static_cast<const R *>(in.m_f)[src];
+        out.status[p] = in.status[src];
+        out.scp_iters[p] = in.scp_iters[src];
+        out.pipg_iters[p] = in.pipg_iters[src];
+        out.defect_inf[p] = in.defect_inf[src];
+        out.ctcs_viol[p] = in.ctcs_viol[src];
+        out.objective[p] = in.objective[src];
+    }
+    const R *xs = static_cast<const R *>(in.x) + src * kmax * NX;
+    const R *us = static_cast<const R *>(in.u) + src * kmax * NU;
+    R *xd = static_cast<R *>(out.x) + (long)p * kmax * NX;
+    R *ud = static_cast<R *>(out.u) + (long)p * kmax * NU;
+    for (int e = threadIdx.x; e < kmax * NX; e += blockDim.x) xd[e] = xs[e];
+    for (int e = threadIdx.x; e < kmax * NU; e += blockDim.x) ud[e] = us[e];
+}
+
+hipError_t launch_select_best(int dtype, int kmax, const Solution &in, const Solution &out,
+                              int problems, int starts, int32_t *best, hipStream_t stream)
+{
+    if (problems == 0) return hipSuccess;
+    if (dtype == 1)
+        select_best_kernel<double><<<dim3((unsigned)problems), dim3(64), 0, stream>>>(
+            in, out, problems, starts, kmax, best);
+    else
+        select_best_kernel<float><<<dim3((unsigned)problems), dim3(64), 0, stream>>>(
+            in, out, problems, starts, kmax, best);
+    return hipGetLastError();
+}
+
 }  // namespace scp
 
 namespace scp {

@@ -94,6 +94,13 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
                                 const Problem &prob, const int32_t *status, const Workspace &ws,
                                 hipStream_t stream);
 
+// Multi-start selection: the solution `in` holds problems * starts instances, the starts of
+// problem p at p*starts .. p*starts + starts - 1.  best[p] = the start with status 0 and the
+// smallest objective (ties: the smallest index), -1 if none converged; `out` (problems
+// instances) receives that start's results, start 0's when none converged.
+hipError_t launch_select_best(int dtype, int kmax, const Solution &in, const Solution &out,
+                              int problems, int starts, int32_t *best, hipStream_t stream);
+
 // Gradient of (m_f, t_f) of the truncated last-iteration map (discretization at the
 // recorded reference, QP build, `nsteps` PIPG steps from the recorded warm start) with
 // respect to theta = (x0[15], m_wet, alpha_mdot, T_max), contracted with the cotangent

@@ -179,3 +179,14 @@ def make_instances(config, B=None, ids=None, seed=None):
         for k in ("x0", "xf", "params"):
             out[k] = out[k].astype(np.float32).astype(np.float64)
     return out
+
+
+def multistart(inst, s_init):
+    """Multi-start batch: problem p of `inst` repeated once per initial dilation guess, the
+    copies of p at rows p*M .. p*M + M - 1 (M = len(s_init)), copy j with s_init[j] in the
+    s_init column of params; nothing else changes."""
+    M = len(s_init)
+    out = {k: np.repeat(np.asarray(v), M, axis=0) for k, v in inst.items()}
+    out["params"] = out["params"].copy()
+    out["params"][:, 21] = np.tile(np.asarray(s_init, dtype=np.float64), len(inst["K"]))
+    return out
