@@ -313,6 +313,29 @@ def test_dispatch_modes_match_plain_launches(mode, occupancy):
     s.close()
 
 
+@pytest.mark.parametrize("mode,occupancy", [(1, 6), (1, 5), (0, 6)])
+def test_benchmark_variants_match_plain_launches(mode, occupancy):
+    # the launch variants the benchmark autotunes between, on its own settings (K = 20, the
+    # 320-lane kernel, fixed iterations), replayed three times: bit for bit the plain launches
+    import torch
+    print("case: C1 settings, mode %d occupancy %d" % (mode, occupancy), flush=True)
+    cfg = I.solver_settings("C1", scp_iters_max=4, pipg_iters_max=300)
+    inst = I.make_instances("C1", B=64)
+    ref = _gpu(cfg, inst, "f32", k_max=20)
+    s = api.BatchSolver(dict(cfg, mode=mode, occupancy=occupancy), dtype="f32", k_max=20,
+                        max_batch=64)
+    prob = s.to_device(inst)
+    sol = s.alloc_solution(64)
+    for rep in range(3):
+        for v in sol.values():
+            v.zero_()
+        s.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        for k in ref:
+            np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k], err_msg="%s rep %d" % (k, rep))
+    s.close()
+
+
 def test_autotune_picks_a_mode_and_keeps_results(tmp_path):
     import torch
     cfg = I.solver_settings("C1", scp_iters_max=3, pipg_iters_max=200)
