@@ -102,14 +102,16 @@ typedef struct {
 
 /* A batch of B problems.  params columns: m_wet, m_dry, alpha_mdot, g[3], J_diag[3],
  * r_T[3], T_min, T_max, delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs,
- * s_init (angles in radians).  x0 is the initial state (its y entry is ignored: y(0) = 0);
+ * s_init, v_max (angles in radians; v_max = +inf for no speed bound, otherwise the path
+ * constraint ||v||^2 <= v_max^2 of section "6-DoF Powered Descent Guidance" joins the CTCS
+ * integrand).  x0 is the initial state (its y entry is ignored: y(0) = 0);
  * xf = (r, v, q, w) is the landing condition, of which r, v, the tilt part (q2, q3) of q and
  * w are imposed.  An instance whose K is outside [2, k_max] is not solved (status 3). */
 typedef struct {
     int32_t batch;              /* B >= 0                                                  */
     const void *x0;             /* real [B][15]                                            */
     const void *xf;             /* real [B][13]                                            */
-    const void *params;         /* real [B][22]                                            */
+    const void *params;         /* real [B][23]                                            */
     const int32_t *K;           /* int32 [B] node counts                                   */
 } scp_problem;
 

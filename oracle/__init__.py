@@ -7,7 +7,7 @@ imports the GPU library.  The C source (``scp_oracle.c``) is compiled with gcc, 
 fast-math and without FMA contraction, into ``_scp_oracle.so`` next to it.
 
 Layouts (row-major float64 numpy arrays):
-  x0[B,15], xf[B,13], params[B,22], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
+  x0[B,15], xf[B,13], params[B,23], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
 
 ``solve_f32`` runs the same C source compiled with float in place of double
 (``_scp_oracle_f32.so``): a single-precision evaluation of the same algorithm.  Tests use it
@@ -20,7 +20,7 @@ import subprocess
 
 import numpy as np
 
-NX, NU, NP, NXF = 15, 4, 22, 13
+NX, NU, NP, NXF = 15, 4, 23, 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scp_oracle.c")
 _SO = os.path.join(_HERE, "_scp_oracle.so")
@@ -162,7 +162,7 @@ def jacobians(x, u, p):
 
 def constraints(x, u, p):
     x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
-    g = np.zeros(7)
+    g = np.zeros(8)
     lib().orc_constraints(xp, up, pp, _p(g))
     return g
 

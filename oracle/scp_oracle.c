@@ -13,8 +13,9 @@
  *   state  x = (m, r[3], v[3], q[4], w[3], y)   n_x = 15   (q Hamilton, scalar first)
  *   control u = (T[3], s)                       n_u = 4    (s = dilation factor)
  *   nodes k = 0..N-1 (paper's 1..N), intervals k = 0..N-2.
- *   params p[22] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
- *                  delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs, s_init
+ *   params p[23] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
+ *                  delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs, s_init,
+ *                  v_max (+inf: no speed bound)
  *
  * Every floating-point operation is written out in double precision, compiled without
  * fast-math and without FMA contraction.
@@ -27,7 +28,8 @@
 
 #define NX 15
 #define NU 4
-#define NP 22
+#define NP 23
+#define NG 8 /* rows of the path-constraint function g */
 #define NXF 13
 #define IY 14 /* index of the CTCS integrator state y */
 
@@ -49,7 +51,7 @@ static int final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8 && 
 enum {
     P_MWET = 0, P_MDRY = 1, P_ALPHA = 2, P_G = 3, P_J = 6, P_RT = 9, P_TMIN = 12, P_TMAX = 13,
     P_DELTA = 14, P_GAMMA = 15, P_THETA = 16, P_OMEGA = 17, P_SMIN = 18, P_SMAX = 19,
-    P_EPS = 20, P_SINIT = 21
+    P_EPS = 20, P_SINIT = 21, P_VMAX = 22
 };
 
 /* Solver settings; the same fields (in the same order) as the Python wrapper's struct. */
@@ -110,10 +112,12 @@ static void cross3(const double *a, const double *b, double *c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-/* Path constraints g (7 rows: mass, glide slope, tilt, rate, gimbal, T_max, T_min). */
+/* Path constraints g (8 rows: mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed;
+ * the speed row ||v||^2 - v_max^2 of section "6-DoF Powered Descent Guidance" is the constant
+ * -1 when v_max is not finite, i.e. there is no speed bound). */
 static void constraints(const double *x, const double *u, const double *p, double *g)
 {
-    const double *r = x + 1, *q = x + 7, *w = x + 11;
+    const double *r = x + 1, *v = x + 4, *q = x + 7, *w = x + 11;
     double Tn = norm3(u);
     double lat = sqrt(r[1] * r[1] + r[2] * r[2]);
     g[0] = p[P_MDRY] - x[0];
@@ -123,20 +127,22 @@ static void constraints(const double *x, const double *u, const double *p, doubl
     g[4] = Tn - u[0] / cos(p[P_DELTA]);
     g[5] = Tn - p[P_TMAX];
     g[6] = p[P_TMIN] - Tn;
+    g[7] = isfinite(p[P_VMAX]) ? v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - p[P_VMAX] * p[P_VMAX]
+                               : -1.0;
 }
 
-/* Gradients of g w.r.t. x (7 x 15) and w.r.t. T (7 x 3).  d||v||/dv := 0 for ||v|| <= NORM_EPS. */
-static void constraint_grads(const double *x, const double *u, const double *p, double Gx[7][NX],
-                             double Gt[7][3])
+/* Gradients of g w.r.t. x (8 x 15) and w.r.t. T (8 x 3).  d||v||/dv := 0 for ||v|| <= NORM_EPS. */
+static void constraint_grads(const double *x, const double *u, const double *p, double Gx[NG][NX],
+                             double Gt[NG][3])
 {
-    const double *r = x + 1, *q = x + 7, *w = x + 11;
+    const double *r = x + 1, *v = x + 4, *q = x + 7, *w = x + 11;
     double Tn = norm3(u);
     double lat = sqrt(r[1] * r[1] + r[2] * r[2]);
     double tg = tan(p[P_GAMMA]);
     double dT[3] = {0, 0, 0};
     int i;
-    memset(Gx, 0, sizeof(double) * 7 * NX);
-    memset(Gt, 0, sizeof(double) * 7 * 3);
+    memset(Gx, 0, sizeof(double) * NG * NX);
+    memset(Gt, 0, sizeof(double) * NG * 3);
     if (Tn > NORM_EPS)
         for (i = 0; i < 3; i++) dT[i] = u[i] / Tn;
     Gx[0][0] = -1.0;
@@ -154,6 +160,8 @@ static void constraint_grads(const double *x, const double *u, const double *p, 
         Gt[6][i] = -dT[i];
     }
     Gt[4][0] -= 1.0 / cos(p[P_DELTA]);
+    if (isfinite(p[P_VMAX]))
+        for (i = 0; i < 3; i++) Gx[7][4 + i] = 2.0 * v[i];
 }
 
 /* Augmented, time-dilated dynamics f(x,u) = s * (F(xi,T), sum_i [g_i]_+^2). */
@@ -162,7 +170,7 @@ void orc_dynamics(const double *x, const double *u, const double *p, double *f)
     const double *v = x + 4, *q = x + 7, *w = x + 11;
     const double *J = p + P_J, *rT = p + P_RT, *gI = p + P_G;
     double s = u[3], m = x[0];
-    double C[3][3], Om[4][4], g[7];
+    double C[3][3], Om[4][4], g[NG];
     double Jw[3], wxJw[3], rxT[3];
     double F[NX];
     int i, j;
@@ -187,7 +195,7 @@ void orc_dynamics(const double *x, const double *u, const double *p, double *f)
     for (i = 0; i < 3; i++) F[11 + i] = (rxT[i] - wxJw[i]) / J[i];
     constraints(x, u, p, g);
     F[IY] = 0.0;
-    for (i = 0; i < 7; i++) {
+    for (i = 0; i < NG; i++) {
         double gp = g[i] > 0.0 ? g[i] : 0.0;
         F[IY] += gp * gp;
     }
@@ -200,7 +208,7 @@ void orc_jacobians(const double *x, const double *u, const double *p, double *A,
     const double *q = x + 7, *w = x + 11;
     const double *J = p + P_J, *rT = p + P_RT;
     double s = u[3], m = x[0];
-    double C[3][3], Om[4][4], g[7], Gx[7][NX], Gt[7][3];
+    double C[3][3], Om[4][4], g[NG], Gx[NG][NX], Gt[NG][3];
     double CT[3], dCT_dq[3][4], Xi[4][3];
     double F[NX], f[NX];
     double Tn = norm3(u);
@@ -262,7 +270,7 @@ void orc_jacobians(const double *x, const double *u, const double *p, double *A,
     /* y_dot = sum_i [g_i]_+^2:  d/dx = sum_i 2 [g_i]_+ dg_i/dx */
     constraints(x, u, p, g);
     constraint_grads(x, u, p, Gx, Gt);
-    for (i = 0; i < 7; i++) {
+    for (i = 0; i < NG; i++) {
         double gp = g[i] > 0.0 ? g[i] : 0.0;
         for (j = 0; j < NX; j++) A[IY * NX + j] += 2.0 * gp * Gx[i][j];
     }
@@ -279,7 +287,7 @@ void orc_jacobians(const double *x, const double *u, const double *p, double *A,
         for (i = 0; i < 3; i++)
             for (j = 0; j < 3; j++) B[(11 + i) * NU + j] = Rx[i][j] / J[i];
     }
-    for (i = 0; i < 7; i++) {
+    for (i = 0; i < NG; i++) {
         double gp = g[i] > 0.0 ? g[i] : 0.0;
         for (j = 0; j < 3; j++) B[IY * NU + j] += 2.0 * gp * Gt[i][j];
     }

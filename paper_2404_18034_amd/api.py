@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-NX, NU, NP, NXF = 15, 4, 22, 13
+NX, NU, NP, NXF = 15, 4, 23, 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscp_batch.so")
 
@@ -458,7 +458,7 @@ def _solve_fn():
 
 
 def solve_differentiable(solver, x0, params, xf, K):
-    """(m_f, t_f) of the batched solve as torch functions of x0 [B, 15] and params [B, 22]
+    """(m_f, t_f) of the batched solve as torch functions of x0 [B, 15] and params [B, 23]
     (device tensors of the solver's dtype); gradients flow through the last SCP iteration.
     The solver must have been created with grad_pipg_steps > 0."""
     return _solve_fn().apply(x0, params, solver, xf, K)

@@ -11,7 +11,7 @@ namespace scp {
 
 constexpr int NX = 15;
 constexpr int NU = 4;
-constexpr int NP = 22;
+constexpr int NP = 23;
 constexpr int NXF = 13;
 constexpr int IY = 14;
 constexpr double NORM_EPS = 1e-4;  // below this a norm's derivative is taken as 0
@@ -21,6 +21,8 @@ template <typename R>
 struct Vehicle {
     R m_dry, alpha, g[3], Jinv[3], J[3], rT[3], T_min, T_max;
     R sec_delta, tan_gamma, tilt_c, w_max2;
+    R v_max2;       // squared speed bound (used when has_vmax)
+    bool has_vmax;  // v_max finite: the speed row joins the path constraints
 };
 
 template <typename R>
@@ -42,6 +44,8 @@ __device__ __forceinline__ Vehicle<R> load_vehicle(const R *p)
     v.tan_gamma = R(tan(double(p[15])));
     v.tilt_c = R(1.0 - cos(double(p[16])));
     v.w_max2 = p[17] * p[17];
+    v.has_vmax = isfinite(double(p[22]));
+    v.v_max2 = v.has_vmax ? p[22] * p[22] : R(0);
     return v;
 }
 
@@ -92,9 +96,10 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     F[12] = V.Jinv[1] * ((V.rT[2] * T0 - V.rT[0] * T2) - (w2 * Jw0 - w0 * Jw2));
     F[13] = V.Jinv[2] * ((V.rT[0] * T1 - V.rT[1] * T0) - (w0 * Jw1 - w1 * Jw0));
 
-    // path constraints g (mass, glide slope, tilt, rate, gimbal, T_max, T_min)
+    // path constraints g (mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed; the
+    // speed row is the constant -1 without a speed bound)
     const R lat = sqrt(x[2] * x[2] + x[3] * x[3]);
-    R g[7];
+    R g[8];
     g[0] = V.m_dry - m;
     g[1] = V.tan_gamma * lat - x[1];
     g[2] = R(2) * (q2 * q2 + q3 * q3) - V.tilt_c;
@@ -102,10 +107,11 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     g[4] = Tn - T0 * V.sec_delta;
     g[5] = Tn - V.T_max;
     g[6] = V.T_min - Tn;
-    R gp[7];
+    g[7] = V.has_vmax ? x[4] * x[4] + x[5] * x[5] + x[6] * x[6] - V.v_max2 : R(-1);
+    R gp[8];
     R Fy = R(0);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < 8; ++i) {
         gp[i] = g[i] > R(0) ? g[i] : R(0);
         Fy += gp[i] * gp[i];
     }
@@ -158,7 +164,7 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
                           (dw2 * Jw0 + w2 * dJw0 - dw0 * Jw2 - w0 * dJw2));
     dF[13] = V.Jinv[2] * ((V.rT[0] * dT1 - V.rT[1] * dT0) -
                           (dw0 * Jw1 + w0 * dJw1 - dw1 * Jw0 - w1 * dJw0));
-    R dg[7];
+    R dg[8];
     dg[0] = -dm;
     dg[1] = (lat > R(NORM_EPS) ? V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]) / lat : R(0)) - dx[1];
     dg[2] = R(4) * (q2 * dq2 + q3 * dq3);
@@ -166,9 +172,10 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     dg[4] = dTn - dT0 * V.sec_delta;
     dg[5] = dTn;
     dg[6] = -dTn;
+    dg[7] = V.has_vmax ? R(2) * (x[4] * dx[4] + x[5] * dx[5] + x[6] * dx[6]) : R(0);
     R dFy = R(0);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) dFy += R(2) * gp[i] * dg[i];
+    for (int i = 0; i < 8; ++i) dFy += R(2) * gp[i] * dg[i];
 #pragma unroll
     for (int i = 0; i < 14; ++i) df[i] = ds * F[i] + s * dF[i];
     df[IY] = ds * Fy + s * dFy;

@@ -102,6 +102,8 @@ __device__ __forceinline__ Vehicle<Dual<double, N>> lift_vehicle(const Vehicle<d
     V.tan_gamma = D(W.tan_gamma);
     V.tilt_c = D(W.tilt_c);
     V.w_max2 = D(W.w_max2);
+    V.v_max2 = D(W.v_max2);
+    V.has_vmax = W.has_vmax;
     return V;
 }
 

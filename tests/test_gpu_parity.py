@@ -406,3 +406,51 @@ def test_paper_monte_carlo_256_runs(dtype):
             np.testing.assert_array_equal(g[k][ok], o[k][ok])
     else:
         check_fp32_against_oracle(cfg, inst, g, o, "F1 fp32", kmax=30)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_speed_bound_short_horizon_all_runs(dtype):
+    # the paper's speed bound (the speed row of the path constraints, through the CTCS
+    # integrand and its linearization) on 64 runs of the speed-bounded workload, three
+    # subproblems, every run; the bound changes these trajectories (oracle with and without it)
+    print("case: speed bound, 64 runs, 3 subproblems, %s" % dtype, flush=True)
+    cfg = I.solver_settings("F1S", scp_iters_max=3, early_exit=0)
+    inst = I.make_instances("F1S", B=64)
+    g = _gpu(cfg, inst, dtype, k_max=30)
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
+    free = dict(inst, params=inst["params"].copy())
+    free["params"][:, 22] = np.inf
+    of = oracle.solve(cfg, free["x0"], free["xf"], free["params"], free["K"], kmax=30)
+    moved = np.max(np.abs(o["x"] - of["x"]) / np.array(cfg["px"]), axis=(1, 2))
+    print("speed bound moves the 3-subproblem trajectories by up to %.2e (median %.2e)"
+          % (moved.max(), np.median(moved)))
+    assert np.sum(moved > 1e-3) >= 16
+    if dtype == "f64":
+        errs = _errors(cfg, g, o)
+        _report("F1S fp64 3 subproblems", errs)
+        for e in errs:
+            assert e.max() <= TOL_F64
+    else:
+        check_fp32_against_oracle(cfg, inst, g, o, "F1S fp32 3 subproblems", kmax=30)
+
+
+def test_speed_bound_full_solve_fp64():
+    # the whole solve with the speed bound (at most 25 SCP iterations of 2,500 PIPG
+    # iterations): statuses, iteration counts and trajectories of the oracle on the runs it
+    # certifies as well conditioned
+    print("case: speed bound, 64 runs, full solve, f64", flush=True)
+    cfg = I.solver_settings("F1S")
+    inst = I.make_instances("F1S", B=64)
+    g = _gpu(cfg, inst, "f64", k_max=30)
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
+    ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
+    print("well conditioned: %d / %d; oracle status counts %s, GPU %s"
+          % (ok.sum(), ok.size, np.bincount(o["status"], minlength=3).tolist(),
+             np.bincount(g["status"], minlength=3).tolist()))
+    assert ok.mean() >= 0.6
+    errs = _errors(cfg, g, o)
+    _report("F1S fp64 (well-conditioned)", [e[ok] for e in errs])
+    for e in errs:
+        assert e[ok].max() <= TOL_F64
+    for k in ("status", "scp_iters", "pipg_iters"):
+        np.testing.assert_array_equal(g[k][ok], o[k][ok])

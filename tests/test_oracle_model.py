@@ -22,6 +22,7 @@ def rand_params(rng):
     p = I.nominal_params()
     p[6:9] = 0.01 * (1 + 0.2 * rng.uniform(-1, 1, 3))      # anisotropic inertia
     p[9:12] = [-0.01, 0.002 * rng.normal(), 0.002 * rng.normal()]
+    p[22] = 1.0 + rng.random()                              # a speed bound (active at |v| > 2)
     return p
 
 
@@ -113,6 +114,28 @@ def test_ctcs_integrand_is_sum_of_squared_violations():
     g = oracle.constraints(x, u, p)
     f = oracle.dynamics(x, u, p)
     assert f[14] == pytest.approx(3.0 * np.sum(np.maximum(g, 0.0) ** 2), rel=1e-14)
+
+
+def test_speed_bound_row():
+    # the speed row ||v||^2 - v_max^2 of the constraint list; without a bound (v_max = inf,
+    # the nominal value) it is the constant -1 and never enters the CTCS integrand
+    p = I.nominal_params()
+    assert np.isinf(p[22])
+    x = rand_state(RNG)
+    x[4:7] = [1.5, -2.0, 0.5]
+    u = np.array([2.0, 0.0, 0.0, 3.0])
+    assert oracle.constraints(x, u, p)[7] == -1.0
+    pv = p.copy(); pv[22] = 2.0
+    g = oracle.constraints(x, u, pv)
+    assert g[7] == pytest.approx(1.5 ** 2 + 2.0 ** 2 + 0.5 ** 2 - 4.0, abs=1e-14)
+    np.testing.assert_array_equal(g[:7], oracle.constraints(x, u, p)[:7])
+    # the augmented dynamics gain s * [g_8]_+^2 in the y row and nothing else
+    f, fv = oracle.dynamics(x, u, p), oracle.dynamics(x, u, pv)
+    np.testing.assert_array_equal(f[:14], fv[:14])
+    assert fv[14] - f[14] == pytest.approx(3.0 * g[7] ** 2, rel=1e-12)
+    # on the bound the row is zero
+    x[4:7] *= 2.0 / np.linalg.norm(x[4:7])
+    assert oracle.constraints(x, u, pv)[7] == pytest.approx(0.0, abs=1e-14)
 
 
 def test_constraint_readings():
