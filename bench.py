@@ -190,6 +190,68 @@ def multistart(args):
                       "four_starts": res["multi"]}), flush=True)
 
 
+def grad(args):
+    """Gradients (the vector-Jacobian product of the last SCP iteration, scp_batch_grad) on the
+    differentiation workload: 4,096 x K = 20 in FP32, the forward solve recorded (untimed),
+    then `steps` batched products timed (200 differentiated PIPG steps, checkpoints every 20).
+    The oracle's gradient is central differences of its truncated map (2 x 18 evaluations),
+    timed on a few instances.  One JSON line."""
+    import torch
+    import oracle
+    from paper_2404_18034_amd import api
+    from paper_2404_18034_amd import instances as I
+
+    cfg = I.solver_settings("C3")
+    inst = I.make_instances("C3")
+    B = len(inst["K"])
+    out = {"grad": "vector-Jacobian product of the last SCP iteration, 4,096 x K=20, FP32, "
+                   "200 differentiated PIPG steps (checkpoints every 20)"}
+    grads = []
+    # the RK4 share by the reverse sweep (general form) and by forward tangents (two
+    # parameters reach the discretization)
+    for name, tangent in (("reverse_rk4", 0), ("tangent_rk4", 1)):
+        solver = api.BatchSolver(dict(cfg, grad_rk4_tangent=tangent), dtype="f32", k_max=20,
+                                 max_batch=B, device=0)
+        prob = solver.to_device(inst)
+        sol, last = solver.solve_record_into(prob, solver.alloc_solution(B),
+                                             solver.alloc_lastiter(B))
+        cot = torch.ones((B, 2), dtype=torch.float32, device="cuda:0")
+        g = torch.empty((B, 18), dtype=torch.float32, device="cuda:0")
+        solver.grad_into(prob, last, cot, g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            solver.grad_into(prob, last, cot, g)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        grads.append(g.cpu().numpy())
+        out[name] = {"ms_per_batch": round(ms, 3), "gradients_per_s": round(B / (ms * 1e-3), 1),
+                     "finite": bool(np.all(np.isfinite(grads[-1])))}
+        solver.close()
+    out["forms_max_rel_diff"] = float(np.max(np.abs(grads[0] - grads[1])) /
+                                      max(np.max(np.abs(grads[0])), 1e-30))
+    if not args.no_cpu:
+        n = 4
+        t = time.perf_counter()
+        for b in range(n):
+            K = int(inst["K"][b])
+            L = oracle.lastiter_state(cfg, inst["x0"][b], inst["xf"][b], inst["params"][b], K)
+            theta = oracle.theta_of(inst["x0"][b], inst["params"][b])
+            for i in range(theta.size):
+                for sgn in (1.0, -1.0):
+                    th = theta.copy()
+                    th[i] += sgn * 1e-6
+                    oracle.truncated_map(cfg, inst["x0"][b], inst["xf"][b], inst["params"][b], K,
+                                         th, L, cfg["grad_pipg_steps"])
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(n / dt, 3), "unit": "gradients/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d instances, central differences (36 map "
+                                         "evaluations each, after the recorded solve), %.1f s"
+                                         % (n, dt)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +262,9 @@ def main():
                     help="C1 (default): the 1,024-instance Monte Carlo the metric is quoted on; "
                          "C2 (16,384 uneven K, early exit), C4 (65,536 x K=30) and F1 (the "
                          "paper's 256-run Monte Carlo) for reference")
+    ap.add_argument("--grad", action="store_true",
+                    help="time the batched gradient (scp_batch_grad) on the differentiation "
+                         "workload (4,096 x K=20)")
     ap.add_argument("--multistart", action="store_true",
                     help="multi-start on the paper's Monte Carlo at K=20 (four s_init guesses)")
     ap.add_argument("--sweep", action="store_true",
@@ -225,6 +290,9 @@ def main():
         return
     if args.multistart:
         multistart(args)
+        return
+    if args.grad:
+        grad(args)
         return
 
     import torch
