@@ -91,7 +91,8 @@ typedef struct {
                                    many waves per SIMD; FP64 always uses 0                */
     int32_t grad_rk4_tangent;   /* how scp_batch_grad differentiates the discretization:
                                    0 = reverse (adjoint) sweep through the RK4 stages,
-                                   1 = forward tangents along (alpha_mdot, T_max)          */
+                                   1 = forward tangents along (alpha_mdot, T_max); the
+                                   two agree to rounding, 1 is the faster here            */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;

@@ -141,7 +141,9 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
         setattr(s, name, int(cfg[name]))
     s.mode = int(cfg.get("mode", 0))
     s.occupancy = int(cfg.get("occupancy", 0))
-    s.grad_rk4_tangent = int(cfg.get("grad_rk4_tangent", 0))
+    # the tangent form of the RK4 share is the cheaper one for the two parameters that reach
+    # the discretization (the reverse sweep stays available and is checked against it)
+    s.grad_rk4_tangent = int(cfg.get("grad_rk4_tangent", 1))
     s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
     s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",

@@ -1082,7 +1082,11 @@ static hipError_t launch_grad_typed(const Config &cfg, int nsteps, int ckpt, con
     }
     const int threads = qp_block_threads(cfg.kmax);
     const size_t smem = grad_smem_bytes_r(cfg.kmax, sizeof(R));
-    if (threads <= 640)
+    // the workgroup-size bound sets the register budget: a 320-lane bound (k_max <= 20) leaves
+    // room for the kernel's per-lane state without spilling
+    if (threads <= 320)
+        grad_kernel<R, 320><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
+    else if (threads <= 640)
         grad_kernel<R, 640><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
     else
         grad_kernel<R, 1024><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
