@@ -496,21 +496,15 @@ __device__ __forceinline__ void proj_cone_ball<float>(float &t, float &z0, float
 }
 
 // Column i of A^-_k for the transposed product.  FP32: a per-lane LDS slot of 20 floats
-// (80 bytes), read back whole before each product as four 16-byte loads (at that stride eight
-// consecutive lanes cover all 32 banks once); keeping these 15 values out of registers is what
-// lets four 5-wave workgroups share a CU.  FP64: registers.
+// (80 bytes), read back in two halves of two 16-byte loads each, one half per part of the
+// product (at that stride eight consecutive lanes cover all 32 banks once); keeping these 15
+// values out of registers is what lets four 5-wave workgroups share a CU.  FP64: registers.
 template <typename R> struct ColStore;
 template <>
 struct ColStore<float> {
-    static constexpr int LDS_STRIDE = 20, N = 16;
+    static constexpr int LDS_STRIDE = 20;
     float *slot;
     __device__ __forceinline__ void put(int q, float v) { slot[q] = v; }
-    __device__ __forceinline__ void get(float (&c)[N]) const
-    {
-        const float4 *p = reinterpret_cast<const float4 *>(slot);
-        float4 *o = reinterpret_cast<float4 *>(c);
-        for (int n = 0; n < 4; ++n) o[n] = p[n];
-    }
     // entries 0..7 and 8..15 (the last is padding)
     __device__ __forceinline__ void get_lo(float (&c)[8]) const
     {
@@ -529,14 +523,10 @@ struct ColStore<float> {
 };
 template <>
 struct ColStore<double> {
-    static constexpr int LDS_STRIDE = 0, N = NX;
+    static constexpr int LDS_STRIDE = 0;
     double *unused;
     double c[NX];
     __device__ __forceinline__ void put(int q, double v) { c[q] = v; }
-    __device__ __forceinline__ void get(double (&o)[N]) const
-    {
-        for (int q = 0; q < NX; ++q) o[q] = c[q];
-    }
     __device__ __forceinline__ void get_lo(double (&o)[8]) const
     {
         for (int q = 0; q < 8; ++q) o[q] = c[q];
