@@ -271,7 +271,7 @@ def main():
                     help="batch-size sweep 1..65,536 on the paper's Monte Carlo distribution "
                          "against the oracle on the host (one JSON line per size)")
     ap.add_argument("--mode", type=int, default=None,
-                    help="dispatch mode (0 launches, 1 graph, 2 ordered, 3 persistent); "
+                    help="dispatch mode (0 launches, 1 graph, 2 ordered, 3 persistent, 4 K-bucketed); "
                          "default: autotuned on the workload")
     ap.add_argument("--occupancy", type=int, default=None, choices=[0, 4, 5, 6],
                     help="subproblem register-budget variant with --mode (default 0)")

@@ -82,7 +82,10 @@ typedef struct {
                                    count, descending (hardware dispatch as the work queue);
                                    3: as 1, with a persistent subproblem grid (resident
                                    workgroups pop instances from an atomic queue in that
-                                   order)                                                 */
+                                   order);
+                                   4: as 2, and when k_max > 20 the instances with K <= 20
+                                   are solved by the 320-lane subproblem kernel (a second
+                                   launch per SCP iteration) instead of the k_max-sized one */
     int32_t grad_pipg_steps;    /* PIPG steps of the differentiated last iteration (0: the
                                    handle computes no gradients and carves no scratch)     */
     int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */
@@ -169,14 +172,15 @@ scp_status scp_batch_profile(scp_batch h, int enable);
 scp_status scp_batch_profile_read(scp_batch h, double *ms, int32_t *launches);
 
 /* Autotuner.  Times the launch variants (mode, occupancy) = (1, 0), (2, 0), (3, 0), (1, 5),
- * (2, 5), (1, 6), (2, 6) -- variant v is entry v of that list; see scp_settings.mode and .occupancy -- with
+ * (2, 5), (1, 6), (2, 6), (4, 0), (4, 5), (4, 6) -- variant v is entry v of that list; see
+ * scp_settings.mode and .occupancy -- with
  * HIP events, solving `problem` into `solution` (whose contents are overwritten), and keeps
  * the fastest for later solves on this handle.  *variant_out receives its index and
  * ms_out[SCP_TUNE_VARIANTS] the measured milliseconds per variant (-1 where not timed).
  * With a non-NULL cache_path, a JSON-lines file keyed by (GPU arch, k_max, dtype,
  * early_exit, node_projections, batch) is consulted first -- a hit skips the timing -- and
  * the new result is appended.  Synchronizes the handle's stream. */
-#define SCP_TUNE_VARIANTS 7
+#define SCP_TUNE_VARIANTS 10
 scp_status scp_batch_autotune(scp_batch h, const scp_problem *problem, scp_solution *solution,
                               const char *cache_path, int32_t *variant_out, double *ms_out);
 

@@ -35,7 +35,7 @@ class ScpError(RuntimeError):
 
 
 # launch variants timed by scp_batch_autotune: (dispatch mode, occupancy)
-TUNE_VARIANTS = ((1, 0), (2, 0), (3, 0), (1, 5), (2, 5), (1, 6), (2, 6))
+TUNE_VARIANTS = ((1, 0), (2, 0), (3, 0), (1, 5), (2, 5), (1, 6), (2, 6), (4, 0), (4, 5), (4, 6))
 
 
 class Settings(ctypes.Structure):

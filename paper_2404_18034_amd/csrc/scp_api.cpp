@@ -41,7 +41,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
         return false;
     }
     if (s->early_exit && s->pipg_check_every < 1) { why = "pipg_check_every must be >= 1"; return false; }
-    if (s->mode < 0 || s->mode > 3) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered) or 3 (persistent)"; return false; }
+    if (s->mode < 0 || s->mode > 4) { why = "mode must be 0 (launches), 1 (graph), 2 (ordered), 3 (persistent) or 4 (K-bucketed)"; return false; }
     if (s->occupancy != 0 && (s->occupancy < 4 || s->occupancy > 6)) {
         why = "occupancy must be 0, 4, 5 or 6";
         return false;
@@ -267,7 +267,8 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.early_exit = s.early_exit;
     cfg.node_projections = s.node_projections;
     cfg.persistent_blocks = 0;
-    cfg.ordered = s.mode == 2 ? 1 : 0;
+    cfg.ordered = (s.mode == 2 || s.mode == 4) ? 1 : 0;
+    cfg.bucketed = s.mode == 4 ? 1 : 0;
     cfg.occupancy = s.occupancy;
     cfg.grad_rk4_tangent = s.grad_rk4_tangent;
     cfg.scp_tol = s.scp_tol;
@@ -528,8 +529,8 @@ static std::string tune_key(scp_batch h, int batch)
     return k.str();
 }
 
-static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2, 1, 2};
-static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 5, 5, 6, 6};
+static const int TUNE_MODE[SCP_TUNE_VARIANTS] = {1, 2, 3, 1, 2, 1, 2, 4, 4, 4};
+static const int TUNE_OCC[SCP_TUNE_VARIANTS] = {0, 0, 0, 5, 5, 6, 6, 0, 5, 6};
 
 static int cache_lookup(const char *path, const std::string &key)
 {

@@ -51,6 +51,7 @@ struct Args {
     int32_t *bucket;  // [kmax + 1] counting-sort buckets
     int32_t *order;   // [B] instances by node count, descending
     int use_order;    // subproblem workgroup w solves instance order[w]
+    int split;        // 0: every instance; 1: the first n_big of `order` (K > 20); 2: the rest
     // optional record of each subproblem's starting point (the last one solved remains):
     // reference [B][kmax][15], [B][kmax][4]; warm-start duals [B][kmax-1][15], [B][kmax-1];
     // buffered power-iteration estimate [B]
@@ -844,7 +845,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
     using Lds = QpLds<R, MAXT>;
-    const int KR = (kmax + 3) / 4 * 4;
+    const int KR = blockDim.x >> 4;  // rows of this workgroup (a multiple of 4)
     double *red = reinterpret_cast<double *>(smem_raw + Lds::BYTES);  // [16 waves * 8]
     // stopping-test maxima: two sets of six bit patterns (32-bit for FP32, 64-bit for FP64)
     using Bits = decltype(max_bits(R(0)));
@@ -1206,7 +1207,20 @@ subproblem_kernel(Args<R> a)
     // with ordered dispatch, workgroup w takes the w-th instance by node count (descending):
     // the hardware issues workgroups as earlier ones retire, so the longest instances start
     // first and the short ones fill in behind them
-    const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]) : blockIdx.x;
+    // with bucketed launches the K-descending order is split after the n_big instances with
+    // K > 20 (the end of the K = 21 bucket once the order is built): one launch of the k_max
+    // sized kernel takes those, one of the 320-lane kernel the rest
+    int idx = blockIdx.x;
+    if (a.split) {
+        const int nbig = a.kmax > 20 ? a.bucket[a.kmax - 21] : 0;
+        if (a.split == 1) {
+            if (idx >= nbig) return;
+        } else {
+            idx += nbig;
+            if (idx >= a.B) return;
+        }
+    }
+    const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
     subproblem_body<R, MAXT, (WPE >= 6)>(a, b, smem_raw);
 }
@@ -1413,6 +1427,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R));
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
+    a.split = 0;
+    const bool bucketed = cfg.bucketed && cfg.ordered && cfg.kmax > 20;
+    const size_t smem20 = qp_smem_bytes(20, sizeof(R));
     if (persistent || cfg.ordered) {
         const unsigned nb = (unsigned)((cfg.B + 255) / 256);
         order_histogram<R><<<dim3(nb), dim3(256), 0, stream>>>(a);
@@ -1447,6 +1464,16 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
                 subproblem_persistent<R, 640><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
             else
                 subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+        } else if (bucketed) {
+            a.split = 1;
+            if (maxt == 640)
+                launch_subproblem<R, 640>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            else
+                launch_subproblem<R, 1024>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            a.split = 2;
+            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, stream, a);
+            a.split = 0;
         } else if (maxt == 320) {
             launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else if (maxt == 640) {

@@ -32,6 +32,8 @@ struct Config {
     int early_exit, node_projections;
     int persistent_blocks;  // 0: one workgroup per instance; > 0: persistent grid size
     int ordered;            // 1: workgroups take instances by node count, descending
+    int bucketed;           // 1 (with ordered): instances with K <= 20 solved by the 320-lane
+                            //   subproblem kernel, the others by the k_max-sized one
     int occupancy;          // 4 / 5: FP32 subproblem variant bounded to 4 / 5 waves per SIMD
     int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;

@@ -285,10 +285,12 @@ def test_invalid_arguments_raise():
     s.close()
 
 
-@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (0, 5), (2, 5), (0, 6)])
+@pytest.mark.parametrize("mode,occupancy", [(1, 0), (2, 0), (3, 0), (0, 4), (0, 5), (2, 5), (0, 6),
+                                            (4, 0), (4, 5), (4, 6)])
 def test_dispatch_modes_match_plain_launches(mode, occupancy):
-    # graph replay, K-ordered dispatch and the persistent work queue compute the same thing as
-    # plain launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
+    # graph replay, K-ordered dispatch, the persistent work queue and the K-bucketed launches
+    # (K <= 20 in the 320-lane kernel) compute the same thing as plain launches, bit for bit,
+    # on a mixed-K batch with early exit; repeated replays too
     import torch
     cfg = I.solver_settings("C2")
     inst = I.make_instances("C2", B=40)
