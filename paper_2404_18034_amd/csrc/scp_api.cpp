@@ -129,6 +129,8 @@ struct scp_batch_s {
     // graph replay (mode 1): the launch sequence of one solve, captured once per set of
     // arguments on a private stream and replayed on the handle's stream
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux_stream = nullptr;  // K-bucketed mode: the second subproblem launch
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     const void *graph_key[22] = {};
@@ -269,6 +271,8 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.persistent_blocks = 0;
     cfg.ordered = (s.mode == 2 || s.mode == 4) ? 1 : 0;
     cfg.bucketed = s.mode == 4 ? 1 : 0;
+    cfg.aux_stream = nullptr;
+    cfg.ev_fork = cfg.ev_join = nullptr;
     cfg.occupancy = s.occupancy;
     cfg.grad_rk4_tangent = s.grad_rk4_tangent;
     cfg.scp_tol = s.scp_tol;
@@ -339,6 +343,25 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
 
     scp::Config cfg;
     fill_config(h, prob->batch, cfg);
+    if (h->st.mode == 4 && h->st.k_max > 20) {
+        // the second stream and the fork/join events of the K-bucketed launches (created once)
+        if (!h->aux_stream) {
+            e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+                if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+                h->aux_stream = nullptr;
+                h->ev_fork = nullptr;
+                if (cur != h->device) (void)hipSetDevice(cur);
+                return fail(h, SCP_ERR_HIP, std::string("auxiliary stream: ") + hipGetErrorString(e));
+            }
+        }
+        cfg.aux_stream = h->aux_stream;
+        cfg.ev_fork = h->ev_fork;
+        cfg.ev_join = h->ev_join;
+    }
     if (h->st.mode == 3) {
         if (h->persistent_grid == 0) {
             hipDeviceProp_t prop;
@@ -693,6 +716,9 @@ scp_status scp_batch_destroy(scp_batch h)
     drop_events(h);
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     delete h;
     return e == hipSuccess ? SCP_OK : SCP_ERR_HIP;
 }

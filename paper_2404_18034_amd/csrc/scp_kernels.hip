@@ -1465,15 +1465,26 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
             else
                 subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
         } else if (bucketed) {
+            // the two launches touch disjoint instances; on two streams they run side by side
+            hipStream_t s2 = cfg.aux_stream ? cfg.aux_stream : stream;
+            if (cfg.aux_stream) {
+                if ((e = hipEventRecord(cfg.ev_fork, stream)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(s2, cfg.ev_fork, 0)) != hipSuccess) return e;
+            }
+            a.split = 2;
+            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 1;
             if (maxt == 640)
                 launch_subproblem<R, 640>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
             else
                 launch_subproblem<R, 1024>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            a.split = 2;
-            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, stream, a);
             a.split = 0;
+            if (cfg.aux_stream) {
+                if ((e = hipEventRecord(cfg.ev_join, s2)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(stream, cfg.ev_join, 0)) != hipSuccess) return e;
+            }
         } else if (maxt == 320) {
             launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else if (maxt == 640) {

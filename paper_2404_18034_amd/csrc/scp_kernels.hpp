@@ -34,6 +34,9 @@ struct Config {
     int ordered;            // 1: workgroups take instances by node count, descending
     int bucketed;           // 1 (with ordered): instances with K <= 20 solved by the 320-lane
                             //   subproblem kernel, the others by the k_max-sized one
+    hipStream_t aux_stream; // bucketed: the 320-lane launch runs on this stream, forked from
+    hipEvent_t ev_fork;     //   and joined back to the launch stream by these two events
+    hipEvent_t ev_join;     //   (null: both launches on the launch stream, one after the other)
     int occupancy;          // 4 / 5: FP32 subproblem variant bounded to 4 / 5 waves per SIMD
     int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
