@@ -59,7 +59,7 @@ class Settings(ctypes.Structure):
         ("scp_iters_max", ctypes.c_int32), ("pipg_iters_max", ctypes.c_int32),
         ("pipg_check_every", ctypes.c_int32), ("rk4_substeps", ctypes.c_int32),
         ("power_iters_max", ctypes.c_int32), ("early_exit", ctypes.c_int32),
-        ("node_projections", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("node_projections", ctypes.c_int32), ("scalar_dilation", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
         ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
@@ -80,9 +80,9 @@ def make_settings(cfg, cls=None):
     """Build the oracle's settings struct from a plain dict of solver settings."""
     s = (cls or Settings)()
     for name, _ in Settings._fields_:
-        if name in ("px", "pu", "pad"):
+        if name in ("px", "pu"):
             continue
-        setattr(s, name, cfg[name])
+        setattr(s, name, cfg.get(name, 0) if name == "scalar_dilation" else cfg[name])
     for i, v in enumerate(cfg["px"]):
         s.px[i] = float(v)
     for i, v in enumerate(cfg["pu"]):

@@ -64,7 +64,8 @@ typedef struct {
     int32_t early_exit;        /* 1: SCP and PIPG stop on their tolerances; 0: fixed work */
     int32_t node_projections;  /* bitmask of node-wise convex sets: 1 dry mass, 2 glide slope,
                                   4 tilt, 8 rate, 16 thrust (gimbal cone and T_max); 0 none */
-    int32_t pad;
+    int32_t scalar_dilation;   /* 1: one dilation value over the whole horizon (the per-node
+                                  dilation controls of a subproblem constrained equal)   */
     double scp_tol, feas_tol;
     double pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
@@ -804,11 +805,26 @@ static int pipg_custom(const orc_settings *st, const qp_t *qp, double sigma, int
                 if (k > 0)
                     for (i = 0; i < NX; i++)
                         gr += qp->Bp[((k - 1) * NX + i) * NU + j] * tl.phi[(k - 1) * NX + i];
-                hat.u[k * NU + j] =
-                    clampd(tl.u[k * NU + j] - alpha * gr, qp->umin[k * NU + j], qp->umax[k * NU + j]);
+                hat.u[k * NU + j] = tl.u[k * NU + j] - alpha * gr;
+                if (!(st->scalar_dilation && j == NU - 1))
+                    hat.u[k * NU + j] = clampd(hat.u[k * NU + j], qp->umin[k * NU + j],
+                                               qp->umax[k * NU + j]);
             }
             if (st->node_projections & 16)
                 project_thrust(hat.u + k * NU, qp->ubar + k * NU, st->pu, qp->p);
+        }
+        if (st->scalar_dilation) {
+            /* one dilation value: the Euclidean projection of the K fresh dilation values
+             * onto {s_1 = ... = s_K} intersected with every node's box is their mean,
+             * clamped to the intersection of the boxes */
+            double mean = 0.0, lo = -INFINITY, hi = INFINITY;
+            for (k = 0; k < K; k++) {
+                mean += hat.u[k * NU + NU - 1];
+                lo = fmax(lo, qp->umin[k * NU + NU - 1]);
+                hi = fmin(hi, qp->umax[k * NU + NU - 1]);
+            }
+            mean = clampd(mean / K, lo, hi);
+            for (k = 0; k < K; k++) hat.u[k * NU + NU - 1] = mean;
         }
         for (i = 0; i < M * NX; i++) {
             double a = tl.mup[i] - alpha * (st->w_ep + tl.phi[i]);
