@@ -275,6 +275,8 @@ def main():
                          "default: autotuned on the workload")
     ap.add_argument("--occupancy", type=int, default=None, choices=[0, 4, 5, 6],
                     help="subproblem register-budget variant with --mode (default 0)")
+    ap.add_argument("--scalar-dilation", action="store_true",
+                    help="one dilation value over the horizon instead of one per node")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -310,7 +312,7 @@ def main():
 
     wl = args.workload
     cfgd = I.CONFIGS[wl]
-    cfg = I.solver_settings(wl)
+    cfg = I.solver_settings(wl, scalar_dilation=int(args.scalar_dilation))
     if args.mode is not None:
         cfg["mode"] = args.mode
         if args.occupancy is not None:
@@ -359,7 +361,8 @@ def main():
     achieved = flops_per_solve / (sub_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    traffic=measured_traffic(wl), kernel="subproblem_kernel",
+                    traffic=None if args.scalar_dilation else measured_traffic(wl),
+                    kernel="subproblem_kernel",
                     avg_launch_ms=round(sub_ms / max(sub_launches, 1), 4),
                     kernel_ms_per_step={k: round(v[0] / nprof, 3) for k, v in per.items()})
 
@@ -371,10 +374,12 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": WORKLOAD_NAMES[wl],
+        "config": {"workload": WORKLOAD_NAMES[wl] + (", one dilation value over the horizon"
+                                                     if args.scalar_dilation else ""),
                    "batch": B, "K": sorted(set(int(k) for k in cfgd["K"])),
                    "scp_iters": cfg["scp_iters_max"], "pipg_iters": cfg["pipg_iters_max"],
                    "early_exit": bool(cfg["early_exit"]), "node_projections": cfg["node_projections"],
+                   "scalar_dilation": bool(args.scalar_dilation),
                    "mode": solver.mode(), "parallelism": "single GPU"},
         "converged": converged, "solves_per_s_all": round(B / (ms_per_step * 1e-3), 2),
         "roofline": roofline,

@@ -96,6 +96,15 @@ typedef struct {
                                    0 = reverse (adjoint) sweep through the RK4 stages,
                                    1 = forward tangents along (alpha_mdot, T_max); the
                                    two agree to rounding, 1 is the faster here            */
+    int32_t scalar_dilation;    /* 0: the dilation s is a first-order-hold control with one
+                                   value per node (section "Free-Final-Time Problem");
+                                   1: one dilation value over the horizon, i.e. each
+                                   subproblem restricted to s_1 = ... = s_K (its dynamics
+                                   column in interval k is B^-_k[:, s] + B^+_k[:, s]); PIPG
+                                   projects the dilation values onto their mean clamped to
+                                   the s box.  The initial guess must hold one value (it does:
+                                   s_init).  Not with mode 3 or grad_pipg_steps > 0
+                                   (SCP_ERR_UNSUPPORTED at scp_batch_create)              */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;

@@ -10,9 +10,11 @@ Layouts (row-major float64 numpy arrays):
   x0[B,15], xf[B,13], params[B,23], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
 
 ``solve_f32`` runs the same C source compiled with float in place of double
-(``_scp_oracle_f32.so``): a single-precision evaluation of the same algorithm.  Tests use it
-only to measure how far FP32 rounding alone moves an instance's result (its FP32
-conditioning); it is never an expected value.
+(``_scp_oracle_f32.so``): a single-precision evaluation of the same algorithm; with
+``contract=True`` the same source built with fused multiply-adds allowed
+(``_scp_oracle_f32fma.so``), another equally valid single-precision rounding pattern.  Tests
+use them only to measure how far FP32 rounding alone moves an instance's result (its FP32
+conditioning); they are never an expected value.
 """
 import ctypes
 import os
@@ -25,6 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scp_oracle.c")
 _SO = os.path.join(_HERE, "_scp_oracle.so")
 _SO32 = os.path.join(_HERE, "_scp_oracle_f32.so")
+_SO32F = os.path.join(_HERE, "_scp_oracle_f32fma.so")
 
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
           "-D_POSIX_C_SOURCE=200809L", "-pthread"]
@@ -35,9 +38,8 @@ def build(force=False):
     twin (every ``double`` of the source read as ``float``)."""
     import re
     import tempfile
-    if (not force and os.path.exists(_SO) and os.path.exists(_SO32)
-            and os.path.getmtime(_SO) >= os.path.getmtime(_SRC)
-            and os.path.getmtime(_SO32) >= os.path.getmtime(_SRC)):
+    if (not force and all(os.path.exists(p) and os.path.getmtime(p) >= os.path.getmtime(_SRC)
+                          for p in (_SO, _SO32, _SO32F))):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
@@ -51,6 +53,10 @@ def build(force=False):
         tmp = _SO32 + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src32, "-lm"])
         os.replace(tmp, _SO32)
+        flags = [f for f in CFLAGS if f != "-ffp-contract=off"] + ["-ffp-contract=fast", "-mfma"]
+        tmp = _SO32F + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *flags, "-o", tmp, src32, "-lm"])
+        os.replace(tmp, _SO32F)
     return _SO
 
 
@@ -272,15 +278,16 @@ def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
     return out
 
 
-_lib32 = None
+_lib32 = {}
 
 
-def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None):
-    """The same solve evaluated in single precision (see the module note); float64 results."""
-    global _lib32
-    if _lib32 is None:
+def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None, contract=False):
+    """The same solve evaluated in single precision (see the module note); float64 results.
+    ``contract``: the build with fused multiply-adds."""
+    if contract not in _lib32:
         build()
-        _lib32 = ctypes.CDLL(_SO32)
+        _lib32[contract] = ctypes.CDLL(_SO32F if contract else _SO32)
+    lib32 = _lib32[contract]
     st = make_settings(cfg, Settings32)
     f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     x0, xf, params = f(x0), f(xf), f(params)
@@ -294,7 +301,7 @@ def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None):
                pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B, np.float32),
                ctcs_viol=np.zeros(B, np.float32), objective=np.zeros(B, np.float32))
     v = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    rc = _lib32.orc_solve_batch(
+    rc = lib32.orc_solve_batch(
         ctypes.byref(st), B, kmax, v(x0), v(xf), v(params), v(K), nthreads, v(out["x"]),
         v(out["u"]), v(out["t_f"]), v(out["m_f"]), v(out["status"]), v(out["scp_iters"]),
         v(out["pipg_iters"]), v(out["defect_inf"]), v(out["ctcs_viol"]), v(out["objective"]))

@@ -47,6 +47,7 @@ class Settings(ctypes.Structure):
         ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("grad_pipg_steps", ctypes.c_int32), ("grad_ckpt_every", ctypes.c_int32),
         ("occupancy", ctypes.c_int32), ("grad_rk4_tangent", ctypes.c_int32),
+        ("scalar_dilation", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
         ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
@@ -144,6 +145,7 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
     # the tangent form of the RK4 share is the cheaper one for the two parameters that reach
     # the discretization (the reverse sweep stays available and is checked against it)
     s.grad_rk4_tangent = int(cfg.get("grad_rk4_tangent", 1))
+    s.scalar_dilation = int(cfg.get("scalar_dilation", 0))
     s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
     s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",

@@ -47,6 +47,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
         return false;
     }
     if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
+    if (s->scalar_dilation != 0 && s->scalar_dilation != 1) { why = "scalar_dilation must be 0 or 1"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -184,6 +185,10 @@ scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_
         g_create_error = "gradient state of this k_max and dtype does not fit one workgroup's LDS";
         return SCP_ERR_UNSUPPORTED;
     }
+    if (settings->scalar_dilation && (settings->mode == 3 || settings->grad_pipg_steps > 0)) {
+        g_create_error = "scalar_dilation is not implemented with mode 3 or with gradients";
+        return SCP_ERR_UNSUPPORTED;
+    }
     const Layout L = layout_of(settings);
     if (!workspace || workspace_bytes < L.total) {
         g_create_error = "workspace missing or smaller than scp_batch_workspace_bytes()";
@@ -275,6 +280,7 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.ev_fork = cfg.ev_join = nullptr;
     cfg.occupancy = s.occupancy;
     cfg.grad_rk4_tangent = s.grad_rk4_tangent;
+    cfg.scalar_dilation = s.scalar_dilation;
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -548,7 +554,7 @@ static std::string tune_key(scp_batch h, int batch)
     std::ostringstream k;
     k << arch << ":kmax=" << h->st.k_max << ":dtype=" << (h->st.dtype == SCP_F64 ? "f64" : "f32")
       << ":early_exit=" << h->st.early_exit << ":proj=" << h->st.node_projections
-      << ":batch=" << batch;
+      << ":sd=" << h->st.scalar_dilation << ":batch=" << batch;
     return k.str();
 }
 
@@ -604,6 +610,7 @@ scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution
     int best = -1;
     double best_ms = 0.0;
     for (int m = 0; m < SCP_TUNE_VARIANTS; ++m) {
+        if (h->st.scalar_dilation && TUNE_MODE[m] == 3) continue;  // not with one dilation value
         set_variant(h, m);
         scp_status st = scp_batch_solve(h, prob, sol);  // capture + warm-up
         if (st != SCP_OK) break;

@@ -31,6 +31,7 @@ struct Args {
     int B, kmax, j;  // j: 1-based SCP iteration of this launch
     int scp_iters_max, pipg_iters_max, pipg_check_every, rk4_substeps, power_iters_max;
     int early_exit, node_projections;
+    int scalar_dilation;  // 1: one dilation value over the horizon
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
@@ -830,7 +831,12 @@ prepare_kernel(Args<R> a)
 // The block products inside an interval use row broadcasts of register values (DPP);
 // only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
-template <typename R, int MAXT, bool FAIR = false>
+// SD: one dilation value over the horizon.  The subproblem is the per-node one restricted
+// to s_1 = ... = s_K; the Euclidean projection of the fresh dilation values onto that set
+// and the s box is their mean, clamped to the box (every node holds the same reference s
+// and so the same box).  Each node row publishes its value through LDS, and after a barrier
+// every lane sums them in node order, so all nodes take a bit-identical mean.
+template <typename R, int MAXT, bool FAIR = false, bool SD = false>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
 {
@@ -840,8 +846,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
     // waves whose four rows all lie beyond the instance's last node skip the arithmetic
-    // (they only take part in the barriers)
-    const bool wact = ((t >> 6) << 2) < K;
+    // (they only take part in the barriers); with SD every wave computes (on zero rows) and
+    // reaches the extra barrier of the dilation mean
+    const bool wact = SD || ((t >> 6) << 2) < K;
 
     // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
     using Lds = QpLds<R, MAXT>;
@@ -851,6 +858,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     using Bits = decltype(max_bits(R(0)));
     Bits *chk = reinterpret_cast<Bits *>(red + 128);               // [2][8]
     R *myCol = reinterpret_cast<R *>(red + 144) + t * ColStore<R>::LDS_STRIDE;  // FP32: [KR * 16][20]
+    // SD: fresh dilation value of each node (the reduction scratch is idle during PIPG)
+    R *sdil = reinterpret_cast<R *>(red);  // [KR]
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -1091,7 +1100,17 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             if (tmem) un = v;
         }
         xn = clampbox(xn, xlo, xhi);
-        un = clampbox(un, ulo, uhi);
+        if constexpr (SD) {
+            // every wave is active in this variant, so every wave reaches the barrier
+            if (node && i == 7) sdil[k] = un;  // the read copy of s
+            __syncthreads();
+            if (qi == 3) {
+                R s = R(0);
+                for (int q = 0; q < K; ++q) s += sdil[q];
+                un = s / R(K);
+            }
+        }
+        un = clampbox(un, ulo, uhi);  // rows without a node: ulo = uhi = 0
         // extrapolation 2z^ - z~ and relaxation z~ += rho (z^ - z~), in place
         vx = R(2) * xn - xt;
         xt += rho * (xn - xt);
@@ -1199,7 +1218,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 // ------------------------------------------------------------------------------------------
 
 // WPE: minimum waves per SIMD the register allocation must allow (1: no constraint).
-template <typename R, int MAXT, int WPE>
+template <typename R, int MAXT, int WPE, bool SD = false>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE)))
 subproblem_kernel(Args<R> a)
 {
@@ -1222,7 +1241,7 @@ subproblem_kernel(Args<R> a)
     }
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
-    subproblem_body<R, MAXT, (WPE >= 6)>(a, b, smem_raw);
+    subproblem_body<R, MAXT, (WPE >= 6), SD>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
@@ -1314,6 +1333,12 @@ template <typename R, int MAXT>
 static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
                               const Args<R> &a)
 {
+    if (a.scalar_dilation) {
+        // one variant: FP32 bounded to five waves per SIMD, FP64 the compiler's choice
+        subproblem_kernel<R, MAXT, (sizeof(R) == 4 ? 5 : 1), true>
+            <<<dim3(B), dim3(threads), smem, stream>>>(a);
+        return;
+    }
     if constexpr (sizeof(R) == 4) {
         if (occupancy == 6) {
             subproblem_kernel<R, MAXT, 6><<<dim3(B), dim3(threads), smem, stream>>>(a);
@@ -1349,6 +1374,7 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.power_iters_max = cfg.power_iters_max;
     a.early_exit = cfg.early_exit;
     a.node_projections = cfg.node_projections;
+    a.scalar_dilation = cfg.scalar_dilation;
     a.scp_tol = cfg.scp_tol;
     a.feas_tol = cfg.feas_tol;
     a.pipg_eps_abs = cfg.pipg_eps_abs;

@@ -39,6 +39,8 @@ struct Config {
     hipEvent_t ev_join;     //   (null: both launches on the launch stream, one after the other)
     int occupancy;          // 4 / 5: FP32 subproblem variant bounded to 4 / 5 waves per SIMD
     int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
+    int scalar_dilation;    // 1: one dilation value over the horizon (PIPG projects the
+                            //   dilation controls of all nodes onto their mean)
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;

@@ -34,11 +34,13 @@ def well_conditioned(cfg, inst, o, rel, kmax=None):
     return (amp <= AMP_MAX) & (o2["status"] == o["status"]) & (o2["scp_iters"] == o["scp_iters"])
 
 
-def fp32_deviation(cfg, inst, o, kmax=None):
+def fp32_deviation(cfg, inst, o, kmax=None, contract=False):
     """How far FP32 rounding alone moves each instance: the oracle's algorithm evaluated in
-    single precision against the FP64 oracle, scaled-absolute on x and on u (the controls can
-    be far more sensitive than the states).  Oracle-only."""
-    f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=kmax)
+    single precision (with fused multiply-adds when `contract`) against the FP64 oracle,
+    scaled-absolute on x and on u (the controls can be far more sensitive than the states).
+    Oracle-only."""
+    f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=kmax,
+                         contract=contract)
     px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
     with np.errstate(invalid="ignore"):
         return (np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2)),
@@ -46,6 +48,7 @@ def fp32_deviation(cfg, inst, o, kmax=None):
 
 
 FP32_DRAWS = 8
+FP32_FMA_DRAWS = 2
 
 
 def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
@@ -59,14 +62,18 @@ def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
     two draws place within 1e-5 by up to 9e-5; eight draws are taken), so every instance is held to
     max(TOL_F32, 20x its plain-FP32 control deviation), and the final time (the integral of the
     dilation control) to TOL_F32 where the controls are certified.  Status and iteration counts
-    must agree."""
+    must agree.  The GPU contracts multiply-adds, so FP32_FMA_DRAWS further draws take the
+    oracle's single-precision build with contraction (on the inputs and on a moved x0): its
+    rounding pattern can move an instance far more than the uncontracted one does."""
     dx, du = fp32_deviation(cfg, inst, o, kmax)
     rng = np.random.default_rng(11)
-    for _ in range(FP32_DRAWS - 1):
-        inst2 = dict(inst, x0=inst["x0"] * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0,
-                                                                       inst["x0"].shape)))
+    for d in range(FP32_DRAWS - 1 + FP32_FMA_DRAWS):
+        contract = d >= FP32_DRAWS - 1
+        rel = 0.0 if d == FP32_DRAWS - 1 else 1e-7
+        inst2 = dict(inst, x0=inst["x0"] * (1.0 + rel * rng.uniform(-1.0, 1.0,
+                                                                      inst["x0"].shape)))
         inst2["x0"][:, 14] = 0.0
-        dx2, du2 = fp32_deviation(cfg, inst2, o, kmax)
+        dx2, du2 = fp32_deviation(cfg, inst2, o, kmax, contract=contract)
         dx, du = np.maximum(dx, dx2), np.maximum(du, du2)
     fin = o["status"] != 2
     ok = fin & (dx <= TOL_F32 / 10)
