@@ -858,8 +858,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     using Bits = decltype(max_bits(R(0)));
     Bits *chk = reinterpret_cast<Bits *>(red + 128);               // [2][8]
     R *myCol = reinterpret_cast<R *>(red + 144) + t * ColStore<R>::LDS_STRIDE;  // FP32: [KR * 16][20]
-    // SD: fresh dilation value of each node (the reduction scratch is idle during PIPG)
-    R *sdil = reinterpret_cast<R *>(red);  // [KR]
+    // SD: partial sums of the fresh dilation values, one per wave (the reduction scratch is
+    // idle during PIPG)
+    R *sdil = reinterpret_cast<R *>(red);  // [KR / 4]
+    const R invK = R(1.0 / K);
 
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
@@ -1101,13 +1103,20 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         xn = clampbox(xn, xlo, xhi);
         if constexpr (SD) {
-            // every wave is active in this variant, so every wave reaches the barrier
-            if (node && i == 7) sdil[k] = un;  // the read copy of s
+            // every wave is active in this variant, so every wave reaches the barrier.  The
+            // read copies of s (lane 7 of each node row) are summed over the wave's four rows
+            // by two butterfly exchanges (each adds the same pair on both lanes, so the wave
+            // agrees bit for bit), lane 7 publishes the wave's partial, and after the barrier
+            // every lane adds the partials in wave order.
+            R sv = (node && i == 7) ? un : R(0);
+            sv += __shfl_xor(sv, 16);
+            sv += __shfl_xor(sv, 32);
+            if ((t & 63) == 7) sdil[t >> 6] = sv;
             __syncthreads();
             if (qi == 3) {
                 R s = R(0);
-                for (int q = 0; q < K; ++q) s += sdil[q];
-                un = s / R(K);
+                for (int q = 0; q < (KR >> 2); ++q) s += sdil[q];
+                un = s * invK;
             }
         }
         un = clampbox(un, ulo, uhi);  // rows without a node: ulo = uhi = 0
@@ -1334,8 +1343,9 @@ static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hi
                               const Args<R> &a)
 {
     if (a.scalar_dilation) {
-        // one variant: FP32 bounded to five waves per SIMD, FP64 the compiler's choice
-        subproblem_kernel<R, MAXT, (sizeof(R) == 4 ? 5 : 1), true>
+        // one variant: FP32 bounded to six waves per SIMD (with the priority rotation), FP64
+        // the compiler's choice
+        subproblem_kernel<R, MAXT, (sizeof(R) == 4 ? 6 : 1), true>
             <<<dim3(B), dim3(threads), smem, stream>>>(a);
         return;
     }
