@@ -834,8 +834,9 @@ prepare_kernel(Args<R> a)
 // SD: one dilation value over the horizon.  The subproblem is the per-node one restricted
 // to s_1 = ... = s_K; the Euclidean projection of the fresh dilation values onto that set
 // and the s box is their mean, clamped to the box (every node holds the same reference s
-// and so the same box).  Each node row publishes its value through LDS, and after a barrier
-// every lane sums them in node order, so all nodes take a bit-identical mean.
+// and so the same box).  Each wave publishes the sum of its rows' values through LDS before
+// the step's barrier; after it every lane adds the partials in wave order, so all nodes take
+// a bit-identical mean, and the s lanes finish their primal update there.
 template <typename R, int MAXT, bool FAIR = false, bool SD = false>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
@@ -846,9 +847,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
     // waves whose four rows all lie beyond the instance's last node skip the arithmetic
-    // (they only take part in the barriers); with SD every wave computes (on zero rows) and
-    // reaches the extra barrier of the dilation mean
-    const bool wact = SD || ((t >> 6) << 2) < K;
+    // (they only take part in the barriers)
+    const bool wact = ((t >> 6) << 2) < K;
 
     // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
     using Lds = QpLds<R, MAXT>;
@@ -1103,28 +1103,21 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         }
         xn = clampbox(xn, xlo, xhi);
         if constexpr (SD) {
-            // every wave is active in this variant, so every wave reaches the barrier.  The
-            // read copies of s (lane 7 of each node row) are summed over the wave's four rows
+            // the read copies of s (lane 7 of each node row) summed over the wave's four rows
             // by two butterfly exchanges (each adds the same pair on both lanes, so the wave
-            // agrees bit for bit), lane 7 publishes the wave's partial, and after the barrier
-            // every lane adds the partials in wave order.
+            // agrees bit for bit); lane 7 publishes the wave's partial.  The s lanes finish
+            // their update after the barrier; their values stored here are never read.
             R sv = (node && i == 7) ? un : R(0);
             sv += __shfl_xor(sv, 16);
             sv += __shfl_xor(sv, 32);
             if ((t & 63) == 7) sdil[t >> 6] = sv;
-            __syncthreads();
-            if (qi == 3) {
-                R s = R(0);
-                for (int q = 0; q < (KR >> 2); ++q) s += sdil[q];
-                un = s * invK;
-            }
         }
         un = clampbox(un, ulo, uhi);  // rows without a node: ulo = uhi = 0
         // extrapolation 2z^ - z~ and relaxation z~ += rho (z^ - z~), in place
         vx = R(2) * xn - xt;
         xt += rho * (xn - xt);
         vu = R(2) * un - ut;
-        ut += rho * (un - ut);
+        if (!SD || qi != 3) ut += rho * (un - ut);
         sl[Lds::VX] = vx;
         sl[Lds::VU] = vu;
         }  // wact
@@ -1132,7 +1125,20 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         if (wact) {
         // ---- dual (proportional-integral) step ----
         const R vnext = sl[Lds::VX + 16];   // 2x^ - x~ of node k+1 (zero beyond the last node)
-        const R vunext = sl[Lds::VU + 16];  // 2u^ - u~ of node k+1
+        R vunext = sl[Lds::VU + 16];        // 2u^ - u~ of node k+1
+        if constexpr (SD) {
+            // the mean of the active waves' partials, then the box, the extrapolation and the
+            // relaxation of s; every node holds the same s, so node k+1's 2u^ - u~ of s is
+            // this lane's
+            if (qi == 3) {
+                R s = R(0);
+                for (int q = 0; q < ((K + 3) >> 2); ++q) s += sdil[q];
+                un = clampbox(s * invK, ulo, uhi);
+                vu = R(2) * un - ut;
+                ut += rho * (un - ut);
+                vunext = vu;
+            }
+        }
         R mupn = nup - alpha * (wep + vphi);
         R mumn = num - alpha * (wep - vphi);
         mupn = mupn > R(0) ? mupn : R(0);
