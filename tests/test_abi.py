@@ -109,6 +109,19 @@ def test_gradient_settings_validated(lib):
     assert api.workspace_bytes(bad) == 0
 
 
+def test_scalar_dilation_setting_validated(lib):
+    # 0 and 1 are accepted (same workspace: the variant needs no device memory of its own),
+    # other values are rejected; the combinations it does not implement are refused at
+    # create time (a GPU test covers that)
+    cfg = I.solver_settings("C1")
+    n0 = api.workspace_bytes(api.make_settings(dict(cfg, scalar_dilation=0), "f32", 20, 64))
+    n1 = api.workspace_bytes(api.make_settings(dict(cfg, scalar_dilation=1), "f32", 20, 64))
+    assert n0 > 0 and n1 == n0
+    for v in (2, -1):
+        assert api.workspace_bytes(api.make_settings(dict(cfg, scalar_dilation=v),
+                                                     "f32", 20, 64)) == 0
+
+
 def test_tuning_variant_count_matches_header():
     import re
     from paper_2404_18034_amd import api
