@@ -104,7 +104,10 @@ typedef struct {
                                    projects the dilation values onto their mean clamped to
                                    the s box.  The initial guess must hold one value (it does:
                                    s_init).  Not with mode 3 or grad_pipg_steps > 0
-                                   (SCP_ERR_UNSUPPORTED at scp_batch_create)              */
+                                   (SCP_ERR_UNSUPPORTED at scp_batch_create); occupancy is
+                                   ignored (the FP32 variant is bounded to six waves per
+                                   SIMD) and scp_batch_autotune times modes 1, 2 and 4
+                                   only (the other entries of ms_out stay -1)             */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;

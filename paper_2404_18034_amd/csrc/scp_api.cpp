@@ -610,7 +610,8 @@ scp_status scp_batch_autotune(scp_batch h, const scp_problem *prob, scp_solution
     int best = -1;
     double best_ms = 0.0;
     for (int m = 0; m < SCP_TUNE_VARIANTS; ++m) {
-        if (h->st.scalar_dilation && TUNE_MODE[m] == 3) continue;  // not with one dilation value
+        // one dilation value: no persistent form, and one register budget whatever occupancy
+        if (h->st.scalar_dilation && (TUNE_MODE[m] == 3 || TUNE_OCC[m] != 0)) continue;
         set_variant(h, m);
         scp_status st = scp_batch_solve(h, prob, sol);  // capture + warm-up
         if (st != SCP_OK) break;

@@ -107,3 +107,26 @@ def test_scalar_dilation_unsupported_combinations(over):
     with pytest.raises(api.ScpError) as e:
         api.BatchSolver(cfg, dtype="f32", k_max=30, max_batch=8)
     assert e.value.code == 8
+
+
+def test_scalar_dilation_autotune_times_modes_1_2_4_only():
+    # one register budget whatever the occupancy setting, no persistent form: the autotuner
+    # times (1, 0), (2, 0) and (4, 0) and keeps the results of plain launches
+    import torch
+    print("case: scalar dilation, autotune, C2 x 40", flush=True)
+    cfg = I.solver_settings("C2", scalar_dilation=1)
+    inst = I.make_instances("C2", B=40)
+    ref = _gpu(cfg, inst, "f32", k_max=30)
+    s = api.BatchSolver(cfg, dtype="f32", k_max=30, max_batch=64)
+    try:
+        prob = s.to_device(inst)
+        sol = s.alloc_solution(40)
+        best, ms = s.autotune(prob, sol)
+        assert set(ms) == {(1, 0), (2, 0), (4, 0)}, ms
+        assert best in ms
+        s.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        for k in ref:
+            np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k], err_msg=k)
+    finally:
+        s.close()
