@@ -121,7 +121,7 @@ def lib():
             "orc_pipg": [S, c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, c_double,
                          c_int, c_int, _D, _D, _D, _D, _D, _D],
             "orc_solve_batch": [S, c_int, c_int, _D, _D, _D, _I, c_int, _D, _D, _D, _D, _I, _I,
-                                _I, _D, _D, _D],
+                                _I, _D, _D, _D, _D],
             "orc_solve_trace": [S, c_int, _D, _D, _D, _D, _D, _D, _I, c_int, _D],
             "orc_lastiter_state": [S, c_int, _D, _D, _D, _D, _D, _D, _D],
             "orc_iter_len": [c_int],
@@ -266,13 +266,13 @@ def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
     out = dict(x=np.zeros((B, kmax, NX)), u=np.zeros((B, kmax, NU)), t_f=np.zeros(B),
                m_f=np.zeros(B), status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
                pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B), ctcs_viol=np.zeros(B),
-               objective=np.zeros(B))
+               objective=np.zeros(B), step=np.zeros(B))
     rc = lib().orc_solve_batch(
         ctypes.byref(st), B, kmax, a, b, c, K.ctypes.data_as(_I), nthreads,
         _p(out["x"]), _p(out["u"]), _p(out["t_f"]), _p(out["m_f"]),
         out["status"].ctypes.data_as(_I), out["scp_iters"].ctypes.data_as(_I),
         out["pipg_iters"].ctypes.data_as(_I), _p(out["defect_inf"]), _p(out["ctcs_viol"]),
-        _p(out["objective"]))
+        _p(out["objective"]), _p(out["step"]))
     if rc != 0:
         raise ValueError("oracle: invalid node count")
     return out
@@ -299,12 +299,14 @@ def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None, contract=False):
                t_f=np.zeros(B, np.float32), m_f=np.zeros(B, np.float32),
                status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
                pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B, np.float32),
-               ctcs_viol=np.zeros(B, np.float32), objective=np.zeros(B, np.float32))
+               ctcs_viol=np.zeros(B, np.float32), objective=np.zeros(B, np.float32),
+               step=np.zeros(B, np.float32))
     v = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     rc = lib32.orc_solve_batch(
         ctypes.byref(st), B, kmax, v(x0), v(xf), v(params), v(K), nthreads, v(out["x"]),
         v(out["u"]), v(out["t_f"]), v(out["m_f"]), v(out["status"]), v(out["scp_iters"]),
-        v(out["pipg_iters"]), v(out["defect_inf"]), v(out["ctcs_viol"]), v(out["objective"]))
+        v(out["pipg_iters"]), v(out["defect_inf"]), v(out["ctcs_viol"]), v(out["objective"]),
+        v(out["step"]))
     if rc != 0:
         raise ValueError("oracle: invalid node count")
     return {k: (a.astype(np.float64) if a.dtype == np.float32 else a) for k, a in out.items()}

@@ -725,7 +725,7 @@ static void proj_ball(double *z, int n, double rad)
 }
 
 /* State sets (mask bits 1, 2, 4, 8): m >= m_dry, glide-slope cone on r, tilt disk on
- * (q2, q3), rate ball on w. */
+ * (q2, q3), rate ball on w, at an interior node. */
 static void project_state(double *xh, const double *xb, const double *px, const double *p,
                           int mask)
 {
@@ -736,6 +736,27 @@ static void project_state(double *xh, const double *xb, const double *px, const 
     if (mask & 2) proj_soc(&x[1], &x[2], 2, 1.0 / tan(p[P_GAMMA]));
     if (mask & 4) proj_ball(&x[9], 2, sqrt(0.5 * (1.0 - cos(p[P_THETA]))));
     if (mask & 8) proj_ball(&x[11], 3, p[P_OMEGA]);
+    for (i = 0; i < NX; i++) xh[i] = (x[i] - xb[i]) / px[i];
+}
+
+/* The same sets at the last node, intersected with the final boundary condition: the fixed
+ * components already hold their values (r, v, (q2, q3) and (w2, w3) are fixed), so the
+ * glide-slope cone and the tilt disk have nothing left to project; the mass bound acts on
+ * the free mass, and the rate ball on the free roll rate w1 through the fixed transverse
+ * rates: |w1| <= sqrt(w_max^2 - w2^2 - w3^2) (zero when the fixed rates alone leave the
+ * ball), which is the Euclidean projection onto the ball's slice. */
+static void project_state_final(double *xh, const double *xb, const double *px,
+                                const double *p, int mask)
+{
+    double x[NX];
+    int i;
+    for (i = 0; i < NX; i++) x[i] = xb[i] + px[i] * xh[i];
+    if ((mask & 1) && x[0] < p[P_MDRY]) x[0] = p[P_MDRY];
+    if (mask & 8) {
+        double r2 = p[P_OMEGA] * p[P_OMEGA] - x[12] * x[12] - x[13] * x[13];
+        double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+        x[11] = clampd(x[11], -r, r);
+    }
     for (i = 0; i < NX; i++) xh[i] = (x[i] - xb[i]) / px[i];
 }
 
@@ -790,14 +811,19 @@ static int pipg_custom(const orc_settings *st, const qp_t *qp, double sigma, int
                 if (k == K - 1) gr += st->w_cost * ecost[j];
                 hat.x[k * NX + j] = tl.x[k * NX + j] - alpha * gr;
             }
-            if (st->node_projections & 15)
-                project_state(hat.x + k * NX, qp->xbar + k * NX, st->px, qp->p,
-                              st->node_projections);
+            /* boundary values (the first node is fixed entirely), then the node-wise state
+             * sets on what is left free */
             if (k == 0)
                 for (j = 0; j < NX; j++) hat.x[j] = qp->zi[j];
-            if (k == K - 1)
+            if (k == K - 1 && k > 0)
                 for (j = 0; j < NXF; j++)
                     if (final_fixed(1 + j)) hat.x[k * NX + 1 + j] = qp->zf[j];
+            if ((st->node_projections & 15) && k > 0 && k < K - 1)
+                project_state(hat.x + k * NX, qp->xbar + k * NX, st->px, qp->p,
+                              st->node_projections);
+            if ((st->node_projections & 9) && k > 0 && k == K - 1)
+                project_state_final(hat.x + k * NX, qp->xbar + k * NX, st->px, qp->p,
+                                    st->node_projections);
             for (j = 0; j < NU; j++) {
                 double gr = st->w_prox * tl.u[k * NU + j];
                 if (k < M)
@@ -1096,6 +1122,7 @@ typedef struct {
     const int32_t *K;
     double *x, *u, *tf, *mf, *defect, *ctcs, *objective;
     int32_t *status, *scp_iters, *pipg_iters;
+    double *step; /* optional (NULL): scaled step of the last subproblem solved */
 } batch_job;
 
 static void *batch_worker(void *arg)
@@ -1118,6 +1145,7 @@ static void *batch_worker(void *arg)
         jb->status[b] = r.status;
         jb->scp_iters[b] = r.scp_iters;
         jb->pipg_iters[b] = r.pipg_iters;
+        if (jb->step) jb->step[b] = r.step;
     }
     return NULL;
 }
@@ -1125,7 +1153,8 @@ static void *batch_worker(void *arg)
 int orc_solve_batch(const orc_settings *st, int B, int kmax, const double *x0, const double *xf,
                     const double *p, const int32_t *K, int nthreads, double *x, double *u,
                     double *tf, double *mf, int32_t *status, int32_t *scp_iters,
-                    int32_t *pipg_iters, double *defect, double *ctcs, double *objective)
+                    int32_t *pipg_iters, double *defect, double *ctcs, double *objective,
+                    double *step)
 {
     pthread_t th[256];
     batch_job jobs[256];
@@ -1136,7 +1165,7 @@ int orc_solve_batch(const orc_settings *st, int B, int kmax, const double *x0, c
         if (K[t] < 2 || K[t] > kmax) return -1;
     for (t = 0; t < nthreads; t++) {
         batch_job jb = {st, B, kmax, nthreads, t, x0, xf, p, K, x, u, tf, mf, defect, ctcs,
-                        objective, status, scp_iters, pipg_iters};
+                        objective, status, scp_iters, pipg_iters, step};
         jobs[t] = jb;
     }
     if (nthreads == 1) {

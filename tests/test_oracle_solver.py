@@ -225,3 +225,84 @@ def test_thrust_projection_brute_force():
         r = minimize(lambda z: np.sum((z - T) ** 2), x0=np.array([1.0, 0, 0]), constraints=cons,
                      method="SLSQP", options=dict(ftol=1e-14, maxiter=500))
         np.testing.assert_allclose(pu_[:3], r.x, atol=1e-5)
+
+
+def _node_set_qp(K, over_params, xf_w=(0.0, 0.0, 0.0), iters=0):
+    """Scaled QP at the initial guess of the single-instance problem with parameters changed
+    so that every node-wise set binds early (tight thrust ball and gimbal, glide slope near the
+    straight-line guess, small tilt and rate bounds, dry mass near the wet mass), and a landing
+    condition with nonzero transverse rates; returns (cfg, qp, node) with the reference and
+    scales the node-wise projections act through."""
+    cfg = I.solver_settings("C0", node_projections=31)
+    inst = I.make_instances("C0")
+    x0, xf, p = inst["x0"][0].copy(), inst["xf"][0].copy(), inst["params"][0].copy()
+    for i, v in over_params.items():
+        p[i] = v
+    xf[10:13] = xf_w
+    xb, ub = oracle.init_guess(K, x0, xf, p)
+    xe, A, Bm, Bp = oracle.discretize(K, xb, ub, p, cfg["rk4_substeps"])
+    qp = oracle.build_qp(cfg, p, K, x0, xf, xb, ub, xe, A, Bm, Bp)
+    node = dict(xbar=xb, ubar=ub, px=cfg["px"], pu=cfg["pu"], p=p, mask=31)
+    return cfg, qp, node
+
+
+TIGHT = {1: 1.995, 13: 2.02, 14: np.radians(4.0), 15: np.radians(44.0), 16: np.radians(1.5),
+         17: 0.0075}
+
+
+@pytest.mark.parametrize("K,n_iter", [(4, 40), (6, 60)])
+def test_pipg_custom_equals_generic_pipg_node_sets(K, n_iter):
+    # with every node-wise convex set on, at the real prescaling and a nonzero reference: the
+    # block solver (projections through the reference and the scales, the rate ball's slice at
+    # the last node) gives the iterates of the generic PIPG on the dense form, whose projection
+    # is written from the sets' geometry; every set binds during the run
+    cfg, qp, node = _node_set_qp(K, TIGHT, xf_w=(0.004, 0.0055, -0.005))
+    sigma, _ = oracle.power(cfg, qp)
+    alpha, beta = _alpha_beta(cfg, sigma)
+    D = DQ.assemble(qp, cfg["w_prox"], cfg["w_cost"], cfg["w_ep"])
+    active = {}
+    z, w, v = DQ.pipg_generic(D, qp, alpha, beta, cfg["rho"], n_iter, node=node, active=active)
+    sol, n = oracle.pipg(cfg, qp, sigma, n_iter, 0, ref=(node["xbar"], node["ubar"], node["p"]))
+    print("\nsets that moved an iterate (count over nodes and steps):", active)
+    assert set(active) >= {"mass", "glide", "tilt", "rate", "rate slice", "thrust"}
+    np.testing.assert_allclose(DQ.join(sol), z, atol=1e-10)
+    np.testing.assert_allclose(sol["phi"].ravel(), w, atol=1e-10)
+    np.testing.assert_allclose(sol["th"], v, atol=1e-10)
+
+
+def test_pipg_fixed_point_certificate_node_sets():
+    # the returned point of a long run with every node-wise set on satisfies the
+    # projected-gradient fixed point with the dense projection, primal feasibility and
+    # complementarity, and lies in every set
+    K = 5
+    cfg, qp, node = _node_set_qp(K, TIGHT, xf_w=(0.004, 0.0055, -0.005))
+    sigma, _ = oracle.power(cfg, qp)
+    alpha, beta = _alpha_beta(cfg, sigma)
+    sol, _ = oracle.pipg(cfg, qp, sigma, 800000, 0, ref=(node["xbar"], node["ubar"], node["p"]))
+    D = DQ.assemble(qp, cfg["w_prox"], cfg["w_cost"], cfg["w_ep"])
+    z = DQ.join(sol)
+    grad = D["P"] * z + D["p"] + D["G"].T @ sol["phi"].ravel() + D["H"].T @ sol["th"]
+    active = {}
+    assert np.abs(DQ.project(z - alpha * grad, qp, K, node, active) - z).max() < 1e-7
+    print("\nsets active at the fixed point:", active)
+    assert len(active) >= 2
+    assert np.abs(D["G"] @ z - D["g"]).max() < 1e-7
+    slack = D["H"] @ z - D["h"]
+    assert slack.max() < 1e-7
+    assert np.abs(sol["th"] * slack).max() < 1e-7
+    # the point is its own projection (it lies in every set)
+    np.testing.assert_allclose(DQ.project(z, qp, K, node), z, atol=1e-12)
+
+
+def test_dense_cone_projection_against_brute_force():
+    # the dense module's geometric cone projection is itself pinned by constrained minimization
+    rng = np.random.default_rng(21)
+    for a in (0.3, 1.0, 2.7):
+        for _ in range(10):
+            t, z = rng.normal() * 2, rng.normal(size=2) * 2
+            pt, pz = DQ.cone_project(t, z, a)
+            cons = [{"type": "ineq", "fun": lambda v: a * v[0] - np.linalg.norm(v[1:])}]
+            r = minimize(lambda v: np.sum((v - np.r_[t, z]) ** 2), x0=np.array([1.0, 0, 0]),
+                         constraints=cons, method="SLSQP",
+                         options=dict(ftol=1e-15, maxiter=500))
+            np.testing.assert_allclose(np.r_[pt, pz], r.x, atol=1e-5)
