@@ -1,15 +1,17 @@
 """Benchmark: converged 6-DoF SCP solves per second on one MI355X.
 
-Workload: the 1,024-instance Monte Carlo (K = 20 nodes, FP32, fixed 15 SCP iterations x
-1,000 PIPG iterations, seeded dispersions), inputs resident in HBM before timing.  A step
-is one complete batched solve (initial guess, every discretization, power iteration, PIPG
-and reference update).  Prints one JSON line.
+Workload: the throughput Monte Carlo (65,536 instances, K = 30 nodes, FP32, fixed 15 SCP
+iterations x 1,000 PIPG iterations, seeded dispersions including inertia and thrust lever
+arm), inputs resident in HBM before timing.  A step is one complete batched solve (initial
+guess, every discretization, power iteration, PIPG and reference update).  Beside the FP32
+headline the same workload is solved by the FP64 path (fewer steps) and reported in the same
+line.  Prints one JSON line.
 
-Roofline: the dominant kernel is the subproblem kernel (power iteration + PIPG).  Its
-achieved rate is the algorithmic FP32 work of the PIPG iterations it ran divided by its
-launch durations, measured with HIP events recorded on the stream the library launches
-on.  The CPU baseline is the FP64 oracle on a bounded sample of the same workload, run on
-the host cores.
+Roofline: the dominant kernel is the subproblem kernel (PIPG).  Its achieved rate is the
+algorithmic FP32 work of the PIPG iterations it ran divided by its launch durations,
+measured with HIP events recorded on the stream the library launches on.  The CPU baseline
+is the FP64 oracle on a bounded, evenly spaced sample of the same workload, run on the host
+cores.
 """
 import argparse
 import json
@@ -23,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed issue)
-WORKLOAD = "C1"
+WORKLOAD = "C4"
 WORKLOAD_NAMES = {
     "C1": "Monte Carlo 1,024 x K=20, 15 SCP x 1,000 PIPG iterations, seeded dispersions (seed 1)",
     "C2": "uneven Monte Carlo 16,384 x K in {10,20,30}, early exit (SCP 1e-4, PIPG 1e-5), "
@@ -47,7 +49,9 @@ def pipg_flops_per_iter(K):
 KERNEL_SOURCES = ("paper_2404_18034_amd/csrc/scp_kernels.hip",
                   "paper_2404_18034_amd/csrc/scp_common.hpp",
                   "paper_2404_18034_amd/csrc/lander_model.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "subproblem_kernel_traffic_mc1024.txt")
+# hardware-counter summaries of the subproblem kernel's HBM traffic, per workload
+TRAFFIC_FILES = {"C1": os.path.join(ROOT, "profiles", "subproblem_kernel_traffic_mc1024.txt"),
+                 "C4": os.path.join(ROOT, "profiles", "subproblem_kernel_traffic_c4.txt")}
 
 
 def kernel_source_hash():
@@ -60,13 +64,14 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per subproblem launch from the committed hardware-counter summary (taken on
-    the 1,024-instance Monte Carlo), or None for another workload, when there is no summary, or
-    when the kernel sources changed since the counters were taken."""
-    if workload != "C1" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per subproblem launch from the committed hardware-counter summary of this
+    workload, or None when there is no summary or when the kernel sources changed since the
+    counters were taken."""
+    path = TRAFFIC_FILES.get(workload)
+    if path is None or not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
@@ -80,14 +85,17 @@ def measured_traffic(workload):
 
 
 def cpu_baseline(cfg, inst, n_sample, threads, kmax):
-    """The FP64 oracle on the host cores: `n_sample` instances on `threads` threads, plus a
-    serial run on a quarter of them (the paper's CPU reference solves one instance at a
-    time)."""
+    """The FP64 oracle on the host cores: `n_sample` evenly spaced instances of the batch
+    (ids stride * i) on `threads` threads, plus a serial run on a sixteenth of them (the
+    paper's CPU reference solves one instance at a time)."""
     import oracle
     oracle.build()
+    B = inst["K"].shape[0]
+    stride = max(1, B // n_sample)
     out = {}
     for n, th in ((n_sample, threads), (max(1, n_sample // 16), 1)):
-        sub = {k: v[:n] for k, v in inst.items()}
+        ids = np.arange(n) * stride
+        sub = {k: v[ids] for k, v in inst.items()}
         t = time.perf_counter()
         r = oracle.solve(cfg, sub["x0"], sub["xf"], sub["params"], sub["K"], kmax=kmax,
                          nthreads=th)
@@ -96,10 +104,37 @@ def cpu_baseline(cfg, inst, n_sample, threads, kmax):
     n1, dt1, conv1 = out[1]
     return dict(value=round(conv / dt, 3), unit="converged solves/s", cores=threads,
                 kind="oracle",
-                sample="first %d of the %d instances (same settings), %d threads, %.1f s wall, "
-                       "%d converged" % (n, inst["K"].shape[0], threads, dt, conv),
+                sample="instances %d*i, i < %d, of the %d (same settings), %d threads, %.1f s "
+                       "wall, %d converged; the rate is that of the sample" % (
+                           stride, n, B, threads, dt, conv),
                 single_thread=dict(value=round(conv1 / dt1, 3), instances=n1,
                                    wall_s=round(dt1, 2), converged=conv1))
+
+
+def fp64_leg(cfg, inst, steps, K):
+    """The same workload on the FP64 path (graph replay, the compiler's register budget): one
+    untimed solve, then `steps` timed solves."""
+    import torch
+    from paper_2404_18034_amd import api
+    B = inst["K"].shape[0]
+    solver = api.BatchSolver(dict(cfg, mode=1, occupancy=0), dtype="f64", k_max=K, max_batch=B,
+                             device=0)
+    try:
+        prob = solver.to_device(inst)
+        sol = solver.alloc_solution(B)
+        solver.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            solver.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        conv = int(np.sum(sol["status"].cpu().numpy() == 0))
+    finally:
+        solver.close()
+    return dict(value=round(conv / (ms * 1e-3), 2), unit="converged solves/s", dtype="f64",
+                steps=steps, ms_per_step=round(ms, 3), converged=conv,
+                solves_per_s_all=round(B / (ms * 1e-3), 2))
 
 
 def sweep(args):
@@ -154,15 +189,15 @@ def sweep(args):
 
 
 def multistart(args):
-    """Multi-start on the paper's Monte Carlo at K = 20 (256 problems; starts with the initial
-    dilation guess s_init in {4, 5, 6, 7}, all 1,024 solves in one batch, then the choice of
-    the converged start of lowest cost): converged problems and time, against the single
-    start s_init = 5.  One JSON line."""
+    """Multi-start on the paper's Monte Carlo at K = 20 with the node-wise convex sets (256
+    problems; starts with the initial dilation guess s_init in {4, 5, 6, 7}, all 1,024 solves
+    in one batch, then the choice of the converged start of lowest cost): converged problems
+    and time, against the single start s_init = 5.  One JSON line."""
     import torch
     from paper_2404_18034_amd import api
     from paper_2404_18034_amd import instances as I
 
-    cfg = I.solver_settings("F1")
+    cfg = I.solver_settings("F1", node_projections=31)
     cfg["mode"], cfg["occupancy"] = 1, 6
     inst = I.make_instances("F1")
     inst["K"] = np.full(256, 20, np.int32)
@@ -259,9 +294,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1"],
-                    help="C1 (default): the 1,024-instance Monte Carlo the metric is quoted on; "
-                         "C2 (16,384 uneven K, early exit), C4 (65,536 x K=30) and F1 (the "
-                         "paper's 256-run Monte Carlo) for reference")
+                    help="C4 (default): the 65,536 x K=30 throughput Monte Carlo, the largest "
+                         "single-GPU configuration of the metric's 1k-64k range; C1 (1,024 x "
+                         "K=20), C2 (16,384 uneven K, early exit) and F1 (the paper's 256-run "
+                         "Monte Carlo) for reference")
+    ap.add_argument("--fp64-steps", type=int, default=1,
+                    help="timed solves of the same workload on the FP64 path (0: skip)")
     ap.add_argument("--grad", action="store_true",
                     help="time the batched gradient (scp_batch_grad) on the differentiation "
                          "workload (4,096 x K=20)")
@@ -380,17 +418,20 @@ def main():
                    "scp_iters": cfg["scp_iters_max"], "pipg_iters": cfg["pipg_iters_max"],
                    "early_exit": bool(cfg["early_exit"]), "node_projections": cfg["node_projections"],
                    "scalar_dilation": bool(args.scalar_dilation),
+                   "power_iteration": "f32" if cfg.get("power_fp32", 0) else "f64",
                    "mode": solver.mode(), "parallelism": "single GPU"},
         "converged": converged, "solves_per_s_all": round(B / (ms_per_step * 1e-3), 2),
         "roofline": roofline,
     }
     if tuned is not None:
         out["autotune_ms"] = {str(m): round(v, 3) for m, v in tuned[1].items()}
+    solver.close()
+    if args.dtype == "f32" and args.fp64_steps > 0:
+        out["fp64"] = fp64_leg(cfg, inst, args.fp64_steps, K)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(cfg, inst, args.cpu_sample, threads, K)
     print(json.dumps(out), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":

@@ -17,6 +17,14 @@
  *   All arrays are dense, row-major, device-resident (allocated by the caller on the
  *   device the handle was created for), and 16-byte aligned.
  *
+ * Shapes
+ *   The structs below pass bare pointers, so the library cannot see an array's shape or
+ *   element type: it trusts the caller to pass arrays of the documented shapes and of the
+ *   handle's dtype.  Before anything is launched it checks what it can see -- null pointers,
+ *   16-byte alignment, the batch against max_batch -- and an instance whose K is outside
+ *   [2, k_max] is not solved (status 3).  The Python binding checks every array's shape,
+ *   dtype, device and contiguity before it calls in.
+ *
  * Threading and ordering
  *   Every call that takes device memory only enqueues work on the handle's HIP stream and
  *   returns; outputs are valid after the stream is synchronized.  A handle is not
@@ -108,6 +116,12 @@ typedef struct {
                                    ignored (the FP32 variant is bounded to six waves per
                                    SIMD) and scp_batch_autotune times modes 1, 2 and 4
                                    only (the other entries of ms_out stay -1)             */
+    int32_t power_fp32;         /* precision of the customized power iteration (Algorithm
+                                   "Customized power iteration") on the FP32 path: 0 = the
+                                   iterate and the block products in FP64 over the FP32
+                                   blocks (default); 1 = in FP32, sigma and the stopping
+                                   test still FP64 (faster, a variant).  Ignored with
+                                   SCP_F64.  Must be 0 or 1                               */
     double scp_tol;             /* converged: scaled step inf-norm <= scp_tol ...          */
     double feas_tol;            /* ... and scaled defect, scaled CTCS excess <= feas_tol   */
     double pipg_eps_abs, pipg_eps_rel;
@@ -218,7 +232,10 @@ typedef struct {
 scp_status scp_batch_solve_record(scp_batch h, const scp_problem *problem,
                                   scp_solution *solution, const scp_lastiter *last);
 
-/* Vector-Jacobian product of the last SCP iteration.  The differentiated map, an extension
+/* Vector-Jacobian product of the last SCP iteration (not the full [B][2][18] Jacobian: a
+ * caller that wants both rows calls it twice, with cotangents (1, 0) and (0, 1), as the Python
+ * binding's autograd function does for a general cotangent in one call).  The differentiated
+ * map, an extension
  * (the paper does not differentiate its solver), takes
  *     theta = (x0[15], m_wet, alpha_mdot, T_max)
  * to (m_f, t_f) through one SCP iteration started from `last`: the discretization at
@@ -237,9 +254,9 @@ scp_status scp_batch_solve_record(scp_batch h, const scp_problem *problem,
 scp_status scp_batch_grad(scp_batch h, const scp_problem *problem, const scp_lastiter *last,
                           const void *cotangent, void *grad, void *value);
 
-/* Parallel multi-start (named in the paper's Conclusion as future work: several initial
- * guesses per problem are solved in parallel and the converged trajectory of lowest cost is
- * kept).  `solution` holds a batch solved by this handle of problems * starts instances in
+/* Multi-start choice (the paper's Conclusion names multi-start as future work): after one
+ * batched solve of every start of every problem, pick for each problem its cheapest converged
+ * start.  `solution` holds a batch solved by this handle of problems * starts instances in
  * which the starts of problem p are instances p*starts .. p*starts + starts - 1 (they differ
  * only in their initial guess, e.g. the dilation guess s_init in params).  For each problem:
  *   best  int32 [problems]  the start with status 0 and the smallest objective (ties: the

@@ -7,7 +7,10 @@ imports the GPU library.  The C source (``scp_oracle.c``) is compiled with gcc, 
 fast-math and without FMA contraction, into ``_scp_oracle.so`` next to it.
 
 Layouts (row-major float64 numpy arrays):
-  x0[B,15], xf[B,13], params[B,23], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,4].
+  x0[B,15], xf[B,13], params[B,24], K[B] (int32); trajectories x[B,kmax,15], u[B,kmax,n_u].
+The controls are u = (T, s) (n_u = 4) or, for a settings dict with n_u = 7, u = (T, gamma, s)
+with the reaction-control torque gamma: the same C source built with -DNU=7
+(``_scp_oracle_nu7.so``).
 
 ``solve_f32`` runs the same C source compiled with float in place of double
 (``_scp_oracle_f32.so``): a single-precision evaluation of the same algorithm; with
@@ -22,12 +25,13 @@ import subprocess
 
 import numpy as np
 
-NX, NU, NP, NXF = 15, 4, 23, 13
+NX, NU, NP, NXF = 15, 4, 24, 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scp_oracle.c")
 _SO = os.path.join(_HERE, "_scp_oracle.so")
 _SO32 = os.path.join(_HERE, "_scp_oracle_f32.so")
 _SO32F = os.path.join(_HERE, "_scp_oracle_f32fma.so")
+_SO7 = os.path.join(_HERE, "_scp_oracle_nu7.so")
 
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
           "-D_POSIX_C_SOURCE=200809L", "-pthread"]
@@ -39,11 +43,14 @@ def build(force=False):
     import re
     import tempfile
     if (not force and all(os.path.exists(p) and os.path.getmtime(p) >= os.path.getmtime(_SRC)
-                          for p in (_SO, _SO32, _SO32F))):
+                          for p in (_SO, _SO32, _SO32F, _SO7))):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _SO)
+    tmp = _SO7 + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, "-DNU=7", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _SO7)
     with tempfile.TemporaryDirectory() as d:
         src32 = os.path.join(d, "scp_oracle_f32.c")
         with open(_SRC) as f:
@@ -76,15 +83,26 @@ class Settings(ctypes.Structure):
     ]
 
 
+class Settings7(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double * 7 if n == "pu" else t) for n, t in Settings._fields_]
+
+
 class Settings32(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float if t is ctypes.c_double else
                  (ctypes.c_float * NX if n == "px" else ctypes.c_float * NU if n == "pu" else t))
                 for n, t in Settings._fields_]
 
 
+def n_u(cfg):
+    """Number of controls of a settings dict: 4 (thrust, dilation) or 7 (with the torque)."""
+    return int(cfg.get("n_u", NU))
+
+
 def make_settings(cfg, cls=None):
     """Build the oracle's settings struct from a plain dict of solver settings."""
-    s = (cls or Settings)()
+    if cls is None:
+        cls = Settings7 if n_u(cfg) == 7 else Settings
+    s = cls()
     for name, _ in Settings._fields_:
         if name in ("px", "pu"):
             continue
@@ -97,16 +115,28 @@ def make_settings(cfg, cls=None):
 
 
 _lib = None
+_lib7 = None
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)
 
 
-def lib():
-    global _lib
+def lib(nu=NU):
+    """The oracle library for n_u controls (4, or 7 with the reaction-control torque)."""
+    global _lib, _lib7
+    if nu == 7:
+        if _lib7 is None:
+            build()
+            _lib7 = _bind(ctypes.CDLL(_SO7), Settings7)
+        return _lib7
     if _lib is None:
         build()
-        L = ctypes.CDLL(_SO)
-        S = ctypes.POINTER(Settings)
+        _lib = _bind(ctypes.CDLL(_SO), Settings)
+    return _lib
+
+
+def _bind(L, settings_cls):
+    if True:
+        S = ctypes.POINTER(settings_cls)
         c_int, c_double = ctypes.c_int, ctypes.c_double
         sig = {
             "orc_dynamics": [_D, _D, _D, _D],
@@ -138,8 +168,7 @@ def lib():
         L.orc_iter_len.restype = c_int
         L.orc_lastiter_state.restype = c_int
         L.orc_stopping.restype = c_int
-        _lib = L
-    return _lib
+    return L
 
 
 def _d(a):
@@ -153,23 +182,24 @@ def _p(a):
 
 # ----------------------------------------------------------------------------- model ----
 def dynamics(x, u, p):
+    """f(x, u) of the lander; u has 4 or 7 entries (the latter with the torque)."""
     x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
     f = np.zeros(NX)
-    lib().orc_dynamics(xp, up, pp, _p(f))
+    lib(u.size).orc_dynamics(xp, up, pp, _p(f))
     return f
 
 
 def jacobians(x, u, p):
     x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
-    A = np.zeros((NX, NX)); B = np.zeros((NX, NU))
-    lib().orc_jacobians(xp, up, pp, _p(A), _p(B))
+    A = np.zeros((NX, NX)); B = np.zeros((NX, u.size))
+    lib(u.size).orc_jacobians(xp, up, pp, _p(A), _p(B))
     return A, B
 
 
 def constraints(x, u, p):
     x, xp = _d(x); u, up = _d(u); p, pp = _d(p)
-    g = np.zeros(8)
-    lib().orc_constraints(xp, up, pp, _p(g))
+    g = np.zeros(9)
+    lib(u.size).orc_constraints(xp, up, pp, _p(g))
     return g
 
 
@@ -179,10 +209,11 @@ def discretize_interval(xk, uk, uk1, p, dtau, nsub, A0=None, B0=None):
     xk, a = _d(xk); uk, b = _d(uk); uk1, c = _d(uk1)
     p = np.zeros(NP) if p is None else p
     p, pp = _d(p)
+    nu = uk.size
     A0c = None if A0 is None else np.ascontiguousarray(A0, dtype=np.float64)
     B0c = None if B0 is None else np.ascontiguousarray(B0, dtype=np.float64)
-    xe = np.zeros(NX); A = np.zeros((NX, NX)); Bm = np.zeros((NX, NU)); Bp = np.zeros((NX, NU))
-    lib().orc_discretize_interval(a, b, c, pp, _p(A0c), _p(B0c), float(dtau), int(nsub),
+    xe = np.zeros(NX); A = np.zeros((NX, NX)); Bm = np.zeros((NX, nu)); Bp = np.zeros((NX, nu))
+    lib(nu).orc_discretize_interval(a, b, c, pp, _p(A0c), _p(B0c), float(dtau), int(nsub),
                                   _p(xe), _p(A), _p(Bm), _p(Bp))
     return xe, A, Bm, Bp
 
@@ -190,16 +221,17 @@ def discretize_interval(xk, uk, uk1, p, dtau, nsub, A0=None, B0=None):
 def discretize(K, xbar, ubar, p, nsub):
     xbar, xp = _d(xbar); ubar, up = _d(ubar); p, pp = _d(p)
     M = K - 1
+    nu = ubar.shape[-1]
     xe = np.zeros((M, NX)); A = np.zeros((M, NX, NX))
-    Bm = np.zeros((M, NX, NU)); Bp = np.zeros((M, NX, NU))
-    lib().orc_discretize(K, xp, up, pp, int(nsub), _p(xe), _p(A), _p(Bm), _p(Bp))
+    Bm = np.zeros((M, NX, nu)); Bp = np.zeros((M, NX, nu))
+    lib(nu).orc_discretize(K, xp, up, pp, int(nsub), _p(xe), _p(A), _p(Bm), _p(Bp))
     return xe, A, Bm, Bp
 
 
-def init_guess(K, x0, xf, p):
+def init_guess(K, x0, xf, p, nu=NU):
     x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
-    xb = np.zeros((K, NX)); ub = np.zeros((K, NU))
-    lib().orc_init_guess(K, a, b, c, _p(xb), _p(ub))
+    xb = np.zeros((K, NX)); ub = np.zeros((K, nu))
+    lib(nu).orc_init_guess(K, a, b, c, _p(xb), _p(ub))
     return xb, ub
 
 
@@ -208,11 +240,12 @@ def build_qp(cfg, p, K, x0, xf, xbar, ubar, xend, A, Bm, Bp):
     st = make_settings(cfg)
     args = [_d(v) for v in (p, x0, xf, xbar, ubar, xend, A, Bm, Bp)]
     M = K - 1
-    out = dict(Am=np.zeros((M, NX, NX)), Bm=np.zeros((M, NX, NU)), Bp=np.zeros((M, NX, NU)),
-               w=np.zeros((M, NX)), eps=np.zeros(M), umin=np.zeros((K, NU)),
-               umax=np.zeros((K, NU)), zi=np.zeros(NX), zf=np.zeros(NXF))
+    nu = n_u(cfg)
+    out = dict(Am=np.zeros((M, NX, NX)), Bm=np.zeros((M, NX, nu)), Bp=np.zeros((M, NX, nu)),
+               w=np.zeros((M, NX)), eps=np.zeros(M), umin=np.zeros((K, nu)),
+               umax=np.zeros((K, nu)), zi=np.zeros(NX), zf=np.zeros(NXF))
     a = [x[1] for x in args]
-    lib().orc_build_qp(ctypes.byref(st), a[0], K, a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8],
+    lib(nu).orc_build_qp(ctypes.byref(st), a[0], K, a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8],
                        *[_p(out[k]) for k in ("Am", "Bm", "Bp", "w", "eps", "umin", "umax",
                                               "zi", "zf")])
     return out
@@ -223,13 +256,13 @@ def power(cfg, qp):
     K = qp["umin"].shape[0] if "umin" in qp else qp["Am"].shape[0] + 1
     Am, a = _d(qp["Am"]); Bm, b = _d(qp["Bm"]); Bp, c = _d(qp["Bp"])
     it = ctypes.c_int32(0)
-    sigma = lib().orc_power(ctypes.byref(st), K, a, b, c, ctypes.byref(it))
+    sigma = lib(n_u(cfg)).orc_power(ctypes.byref(st), K, a, b, c, ctypes.byref(it))
     return sigma, it.value
 
 
-def zero_warm_start(K):
+def zero_warm_start(K, nu=NU):
     M = K - 1
-    return dict(x=np.zeros((K, NX)), u=np.zeros((K, NU)), mup=np.zeros((M, NX)),
+    return dict(x=np.zeros((K, NX)), u=np.zeros((K, nu)), mup=np.zeros((M, NX)),
                 mum=np.zeros((M, NX)), phi=np.zeros((M, NX)), th=np.zeros(M))
 
 
@@ -239,13 +272,13 @@ def pipg(cfg, qp, sigma, jmax, check, ws=None, ref=None):
     ``ref`` = (xbar, ubar, params) is needed only when node projections are enabled."""
     st = make_settings(cfg)
     K = qp["umin"].shape[0]
-    ws = zero_warm_start(K) if ws is None else ws
+    ws = zero_warm_start(K, n_u(cfg)) if ws is None else ws
     out = {k: np.array(v, dtype=np.float64, copy=True) for k, v in ws.items()}
     q = {k: np.ascontiguousarray(qp[k], dtype=np.float64)
          for k in ("Am", "Bm", "Bp", "w", "eps", "umin", "umax", "zi", "zf")}
     refs = [None, None, None] if ref is None else [np.ascontiguousarray(r, dtype=np.float64)
                                                    for r in ref]
-    n = lib().orc_pipg(ctypes.byref(st), K, *[_p(q[k]) for k in ("Am", "Bm", "Bp", "w", "eps",
+    n = lib(n_u(cfg)).orc_pipg(ctypes.byref(st), K, *[_p(q[k]) for k in ("Am", "Bm", "Bp", "w", "eps",
                                                                  "umin", "umax", "zi", "zf")],
                        *[_p(r) for r in refs], float(sigma), int(jmax), int(check),
                        *[_p(out[k]) for k in ("x", "u", "mup", "mum", "phi", "th")])
@@ -261,13 +294,14 @@ def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
     x0, a = _d(x0); xf, b = _d(xf); params, c = _d(params)
     K = np.ascontiguousarray(K, dtype=np.int32)
     B = x0.shape[0]
+    nu = n_u(cfg)
     kmax = int(K.max()) if kmax is None else int(kmax)
     nthreads = os.cpu_count() if nthreads is None else int(nthreads)
-    out = dict(x=np.zeros((B, kmax, NX)), u=np.zeros((B, kmax, NU)), t_f=np.zeros(B),
+    out = dict(x=np.zeros((B, kmax, NX)), u=np.zeros((B, kmax, nu)), t_f=np.zeros(B),
                m_f=np.zeros(B), status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
                pipg_iters=np.zeros(B, np.int32), defect_inf=np.zeros(B), ctcs_viol=np.zeros(B),
                objective=np.zeros(B), step=np.zeros(B))
-    rc = lib().orc_solve_batch(
+    rc = lib(nu).orc_solve_batch(
         ctypes.byref(st), B, kmax, a, b, c, K.ctypes.data_as(_I), nthreads,
         _p(out["x"]), _p(out["u"]), _p(out["t_f"]), _p(out["m_f"]),
         out["status"].ctypes.data_as(_I), out["scp_iters"].ctypes.data_as(_I),
@@ -284,6 +318,8 @@ _lib32 = {}
 def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None, contract=False):
     """The same solve evaluated in single precision (see the module note); float64 results.
     ``contract``: the build with fused multiply-adds."""
+    if n_u(cfg) != NU:
+        raise ValueError("the single-precision oracle builds have n_u = 4 only")
     if contract not in _lib32:
         build()
         _lib32[contract] = ctypes.CDLL(_SO32F if contract else _SO32)
@@ -331,9 +367,9 @@ def select_best(status, objective, problems, starts):
 def solve_trace(cfg, x0, xf, p, K, trace_n=64):
     st = make_settings(cfg)
     x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
-    xb = np.zeros((K, NX)); ub = np.zeros((K, NU))
+    xb = np.zeros((K, NX)); ub = np.zeros((K, n_u(cfg)))
     sc = np.zeros(6); ints = np.zeros(3, np.int32); tr = np.zeros((trace_n, 4))
-    lib().orc_solve_trace(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(sc),
+    lib(n_u(cfg)).orc_solve_trace(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(sc),
                           ints.ctypes.data_as(_I), int(trace_n), _p(tr))
     n = int(ints[1])
     return dict(x=xb, u=ub, t_f=sc[0], m_f=sc[1], defect_inf=sc[2], ctcs_viol=sc[3],
@@ -345,9 +381,10 @@ def lastiter_state(cfg, x0, xf, p, K):
     """Reference, warm start and sigma of the last SCP iteration of a fixed-work solve."""
     st = make_settings(cfg)
     x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p)
-    n = lib().orc_iter_len(int(K))
-    xb = np.zeros((K, NX)); ub = np.zeros((K, NU)); ws = np.zeros(n); sg = ctypes.c_double(0)
-    rc = lib().orc_lastiter_state(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(ws),
+    nu = n_u(cfg)
+    n = lib(nu).orc_iter_len(int(K))
+    xb = np.zeros((K, NX)); ub = np.zeros((K, nu)); ws = np.zeros(n); sg = ctypes.c_double(0)
+    rc = lib(nu).orc_lastiter_state(ctypes.byref(st), int(K), a, b, c, _p(xb), _p(ub), _p(ws),
                                   ctypes.byref(sg))
     if rc != 0:
         raise RuntimeError("oracle: no last iteration recorded")
@@ -360,7 +397,7 @@ def truncated_map(cfg, x0, xf, p, K, theta, last, n_steps):
     x0, a = _d(x0); xf, b = _d(xf); p, c = _d(p); th, t = _d(theta)
     out = np.zeros(2)
     xb, xbp = _d(last["xbar"]); ub, ubp = _d(last["ubar"]); ws, wsp = _d(last["ws"])
-    lib().orc_truncated_map(ctypes.byref(st), int(K), a, b, c, t, xbp, ubp, wsp,
+    lib(n_u(cfg)).orc_truncated_map(ctypes.byref(st), int(K), a, b, c, t, xbp, ubp, wsp,
                             float(last["sigma"]), int(n_steps), _p(out))
     return out
 
@@ -373,10 +410,11 @@ def theta_of(x0, p):
 def stopping(new, old, eabs, erel):
     """The customized stopping test on two iterate dicts (keys x, u, mup, mum, phi, th)."""
     K = new["x"].shape[0]
+    nu = new["u"].shape[-1]
     keys = ("x", "u", "mup", "mum", "phi", "th")
     a = [np.ascontiguousarray(new[k], dtype=np.float64) for k in keys]
     b = [np.ascontiguousarray(old[k], dtype=np.float64) for k in keys]
-    return bool(lib().orc_stopping(K, *[_p(v) for v in a], *[_p(v) for v in b], float(eabs),
+    return bool(lib(nu).orc_stopping(K, *[_p(v) for v in a], *[_p(v) for v in b], float(eabs),
                                    float(erel)))
 
 
@@ -384,5 +422,5 @@ def project_node(p, x, u):
     """Node-wise convex-set projection of a state (15) and control (4), original units."""
     p, pp = _d(p)
     x = np.array(x, dtype=np.float64, copy=True); u = np.array(u, dtype=np.float64, copy=True)
-    lib().orc_project_node(pp, _p(x), _p(u))
+    lib(u.size).orc_project_node(pp, _p(x), _p(u))
     return x, u

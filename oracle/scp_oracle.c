@@ -11,11 +11,12 @@
  *
  * Conventions (the paper's notation, 0-based indices in code):
  *   state  x = (m, r[3], v[3], q[4], w[3], y)   n_x = 15   (q Hamilton, scalar first)
- *   control u = (T[3], s)                       n_u = 4    (s = dilation factor)
+ *   control u = (T[3], s)                       n_u = 4    (s = dilation factor), or with
+ *           the reaction-control torque (built with -DNU=7) u = (T[3], gamma[3], s)
  *   nodes k = 0..N-1 (paper's 1..N), intervals k = 0..N-2.
- *   params p[23] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
+ *   params p[24] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
  *                  delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs, s_init,
- *                  v_max (+inf: no speed bound)
+ *                  v_max (+inf: no speed bound), gamma_max (torque bound; n_u = 7 only)
  *
  * Every floating-point operation is written out in double precision, compiled without
  * fast-math and without FMA contraction.
@@ -27,9 +28,15 @@
 #include <string.h>
 
 #define NX 15
-#define NU 4
-#define NP 23
-#define NG 8 /* rows of the path-constraint function g */
+#ifndef NU
+#define NU 4 /* thrust and dilation; 7 adds the reaction-control torque */
+#endif
+#if NU != 4 && NU != 7
+#error "NU must be 4 or 7"
+#endif
+#define IS (NU - 1) /* index of the dilation s in u */
+#define NP 24
+#define NG 9 /* rows of the path-constraint function g (the torque row is -1 when n_u = 4) */
 #define NXF 13
 #define IY 14 /* index of the CTCS integrator state y */
 
@@ -51,7 +58,7 @@ static int final_fixed(int i) { return i >= 1 && i <= 13 && i != 7 && i != 8 && 
 enum {
     P_MWET = 0, P_MDRY = 1, P_ALPHA = 2, P_G = 3, P_J = 6, P_RT = 9, P_TMIN = 12, P_TMAX = 13,
     P_DELTA = 14, P_GAMMA = 15, P_THETA = 16, P_OMEGA = 17, P_SMIN = 18, P_SMAX = 19,
-    P_EPS = 20, P_SINIT = 21, P_VMAX = 22
+    P_EPS = 20, P_SINIT = 21, P_VMAX = 22, P_GMAX = 23
 };
 
 /* Solver settings; the same fields (in the same order) as the Python wrapper's struct. */
@@ -113,9 +120,10 @@ static void cross3(const double *a, const double *b, double *c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-/* Path constraints g (8 rows: mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed;
- * the speed row ||v||^2 - v_max^2 of section "6-DoF Powered Descent Guidance" is the constant
- * -1 when v_max is not finite, i.e. there is no speed bound). */
+/* Path constraints g (9 rows: mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed,
+ * torque; the speed row ||v||^2 - v_max^2 of section "6-DoF Powered Descent Guidance" is the
+ * constant -1 when v_max is not finite, i.e. there is no speed bound, and the torque row
+ * ||gamma||^2 - gamma_max^2 likewise without a finite bound or without the torque input). */
 static void constraints(const double *x, const double *u, const double *p, double *g)
 {
     const double *r = x + 1, *v = x + 4, *q = x + 7, *w = x + 11;
@@ -130,9 +138,16 @@ static void constraints(const double *x, const double *u, const double *p, doubl
     g[6] = p[P_TMIN] - Tn;
     g[7] = isfinite(p[P_VMAX]) ? v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - p[P_VMAX] * p[P_VMAX]
                                : -1.0;
+#if NU == 7
+    g[8] = isfinite(p[P_GMAX]) ? u[3] * u[3] + u[4] * u[4] + u[5] * u[5] - p[P_GMAX] * p[P_GMAX]
+                               : -1.0;
+#else
+    g[8] = -1.0;
+#endif
 }
 
-/* Gradients of g w.r.t. x (8 x 15) and w.r.t. T (8 x 3).  d||v||/dv := 0 for ||v|| <= NORM_EPS. */
+/* Gradients of g w.r.t. x (9 x 15) and w.r.t. T (9 x 3).  d||v||/dv := 0 for ||v|| <= NORM_EPS.
+ * The torque row's gradient w.r.t. gamma (2 gamma) is formed where it is used. */
 static void constraint_grads(const double *x, const double *u, const double *p, double Gx[NG][NX],
                              double Gt[NG][3])
 {
@@ -165,12 +180,12 @@ static void constraint_grads(const double *x, const double *u, const double *p, 
         for (i = 0; i < 3; i++) Gx[7][4 + i] = 2.0 * v[i];
 }
 
-/* Augmented, time-dilated dynamics f(x,u) = s * (F(xi,T), sum_i [g_i]_+^2). */
+/* Augmented, time-dilated dynamics f(x,u) = s * (F(xi,zeta), sum_i [g_i]_+^2). */
 void orc_dynamics(const double *x, const double *u, const double *p, double *f)
 {
     const double *v = x + 4, *q = x + 7, *w = x + 11;
     const double *J = p + P_J, *rT = p + P_RT, *gI = p + P_G;
-    double s = u[3], m = x[0];
+    double s = u[IS], m = x[0];
     double C[3][3], Om[4][4], g[NG];
     double Jw[3], wxJw[3], rxT[3];
     double F[NX];
@@ -193,7 +208,12 @@ void orc_dynamics(const double *x, const double *u, const double *p, double *f)
     for (i = 0; i < 3; i++) Jw[i] = J[i] * w[i];
     cross3(w, Jw, wxJw);
     cross3(rT, u, rxT);
+#if NU == 7
+    /* the reaction-control torque gamma (body frame) joins the thrust torque */
+    for (i = 0; i < 3; i++) F[11 + i] = (rxT[i] - wxJw[i] + u[3 + i]) / J[i];
+#else
     for (i = 0; i < 3; i++) F[11 + i] = (rxT[i] - wxJw[i]) / J[i];
+#endif
     constraints(x, u, p, g);
     F[IY] = 0.0;
     for (i = 0; i < NG; i++) {
@@ -203,12 +223,12 @@ void orc_dynamics(const double *x, const double *u, const double *p, double *f)
     for (i = 0; i < NX; i++) f[i] = s * F[i];
 }
 
-/* Analytic Jacobians A = df/dx (15x15, row-major) and B = df/du (15x4, row-major). */
+/* Analytic Jacobians A = df/dx (15x15, row-major) and B = df/du (15 x NU, row-major). */
 void orc_jacobians(const double *x, const double *u, const double *p, double *A, double *B)
 {
     const double *q = x + 7, *w = x + 11;
     const double *J = p + P_J, *rT = p + P_RT;
-    double s = u[3], m = x[0];
+    double s = u[IS], m = x[0];
     double C[3][3], Om[4][4], g[NG], Gx[NG][NX], Gt[NG][3];
     double CT[3], dCT_dq[3][4], Xi[4][3];
     double F[NX], f[NX];
@@ -292,16 +312,26 @@ void orc_jacobians(const double *x, const double *u, const double *p, double *A,
         double gp = g[i] > 0.0 ? g[i] : 0.0;
         for (j = 0; j < 3; j++) B[IY * NU + j] += 2.0 * gp * Gt[i][j];
     }
+#if NU == 7
+    /* the torque enters w_dot through J^-1, and the CTCS integrand through its bound row */
+    for (i = 0; i < 3; i++) B[(11 + i) * NU + 3 + i] = 1.0 / J[i];
+    {
+        double gp = g[8] > 0.0 ? g[8] : 0.0;
+        for (j = 0; j < 3; j++) B[IY * NU + 3 + j] += 2.0 * gp * (2.0 * u[3 + j]);
+    }
+#endif
     for (i = 0; i < NX; i++)
-        for (j = 0; j < 3; j++) B[i * NU + j] *= s;
+        for (j = 0; j < IS; j++) B[i * NU + j] *= s;
     /* df/ds = F */
     orc_dynamics(x, u, p, f);
     for (i = 0; i < NX; i++) F[i] = (s != 0.0) ? f[i] / s : 0.0;
     if (s == 0.0) { /* evaluate F directly when s = 0 */
-        double u1[NU] = {u[0], u[1], u[2], 1.0};
+        double u1[NU];
+        for (j = 0; j < NU; j++) u1[j] = u[j];
+        u1[IS] = 1.0;
         orc_dynamics(x, u1, p, F);
     }
-    for (i = 0; i < NX; i++) B[i * NU + 3] = F[i];
+    for (i = 0; i < NX; i++) B[i * NU + IS] = F[i];
 }
 
 void orc_constraints(const double *x, const double *u, const double *p, double *g)
@@ -317,7 +347,7 @@ typedef struct {
     int linear;        /* 0: 6-DoF lander; 1: linear test model */
     const double *p;   /* lander parameters                      */
     const double *A0;  /* linear model, 15x15 row-major          */
-    const double *B0;  /* linear model, 15x4 row-major           */
+    const double *B0;  /* linear model, 15xNU row-major          */
 } model_t;
 
 static void model_f(const model_t *md, const double *x, const double *u, double *f)
@@ -351,7 +381,7 @@ static void model_jac(const model_t *md, const double *x, const double *u, doubl
  *   Phi_x' = A Phi_x,  Phi_u-' = A Phi_u- + B lambda-,  Phi_u+' = A Phi_u+ + B lambda+,
  * with Phi_x(tau_k) = I, Phi_u+-(tau_k) = 0, a first-order-hold control, integrated jointly
  * with n_sub classical RK4 steps.  Output: x^k(tau_k+1), A_k, B_k-, B_k+.
- * The 360-dimensional augmented state is X = (x[15], Phi_x[15x15], Phi_u-[15x4], Phi_u+[15x4]).
+ * The augmented state is X = (x[15], Phi_x[15x15], Phi_u-[15xNU], Phi_u+[15xNU]) (360 values for n_u = 4, 450 for 7).
  * ------------------------------------------------------------------------------------------ */
 #define NAUG (NX + NX * NX + 2 * NX * NU)
 
@@ -451,10 +481,9 @@ void orc_init_guess(int K, const double *x0, const double *xf, const double *p, 
         qn = sqrt(qn);
         for (i = 7; i < 11; i++) x[i] /= qn;
         x[IY] = 0.0;
+        for (i = 0; i < NU; i++) u[i] = 0.0;  /* the torque guess is zero */
         u[0] = x0[0] * gn;
-        u[1] = 0.0;
-        u[2] = 0.0;
-        u[3] = p[P_SINIT];
+        u[IS] = p[P_SINIT];
     }
 }
 
@@ -464,10 +493,10 @@ void orc_init_guess(int K, const double *x0, const double *xf, const double *p, 
 typedef struct {
     int K;                 /* number of nodes N                                   */
     double *Am;            /* [K-1][15][15]  A_hat^-_k = Px^-1 A_k Px               */
-    double *Bm, *Bp;       /* [K-1][15][4]   B_hat^-+_k = Px^-1 B^-+_k Pu           */
+    double *Bm, *Bp;       /* [K-1][15][NU]  B_hat^-+_k = Px^-1 B^-+_k Pu           */
     double *w;             /* [K-1][15]      w_hat_k = Px^-1 (x^k(tau_k+1) - x_k+1) */
     double *eps;           /* [K-1]          eps_hat_k                              */
-    double *umin, *umax;   /* [K][4]         scaled control bounds (+-inf for T)    */
+    double *umin, *umax;   /* [K][NU]        scaled control bounds (+-inf but for s) */
     double zi[NX];         /* scaled initial condition (all 15 components)         */
     double zf[NXF];        /* scaled final condition on r, v, q, w                 */
     const double *xbar;    /* [K][15] reference state (node-wise sets only)         */
@@ -550,12 +579,12 @@ static void build_qp(const orc_settings *st, const double *p, int K, const doubl
         qp->eps[k] = (p[P_EPS] - (xbar[(k + 1) * NX + IY] - xbar[k * NX + IY])) / px[IY];
     }
     for (k = 0; k < K; k++) {
-        for (j = 0; j < 3; j++) {
+        for (j = 0; j < IS; j++) { /* only the dilation is boxed */
             qp->umin[k * NU + j] = -INFINITY;
             qp->umax[k * NU + j] = INFINITY;
         }
-        qp->umin[k * NU + 3] = (p[P_SMIN] - ubar[k * NU + 3]) / pu[3];
-        qp->umax[k * NU + 3] = (p[P_SMAX] - ubar[k * NU + 3]) / pu[3];
+        qp->umin[k * NU + IS] = (p[P_SMIN] - ubar[k * NU + IS]) / pu[IS];
+        qp->umax[k * NU + IS] = (p[P_SMAX] - ubar[k * NU + IS]) / pu[IS];
     }
     for (i = 0; i < NX; i++) {
         double zi = (i < IY) ? x0[i] : 0.0; /* (z_i, 0): y(0) = 0 */
@@ -1097,7 +1126,7 @@ static void scp_solve_one(const orc_settings *st, int K, const double *x0, const
         }
     }
     res->tf = 0.0;
-    for (k = 0; k < M; k++) res->tf += dtau * 0.5 * (ubar[k * NU + 3] + ubar[(k + 1) * NU + 3]);
+    for (k = 0; k < M; k++) res->tf += dtau * 0.5 * (ubar[k * NU + IS] + ubar[(k + 1) * NU + IS]);
     res->mf = xbar[(K - 1) * NX + 0];
     res->defect = d;
     res->ctcs = c;
@@ -1250,8 +1279,8 @@ void orc_truncated_map(const orc_settings *st, int K, const double *x0, const do
     out[0] = xbar_last[(K - 1) * NX + 0] + st->px[0] * ws.x[(K - 1) * NX + 0];
     out[1] = 0.0;
     for (k = 0; k < M; k++) {
-        double s0 = ubar_last[k * NU + 3] + st->pu[3] * ws.u[k * NU + 3];
-        double s1 = ubar_last[(k + 1) * NU + 3] + st->pu[3] * ws.u[(k + 1) * NU + 3];
+        double s0 = ubar_last[k * NU + IS] + st->pu[IS] * ws.u[k * NU + IS];
+        double s1 = ubar_last[(k + 1) * NU + IS] + st->pu[IS] * ws.u[(k + 1) * NU + IS];
         out[1] += dtau * 0.5 * (s0 + s1);
     }
     free(xend); free(A); free(Bm); free(Bp);

@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-NX, NU, NP, NXF = 15, 4, 23, 13
+NX, NU, NP, NXF = 15, 4, 24, 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscp_batch.so")
 
@@ -47,7 +47,7 @@ class Settings(ctypes.Structure):
         ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("grad_pipg_steps", ctypes.c_int32), ("grad_ckpt_every", ctypes.c_int32),
         ("occupancy", ctypes.c_int32), ("grad_rk4_tangent", ctypes.c_int32),
-        ("scalar_dilation", ctypes.c_int32),
+        ("scalar_dilation", ctypes.c_int32), ("power_fp32", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
         ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
@@ -146,6 +146,7 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
     # the discretization (the reverse sweep stays available and is checked against it)
     s.grad_rk4_tangent = int(cfg.get("grad_rk4_tangent", 1))
     s.scalar_dilation = int(cfg.get("scalar_dilation", 0))
+    s.power_fp32 = int(cfg.get("power_fp32", 0))
     s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
     s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",

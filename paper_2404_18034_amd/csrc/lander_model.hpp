@@ -11,7 +11,7 @@ namespace scp {
 
 constexpr int NX = 15;
 constexpr int NU = 4;
-constexpr int NP = 23;
+constexpr int NP = 24;
 constexpr int NXF = 13;
 constexpr int IY = 14;
 constexpr double NORM_EPS = 1e-4;  // below this a norm's derivative is taken as 0

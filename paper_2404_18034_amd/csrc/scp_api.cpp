@@ -48,6 +48,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
     }
     if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
     if (s->scalar_dilation != 0 && s->scalar_dilation != 1) { why = "scalar_dilation must be 0 or 1"; return false; }
+    if (s->power_fp32 != 0 && s->power_fp32 != 1) { why = "power_fp32 must be 0 or 1"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -260,9 +261,8 @@ static bool lastiter_ok(scp_batch h, const scp_lastiter *rec)
     return true;
 }
 
-static void fill_config(scp_batch h, int batch, scp::Config &cfg)
+static void fill_config_from(const scp_settings &s, int batch, scp::Config &cfg)
 {
-    const scp_settings &s = h->st;
     cfg.dtype = s.dtype == SCP_F64 ? 1 : 0;
     cfg.B = batch;
     cfg.kmax = s.k_max;
@@ -281,6 +281,7 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     cfg.occupancy = s.occupancy;
     cfg.grad_rk4_tangent = s.grad_rk4_tangent;
     cfg.scalar_dilation = s.scalar_dilation;
+    cfg.power_fp32 = s.power_fp32;
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -297,25 +298,32 @@ static void fill_config(scp_batch h, int batch, scp::Config &cfg)
     memcpy(cfg.pu, s.pu, sizeof(cfg.pu));
 }
 
-static scp::Workspace workspace_of(scp_batch h)
+static void fill_config(scp_batch h, int batch, scp::Config &cfg)
+{
+    fill_config_from(h->st, batch, cfg);
+}
+
+static scp::Workspace workspace_at(char *ws, const Layout &L)
 {
     scp::Workspace W;
-    W.blocks = h->ws + h->L.blocks;
-    W.what = h->ws + h->L.what;
-    W.dy = reinterpret_cast<double *>(h->ws + h->L.dy);
-    W.mup = h->ws + h->L.mup;
-    W.mum = h->ws + h->L.mum;
-    W.phi = h->ws + h->L.phi;
-    W.th = h->ws + h->L.th;
-    W.step = reinterpret_cast<double *>(h->ws + h->L.step);
-    W.sigma = reinterpret_cast<double *>(h->ws + h->L.sigma);
-    W.stepsz = h->ws + h->L.stepsz;
-    W.pipg_total = reinterpret_cast<int32_t *>(h->ws + h->L.pipg_total);
-    W.queue = reinterpret_cast<int32_t *>(h->ws + h->L.queue);
-    W.bucket = reinterpret_cast<int32_t *>(h->ws + h->L.bucket);
-    W.order = reinterpret_cast<int32_t *>(h->ws + h->L.order);
+    W.blocks = ws + L.blocks;
+    W.what = ws + L.what;
+    W.dy = reinterpret_cast<double *>(ws + L.dy);
+    W.mup = ws + L.mup;
+    W.mum = ws + L.mum;
+    W.phi = ws + L.phi;
+    W.th = ws + L.th;
+    W.step = reinterpret_cast<double *>(ws + L.step);
+    W.sigma = reinterpret_cast<double *>(ws + L.sigma);
+    W.stepsz = ws + L.stepsz;
+    W.pipg_total = reinterpret_cast<int32_t *>(ws + L.pipg_total);
+    W.queue = reinterpret_cast<int32_t *>(ws + L.queue);
+    W.bucket = reinterpret_cast<int32_t *>(ws + L.bucket);
+    W.order = reinterpret_cast<int32_t *>(ws + L.order);
     return W;
 }
+
+static scp::Workspace workspace_of(scp_batch h) { return workspace_at(h->ws, h->L); }
 
 static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution *sol,
                              const scp_lastiter *rec)
@@ -554,7 +562,7 @@ static std::string tune_key(scp_batch h, int batch)
     std::ostringstream k;
     k << arch << ":kmax=" << h->st.k_max << ":dtype=" << (h->st.dtype == SCP_F64 ? "f64" : "f32")
       << ":early_exit=" << h->st.early_exit << ":proj=" << h->st.node_projections
-      << ":sd=" << h->st.scalar_dilation << ":batch=" << batch;
+      << ":sd=" << h->st.scalar_dilation << ":pw32=" << h->st.power_fp32 << ":batch=" << batch;
     return k.str();
 }
 

@@ -525,10 +525,20 @@ struct NodeSets {
 };
 
 // State sets of node k (bits 1, 2, 4, 8): pre-projection x^ in XP (scaled), reference xb
-// (original units).  Writes the projected non-fixed group members into xh.
+// (original units).  Writes the projected non-fixed group members into xh, which holds the
+// boundary values of the fixed members already.  At the last node (`last`) the roll rate is
+// projected onto the rate ball's slice through the fixed transverse rates.
+template <typename R>
+__device__ __forceinline__ R roll_rate_radius(const NodeSets<R> &S, const R *xh, const R *xb,
+                                              const R *px)
+{
+    const R c2 = xb[12] + px[12] * xh[12], c3 = xb[13] + px[13] * xh[13];
+    const R r2 = S.w_max * S.w_max - c2 * c2 - c3 * c3;
+    return r2 > R(0) ? sqrt(r2) : R(0);
+}
 template <typename R>
 __device__ __forceinline__ void xproj_fwd(const NodeSets<R> &S, const R *xp, const R *xb,
-                                          const R *px, const bool *fixed, R *xh)
+                                          const R *px, const bool *fixed, bool last, R *xh)
 {
     R xo[NX];
     for (int q = 0; q < NX; ++q) xo[q] = xb[q] + px[q] * xp[q];
@@ -548,7 +558,11 @@ __device__ __forceinline__ void xproj_fwd(const NodeSets<R> &S, const R *xp, con
         for (int q = 0; q < 2; ++q)
             if (!fixed[9 + q]) xh[9 + q] = (z[q] - xb[9 + q]) / px[9 + q];
     }
-    if (S.mask & 8) {
+    if ((S.mask & 8) && last) {
+        const R r = roll_rate_radius<R>(S, xh, xb, px);
+        const R w1 = fmin(fmax(xo[11], -r), r);
+        xh[11] = (w1 - xb[11]) / px[11];
+    } else if (S.mask & 8) {
         R z[3] = {xo[11], xo[12], xo[13]};
         ball_fwd<R, 3>(z, S.w_max);
         for (int q = 0; q < 3; ++q)
@@ -560,7 +574,7 @@ __device__ __forceinline__ void xproj_fwd(const NodeSets<R> &S, const R *xp, con
 // members already carry a zero adjoint.
 template <typename R>
 __device__ __forceinline__ void xproj_vjp(const NodeSets<R> &S, const R *xp, const R *xb,
-                                          const R *px, R *g)
+                                          const R *px, const R *xh, bool last, R *g)
 {
     R xo[NX];
     for (int q = 0; q < NX; ++q) xo[q] = xb[q] + px[q] * xp[q];
@@ -579,7 +593,10 @@ __device__ __forceinline__ void xproj_vjp(const NodeSets<R> &S, const R *xp, con
         g[9] = zb[0] * px[9];
         g[10] = zb[1] * px[10];
     }
-    if (S.mask & 8) {
+    if ((S.mask & 8) && last) {
+        const R r = roll_rate_radius<R>(S, xh, xb, px);
+        if (!(xo[11] >= -r && xo[11] <= r)) g[11] = R(0);
+    } else if (S.mask & 8) {
         R zb[3] = {g[11] / px[11], g[12] / px[12], g[13] / px[13]};
         const R z[3] = {xo[11], xo[12], xo[13]};
         (void)ball_vjp<R, 3>(z, S.w_max, zb);
@@ -773,7 +790,8 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
         }
         __syncthreads();
         if (node && i == 0 && (sets.mask & 15))
-            xproj_fwd<R>(sets, XP + k * 16, XB + k * 16, pxr, fixed_node, XH + k * 16);
+            xproj_fwd<R>(sets, XP + k * 16, XB + k * 16, pxr, fixed_node, k == K - 1 && k > 0,
+                         XH + k * 16);
         if (node && i == 1) uproj_fwd<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UH + k * NU);
         __syncthreads();
     };
@@ -944,7 +962,8 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
             __syncthreads();
             // projections
             if (node && i == 0 && (sets.mask & 15))
-                xproj_vjp<R>(sets, XP + k * 16, XB + k * 16, pxr, XHB + k * 16);
+                xproj_vjp<R>(sets, XP + k * 16, XB + k * 16, pxr, XH + k * 16,
+                             k == K - 1 && k > 0, XHB + k * 16);
             if (node && i == 1)
                 accT += uproj_vjp<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UHB + k * NU);
             __syncthreads();

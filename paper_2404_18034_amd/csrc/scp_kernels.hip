@@ -594,10 +594,101 @@ __device__ __forceinline__ double from_max_bits(unsigned long long b)
     return __longlong_as_double((long long)b);
 }
 
+// ------------------------------------------------------------------------------------------
+// Power-iteration products in FP64 over FP32 blocks (the FP32 path's default): each term
+// widens its block entry and multiplies it by the FP64 iterate of lane L of the row, read
+// through a DPP row broadcast.
+// ------------------------------------------------------------------------------------------
+// marks the values of c as redefined at this point (no instruction is emitted), so that a
+// conversion of them is not hoisted out of the enclosing loop: widening the blocks once
+// would take twice their registers
+template <typename T, int N>
+__device__ __forceinline__ void keep_narrow(T (&c)[N])
+{
+    for (int n = 0; n < N; ++n) asm volatile("" : "+v"(c[n]));
+}
+// sum_{j<N} c[j] * (lane J0 + S*j of this row's v), in the order j = 0, 1, ...; generic form
+template <typename C, typename P, int J0, int S, int... J>
+__device__ __forceinline__ P pw_dot_impl(const C *c, P v, P acc, std::integer_sequence<int, J...>)
+{
+    ((acc = acc + P(c[J]) * rowb<J0 + S * J>(v)), ...);
+    return acc;
+}
+template <typename C, typename P, int J0, int S, int N>
+__device__ __forceinline__ P pw_dot(const C *c, P v, P acc)
+{
+    if constexpr (sizeof(C) == sizeof(P)) {
+        if constexpr (J0 == 0 && S == 1 && N == NX) return rowdot15<P>(c, v, acc);
+        else if constexpr (J0 == 0 && S == 4 && N == NU) return rowdot4q<P>(c, v, acc);
+        else if constexpr (S == 1) return rowdot_part<P, J0, N>(c, v, acc);
+    }
+    return pw_dot_impl<C, P, J0, S>(c, v, acc, std::make_integer_sequence<int, N>{});
+}
+// FP32 coefficients, FP64 iterate: one v_cvt_f64_f32 and one v_fmac_f64 with a DPP
+// row_newbcast source per term (the leading s_nop covers the DPP read of v)
+#define SCP_PW_TERM(T, C, L) \
+    "v_cvt_f64_f32 %[" #T "], %[" #C "]\n\t" \
+    "v_fmac_f64_dpp %[acc], %[v], %[" #T "] row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t"
+template <>
+__device__ __forceinline__ double pw_dot<float, double, 0, 1, NX>(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile("s_nop 4\n\t"
+                 SCP_PW_TERM(t0, c0, 0) SCP_PW_TERM(t1, c1, 1) SCP_PW_TERM(t0, c2, 2)
+                 SCP_PW_TERM(t1, c3, 3) SCP_PW_TERM(t0, c4, 4) SCP_PW_TERM(t1, c5, 5)
+                 SCP_PW_TERM(t0, c6, 6) SCP_PW_TERM(t1, c7, 7) SCP_PW_TERM(t0, c8, 8)
+                 SCP_PW_TERM(t1, c9, 9) SCP_PW_TERM(t0, c10, 10) SCP_PW_TERM(t1, c11, 11)
+                 SCP_PW_TERM(t0, c12, 12) SCP_PW_TERM(t1, c13, 13) SCP_PW_TERM(t0, c14, 14)
+                 : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+                 : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]),
+                   [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]),
+                   [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]), [c11] "v"(c[11]),
+                   [c12] "v"(c[12]), [c13] "v"(c[13]), [c14] "v"(c[14]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double pw_dot<float, double, 0, 1, 8>(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile("s_nop 4\n\t"
+                 SCP_PW_TERM(t0, c0, 0) SCP_PW_TERM(t1, c1, 1) SCP_PW_TERM(t0, c2, 2)
+                 SCP_PW_TERM(t1, c3, 3) SCP_PW_TERM(t0, c4, 4) SCP_PW_TERM(t1, c5, 5)
+                 SCP_PW_TERM(t0, c6, 6) SCP_PW_TERM(t1, c7, 7)
+                 : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+                 : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]),
+                   [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double pw_dot<float, double, 8, 1, 7>(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile("s_nop 4\n\t"
+                 SCP_PW_TERM(t0, c0, 8) SCP_PW_TERM(t1, c1, 9) SCP_PW_TERM(t0, c2, 10)
+                 SCP_PW_TERM(t1, c3, 11) SCP_PW_TERM(t0, c4, 12) SCP_PW_TERM(t1, c5, 13)
+                 SCP_PW_TERM(t0, c6, 14)
+                 : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+                 : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]),
+                   [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double pw_dot<float, double, 0, 4, NU>(const float *c, double v, double acc)
+{
+    double t0, t1;
+    asm volatile("s_nop 4\n\t"
+                 SCP_PW_TERM(t0, c0, 0) SCP_PW_TERM(t1, c1, 4) SCP_PW_TERM(t0, c2, 8)
+                 SCP_PW_TERM(t1, c3, 12)
+                 : [acc] "+v"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1)
+                 : [v] "v"(v), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]));
+    return acc;
+}
+#undef SCP_PW_TERM
+
 // LDS of the preparation kernel for a workgroup of at most MAXT lanes: per-lane slots, in the
-// working precision, of the power iterate (x part Z and u part U, rows 0 .. ROWS, the row
-// after the last workgroup row zero) and of phi and theta (rows -1 .. ROWS-1, row -1 zero),
-// then the FP64 reduction scratch.
+// power iteration's precision R, of the power iterate (x part Z and u part U, rows 0 .. ROWS,
+// the row after the last workgroup row zero) and of phi and theta (rows -1 .. ROWS-1, row -1
+// zero), then the FP64 reduction scratch.
 template <typename R, int MAXT>
 struct PrepLds {
     static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
@@ -631,7 +722,9 @@ __device__ __forceinline__ double wave_sum(R v)
 // is a kernel of its own so that its registers (the FP64 reductions of the test, the
 // power-iteration blocks) do not count against the register budget of the PIPG iteration.
 // ------------------------------------------------------------------------------------------
-template <typename R, int MAXT>
+// P: precision of the power iteration (iterate and block products); FP64 unless the FP32
+// variant is selected on the FP32 path.
+template <typename R, typename P, int MAXT>
 __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsigned char *smem_raw)
 {
     if (b >= a.B) return;
@@ -640,8 +733,8 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     const int t = threadIdx.x;
     const int k = t >> 4, i = t & 15;
     const bool wact = ((t >> 6) << 2) < K;
-    using Lds = PrepLds<R, MAXT>;
-    R *sl = reinterpret_cast<R *>(smem_raw) + t;                            // exchange slots
+    using Lds = PrepLds<P, MAXT>;
+    P *sl = reinterpret_cast<P *>(smem_raw) + t;                            // exchange slots
     double *red = reinterpret_cast<double *>(smem_raw + Lds::RED_BYTES);  // [16 waves * 8]
 
     const bool node = k < K;               // row holds a node
@@ -718,13 +811,14 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     // phi = H z / sigma (dynamics rows; theta for the CTCS rows) and z' = H^T phi, where
     // mu+' = phi and mu-' = -phi; the block products use row broadcasts of the iterate, the
     // neighbouring rows pass through this lane's LDS slots.  Two barriers per step.  The
-    // iterate and the products are in the working precision (FP32: 1/sigma is rounded once
-    // per step and multiplied); the squared norm is summed over each row in the working
-    // precision and over the rows in FP64; sigma and the stopping test are FP64.
+    // iterate and the products are in P (FP64 by default: the blocks are widened term by
+    // term); the squared norm is summed over each row in P and over the rows in FP64; sigma
+    // and the stopping test are FP64.  In the FP32 variant 1/sigma is rounded once per step
+    // and multiplied.
     const int KR = (kmax + 3) / 4 * 4;
     const bool thlane = dual && i == IY;
-    R zx = isx ? R(1) : R(0), zu = node ? R(1) : R(0);
-    R dmu = R(0);  // mu+ - mu- of this dynamics row
+    P zx = isx ? P(1) : P(0), zu = node ? P(1) : P(0);
+    P dmu = P(0);  // mu+ - mu- of this dynamics row
     double sigma;
     {
         double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NU) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
@@ -734,66 +828,72 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     sl[Lds::Z] = zx;
     sl[Lds::U] = zu;
     if (t < 16) {
-        sl[Lds::Z + KR * 16] = R(0);  // row after the last workgroup row
-        sl[Lds::U + KR * 16] = R(0);
-        sl[Lds::P] = R(0);            // row -1
-        sl[Lds::T] = R(0);
+        sl[Lds::Z + KR * 16] = P(0);  // row after the last workgroup row
+        sl[Lds::U + KR * 16] = P(0);
+        sl[Lds::P] = P(0);            // row -1
+        sl[Lds::T] = P(0);
     }
     __syncthreads();
     double sstar = sigma;
     const int nw = (blockDim.x + 63) >> 6;
     for (int it = 1; it <= a.power_iters_max; ++it) {
-        R ph = R(0), thv = R(0);
+        if constexpr (sizeof(R) < sizeof(P)) {
+            keep_narrow(rowA);
+            keep_narrow(rowBm);
+            keep_narrow(rowBp);
+            keep_narrow(rowBq);
+        }
+        P ph = P(0), thv = P(0);
         if (wact) {
             // A^-_k z_k - z_{k+1} + B^-_k u_k + B^+_k u_{k+1} + (mu+ - mu-), divided by sigma
-            const R zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
-            R r = rowdot15<R>(rowA, zx, R(0));
+            const P zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
+            P r = pw_dot<R, P, 0, 1, NX>(rowA, zx, P(0));
             r -= zxn;
-            r = rowdot4q<R>(rowBm, zu, r);
-            r = rowdot4q<R>(rowBp, zun, r);
+            r = pw_dot<R, P, 0, 4, NU>(rowBm, zu, r);
+            r = pw_dot<R, P, 0, 4, NU>(rowBp, zun, r);
             r += dmu;
-            if constexpr (sizeof(R) == 8) {
+            if constexpr (sizeof(P) == 8) {
                 ph = dual ? r / sigma : 0.0;
                 thv = thlane ? (zxn - zx) / sigma : 0.0;
             } else {
-                const R isg = R(1.0 / sigma);
-                ph = dual ? r * isg : R(0);
-                thv = thlane ? (zxn - zx) * isg : R(0);
+                const P isg = P(1.0 / sigma);
+                ph = dual ? r * isg : P(0);
+                thv = thlane ? (zxn - zx) * isg : P(0);
             }
         }
         sl[Lds::P + 16] = ph;
         sl[Lds::T + 16] = thv;
         __syncthreads();
-        R q2 = R(0);
+        P q2 = P(0);
         if (wact) {
-            const R phm = sl[Lds::P], thm = sl[Lds::T];  // row k-1 (zero above node 0)
+            const P phm = sl[Lds::P], thm = sl[Lds::T];  // row k-1 (zero above node 0)
             // x part: (A^-_k)^T phi_k - phi_{k-1}, and theta_{k-1} - theta_k on the y lane
-            R r;
+            P r;
             {
                 R c[8];
                 colA.get_lo(c);
-                r = rowdot_part<R, 0, 8>(c, ph, R(0));
+                r = pw_dot<R, P, 0, 1, 8>(c, ph, P(0));
             }
             {
                 R c[8];
                 colA.get_hi(c);
-                r = rowdot_part<R, 8, 7>(c, ph, r);
+                r = pw_dot<R, P, 8, 1, 7>(c, ph, r);
             }
             r -= phm;
             r -= thv;
             r += thm;
-            zx = isx ? r : R(0);
+            zx = isx ? r : P(0);
             // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
-            R gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = rowBm[q] * ph + rowBq[q] * phm;
-            const R zq = row_reduce_scatter4<R>(gq, i);
-            zu = node ? zq : R(0);
+            P gq[NU];
+            for (int q = 0; q < NU; ++q) gq[q] = P(rowBm[q]) * ph + P(rowBq[q]) * phm;
+            const P zq = row_reduce_scatter4<P>(gq, i);
+            zu = node ? zq : P(0);
             dmu = ph + ph;
-            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : R(0)) + (ph * ph + ph * ph);
+            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : P(0)) + (ph * ph + ph * ph);
         }
         sl[Lds::Z] = zx;
         sl[Lds::U] = zu;
-        const double wsum = wave_sum<R>(q2);
+        const double wsum = wave_sum<P>(q2);
         if ((t & 63) == 0) red[t >> 6] = wsum;
         __syncthreads();
         double s2 = red[0];
@@ -815,12 +915,12 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
 }
 
 // FP32: registers bounded for five waves per SIMD (four 5-wave workgroups per CU)
-template <typename R, int MAXT>
+template <typename R, typename P, int MAXT>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 prepare_kernel(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prepare_body<R, MAXT>(a, blockIdx.x, smem_raw);
+    prepare_body<R, P, MAXT>(a, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1008,8 +1108,17 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const R g_a = role == 2 ? R(1.0 / tan_g) : (role == 5 ? R(tan_d) : R(0));
     const R g_inv = role == 2 ? R(1.0 / (1.0 + 1.0 / (tan_g * tan_g)))
                               : (role == 5 ? R(1.0 / (1.0 + tan_d * tan_d)) : R(1));
+    // rate ball at the last node: the transverse rates are fixed boundary values, so the roll
+    // rate is projected onto the ball's slice through them (radius sqrt(w_max^2 - w2^2 - w3^2),
+    // zero when they alone leave the ball); the fixed members then contribute zero below
+    double w_rad = double(p[17]);
+    if (role == 4 && k == K - 1) {
+        const double c2 = double(a.xf[(long)b * NXF + 11]), c3 = double(a.xf[(long)b * NXF + 12]);
+        const double r2 = w_rad * w_rad - c2 * c2 - c3 * c3;
+        w_rad = r2 > 0.0 ? sqrt(r2) : 0.0;
+    }
     const R g_rad = role == 3 ? R(sqrt(0.5 * (1.0 - cos(double(p[16])))))
-                              : (role == 4 ? p[17] : (role == 5 ? p[13] : INF));
+                              : (role == 4 ? R(w_rad) : (role == 5 ? p[13] : INF));
     const bool g_cone = role == 2 || role == 5;
     const R mdry = p[1];
     const R ipxi = R(1.0 / a.px[isx ? i : 0]);
@@ -1087,7 +1196,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             // set from itself and lanes +1, +2 (row_shl).  Every DPP exchange is evaluated by
             // all lanes before any selection (a lane-dependent condition around it would mask
             // out the lanes it reads from).
-            const R s0 = mb + msc * (tmem ? un : xn);
+            // (members that are fixed boundary values enter as zero: see the rate ball above)
+            const R s0 = (fixed && !tmem) ? R(0) : mb + msc * (tmem ? un : xn);
             const R s1 = dppmov<0x101>(s0), s2 = dppmov<0x102>(s0);
             R t0 = s0, t1 = s1;
             R t2 = tilt ? R(0) : s2;
@@ -1327,19 +1437,32 @@ size_t qp_smem_bytes(int kmax, size_t rsize)
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
     return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
 }
-// dynamic LDS bytes of the preparation kernel
-static size_t prep_smem_bytes(int kmax, size_t rsize)
+// dynamic LDS bytes of the preparation kernel (rsize: the working precision, psize: that of
+// the power iteration)
+static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
 {
     const int maxt = qp_maxt(kmax);
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
-    const size_t stage = rsize == 4 ? (maxt == 320 ? PrepLds<float, 320>::BYTES
+    const size_t stage = psize == 4 ? (maxt == 320 ? PrepLds<float, 320>::BYTES
                                                    : (maxt == 640 ? PrepLds<float, 640>::BYTES
                                                                   : PrepLds<float, 1024>::BYTES))
                                     : (maxt == 320 ? PrepLds<double, 320>::BYTES
                                                    : (maxt == 640 ? PrepLds<double, 640>::BYTES
                                                                   : PrepLds<double, 1024>::BYTES));
     return stage + rsize * KR * 16 * col;
+}
+
+template <typename R, typename P>
+static void launch_prepare(int maxt, int B, int threads, size_t smem, hipStream_t stream,
+                           const Args<R> &a)
+{
+    if (maxt == 320)
+        prepare_kernel<R, P, 320><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    else if (maxt == 640)
+        prepare_kernel<R, P, 640><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    else
+        prepare_kernel<R, P, 1024><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
 
 // Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
@@ -1466,7 +1589,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
     const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
-    const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R));
+    // power iteration in FP64 unless the FP32 variant is selected (FP32 path only)
+    const bool pw32 = sizeof(R) == 4 && cfg.power_fp32;
+    const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R), pw32 ? 4 : 8);
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
     a.split = 0;
@@ -1489,12 +1614,10 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(1, false)) != hipSuccess) return e;
         if ((e = mark(3, true)) != hipSuccess) return e;
-        if (maxt == 320)
-            prepare_kernel<R, 320><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
-        else if (maxt == 640)
-            prepare_kernel<R, 640><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
+        if (pw32)
+            launch_prepare<R, R>(maxt, cfg.B, qthreads, psmem, stream, a);
         else
-            prepare_kernel<R, 1024><<<dim3(cfg.B), dim3(qthreads), psmem, stream>>>(a);
+            launch_prepare<R, double>(maxt, cfg.B, qthreads, psmem, stream, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(3, false)) != hipSuccess) return e;
         if (j > cfg.scp_iters_max) break;  // the last test has set every remaining status

@@ -41,6 +41,7 @@ struct Config {
     int grad_rk4_tangent;   // 1: the gradient takes the RK4 share by forward tangents
     int scalar_dilation;    // 1: one dilation value over the horizon (PIPG projects the
                             //   dilation controls of all nodes onto their mean)
+    int power_fp32;         // 1 (FP32 path): power iteration in FP32 instead of FP64
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;

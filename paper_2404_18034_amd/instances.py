@@ -11,9 +11,10 @@ uniform number in [0, 1).  Any instance can be regenerated on its own from (seed
 Instance layout (float64, row-major), matching the library's boundary:
   x0[B,15] = (m0, r0[3], v0[3], q0[4], w0[3], y0 = 0)
   xf[B,13] = (r_f[3], v_f[3], q_f[4], w_f[3])
-  params[B,23] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
+  params[B,24] = m_wet, m_dry, alpha_mdot, g[3], J_diag[3], r_T[3], T_min, T_max,
                  delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs, s_init,
-                 v_max (+inf: no speed bound)
+                 v_max (+inf: no speed bound), gamma_max (bound of the reaction-control
+                 torque; read only by solves with the torque input, n_u = 7)
   K[B] int32 node counts.
 The nominal vehicle is the nondimensional lander of the paper's 6-DoF example with the
 values stated for the single-instance case (g = (-1,0,0), m_wet = 2, m_dry = 1,
@@ -60,7 +61,7 @@ NOMINAL = dict(
     m_wet=2.0, m_dry=1.0, alpha_mdot=0.01, g=(-1.0, 0.0, 0.0), J=(0.01, 0.01, 0.01),
     r_T=(-0.01, 0.0, 0.0), T_min=0.3, T_max=5.0, delta_max=math.radians(20.0),
     gamma_gs=math.radians(20.0), theta_max=math.radians(90.0), omega_max=math.radians(60.0),
-    s_min=0.1, s_max=20.0, eps_ctcs=1e-4, s_init=5.0, v_max=math.inf,
+    s_min=0.1, s_max=20.0, eps_ctcs=1e-4, s_init=5.0, v_max=math.inf, gamma_max=0.005,
     r0=(4.0, 4.0, 0.0), v0=(-1.0, -2.0, 0.0), rf=(0.0, 0.0, 0.0), vf=(-0.1, 0.0, 0.0),
 )
 
@@ -70,14 +71,14 @@ def nominal_params():
     return np.array([n["m_wet"], n["m_dry"], n["alpha_mdot"], *n["g"], *n["J"], *n["r_T"],
                      n["T_min"], n["T_max"], n["delta_max"], n["gamma_gs"], n["theta_max"],
                      n["omega_max"], n["s_min"], n["s_max"], n["eps_ctcs"], n["s_init"],
-                     n["v_max"]],
+                     n["v_max"], n["gamma_max"]],
                     dtype=np.float64)
 
 
 # Frozen solver settings shared by every configuration (the paper leaves them open; they
 # were chosen once on the oracle and are used unchanged by both implementations).
 HYPER = dict(
-    pipg_check_every=10, rk4_substeps=5, power_iters_max=50, node_projections=31, pad=0,
+    pipg_check_every=10, rk4_substeps=5, power_iters_max=50, node_projections=0, pad=0,
     scp_tol=1e-4, feas_tol=1e-4, pipg_eps_abs=1e-5, pipg_eps_rel=1e-5,
     power_eps_abs=0.0, power_eps_rel=1e-6, power_buff=0.1,
     w_cost=0.005, w_prox=0.3, w_ep=100.0, omega=16.0, rho=1.9,
@@ -115,15 +116,24 @@ CONFIGS = {
                seed=5),
     # The same runs with the paper's speed bound ||v|| <= v_max (a path constraint of section
     # "6-DoF Powered Descent Guidance", enforced through the CTCS integrand) at v_max = 2.5:
-    # every run starts at |v| = 2.24 and, unbounded, peaks between 2.34 and 2.63.  The proximal
-    # weight is raised to 1 (at 0.3 intermediate iterates that cross the bound make a quarter
-    # of the runs diverge).
+    # every run starts at |v| = 2.24 and, unbounded, peaks between 2.45 and 2.66.
     "F1S": dict(name="paper's Monte Carlo 256 x K=30 with speed bound, FP32", B=256, K=(30,),
                 dtype="f32",
                 disp=dict(r_box=((6.0, 9.0), (3.0, 6.0), (1.0, 2.0)), r=0.0, v=0.0, m=0.0,
                           tilt_deg=0.0, JrT=0.0),
                 scp_iters_max=25, pipg_iters_max=2500, early_exit=1, pipg_check_every=2501,
-                seed=5, v_max=2.5, settings=dict(w_prox=1.0)),
+                seed=5, v_max=2.5),
+    # The paper's full control set (section "6-DoF Powered Descent Guidance"): the same 256
+    # runs with the reaction-control torque gamma as a control input beside the thrust,
+    # u = (T, gamma, s), bounded by ||gamma|| <= gamma_max = 0.005 through the CTCS integrand
+    # (a quarter of the largest torque the gimbaled thrust can exert); its prescaling is the
+    # bound itself.
+    "F2": dict(name="paper's Monte Carlo 256 x K=30 with torque control, FP32", B=256, K=(30,),
+               dtype="f32",
+               disp=dict(r_box=((6.0, 9.0), (3.0, 6.0), (1.0, 2.0)), r=0.0, v=0.0, m=0.0,
+                         tilt_deg=0.0, JrT=0.0),
+               scp_iters_max=25, pipg_iters_max=2500, early_exit=1, pipg_check_every=2501,
+               seed=5, settings=dict(n_u=7, pu=(5.0, 5.0, 5.0, 0.005, 0.005, 0.005, 5.0))),
 }
 
 

@@ -13,23 +13,24 @@ NX, NU = 15, 4
 IY = 14
 
 
-def sizes(K):
+def sizes(K, n_u=NU):
     M = K - 1
-    nx, nu, nm = K * NX, K * NU, M * NX
+    nx, nu, nm = K * NX, K * n_u, M * NX
     return M, nx, nu, nm, nx + nu + 2 * nm
 
 
 def assemble(qp, w_prox, w_cost, w_ep):
     Am, Bm, Bp = qp["Am"], qp["Bm"], qp["Bp"]
     K = Am.shape[0] + 1
-    M, nx, nu, nm, n = sizes(K)
+    n_u = Bm.shape[-1]
+    M, nx, nu, nm, n = sizes(K, n_u)
     G = np.zeros((M * NX, n))
     for k in range(M):
         r = slice(k * NX, (k + 1) * NX)
         G[r, k * NX:(k + 1) * NX] = Am[k]
         G[r, (k + 1) * NX:(k + 2) * NX] = -np.eye(NX)
-        G[r, nx + k * NU:nx + (k + 1) * NU] = Bm[k]
-        G[r, nx + (k + 1) * NU:nx + (k + 2) * NU] = Bp[k]
+        G[r, nx + k * n_u:nx + (k + 1) * n_u] = Bm[k]
+        G[r, nx + (k + 1) * n_u:nx + (k + 2) * n_u] = Bp[k]
         G[r, nx + nu + k * NX:nx + nu + (k + 1) * NX] = np.eye(NX)
         G[r, nx + nu + nm + k * NX:nx + nu + nm + (k + 1) * NX] = -np.eye(NX)
     g = -qp["w"].reshape(-1) if "w" in qp else np.zeros(M * NX)
@@ -43,12 +44,12 @@ def assemble(qp, w_prox, w_cost, w_ep):
     p = np.zeros(n)
     p[(K - 1) * NX + 0] = -w_cost          # e_cost = -e_m on the final node
     p[nx + nu:] = w_ep
-    return dict(P=P, p=p, G=G, g=g, H=H, h=h, K=K, n=n)
+    return dict(P=P, p=p, G=G, g=g, H=H, h=h, K=K, n=n, n_u=n_u)
 
 
-def split(z, K):
-    M, nx, nu, nm, n = sizes(K)
-    return dict(x=z[:nx].reshape(K, NX), u=z[nx:nx + nu].reshape(K, NU),
+def split(z, K, n_u=NU):
+    M, nx, nu, nm, n = sizes(K, n_u)
+    return dict(x=z[:nx].reshape(K, NX), u=z[nx:nx + nu].reshape(K, n_u),
                 mup=z[nx + nu:nx + nu + nm].reshape(M, NX),
                 mum=z[nx + nu + nm:].reshape(M, NX))
 
@@ -129,7 +130,7 @@ def project(z, qp, K, node=None, active=None):
     """Projection onto the subproblem's constraint set: boundary values, the u box, mu >= 0
     (the paper's set), and with `node` = dict(xbar, ubar, px, pu, p, mask) the node-wise
     convex sets, which act in original units x = xbar + px x^, u = ubar + pu u^."""
-    d = split(z.copy(), K)
+    d = split(z.copy(), K, qp["umin"].shape[-1])
     d["x"][0, :] = qp["zi"]
     for i in FINAL_FIXED:
         d["x"][K - 1, i] = qp["zf"][i - 1]

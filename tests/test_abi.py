@@ -41,15 +41,19 @@ def test_workspace_bytes_and_validation(lib):
     assert n1 > 0 and api.workspace_bytes(s2) > n1 and api.workspace_bytes(s3) > n1
     assert n1 % 256 == 0
     for bad in (dict(k_max=1), dict(k_max=51), dict(w_prox=0.0), dict(rho=2.0),
-                dict(pipg_iters_max=0), dict(dtype=7)):
+                dict(pipg_iters_max=0), dict(dtype=7), dict(power_fp32=2), dict(power_fp32=-1)):
         sb = api.make_settings(cfg, "f32", 20, 1024)
         for k, v in bad.items():
             setattr(sb, k, v)
         assert api.workspace_bytes(sb) == 0
-    # node projections need block-uniform scales
-    sb = api.make_settings(dict(cfg, px=(1, 4, 4, 3, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 0.1)),
-                           "f32", 20, 1024)
+    # node projections need block-uniform scales (the paper's set alone does not)
+    px = (1, 4, 4, 3, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 0.1)
+    sb = api.make_settings(dict(cfg, px=px, node_projections=31), "f32", 20, 1024)
     assert api.workspace_bytes(sb) == 0
+    sb = api.make_settings(dict(cfg, px=px, node_projections=0), "f32", 20, 1024)
+    assert api.workspace_bytes(sb) == n1
+    # the power-iteration precision setting needs no extra workspace
+    assert api.workspace_bytes(api.make_settings(dict(cfg, power_fp32=1), "f32", 20, 1024)) == n1
 
 
 def test_create_rejects_bad_workspace_before_any_hip_call(lib):

@@ -11,8 +11,7 @@ import pytest
 import oracle
 from paper_2404_18034_amd import api
 from paper_2404_18034_amd import instances as I
-from test_gpu_parity import (TOL_F64, _errors, _gpu, _report, _valid, check_fp32_against_oracle,
-                             well_conditioned)
+from test_gpu_parity import TOL_F64, _errors, _gpu, _report, _valid, check_fp32_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -38,35 +37,31 @@ def test_scalar_dilation_short_horizon_all_instances(dtype):
         for e in errs:
             assert e.max() <= TOL_F64
     else:
-        check_fp32_against_oracle(cfg, inst, g, o, "C2 scalar dilation fp32 3 subproblems",
-                                  kmax=30)
+        assert check_fp32_bar(cfg, inst, g, o, "C2 scalar dilation fp32 3 subproblems").all()
 
 
 def test_scalar_dilation_full_solve_fp64():
-    # whole solves with early exit: statuses, iteration counts and trajectories on the
-    # instances the oracle certifies as well conditioned
+    # whole solves with early exit: statuses, iteration counts and trajectories on every
+    # instance
     print("case: scalar dilation, C2 x 24, full solve, f64", flush=True)
     cfg = I.solver_settings("C2", scalar_dilation=1)
     inst = I.make_instances("C2", B=24)
     g = _gpu(cfg, inst, "f64", k_max=30)
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
-    ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
-    print("well conditioned: %d / %d; oracle status counts %s"
-          % (ok.sum(), ok.size, np.bincount(o["status"], minlength=3).tolist()))
-    assert ok.mean() >= 0.6
+    print("oracle status counts %s" % np.bincount(o["status"], minlength=3).tolist())
     errs = _errors(cfg, g, o)
-    _report("C2 scalar dilation fp64 (well-conditioned)", [e[ok] for e in errs])
+    _report("C2 scalar dilation fp64", errs)
     for e in errs:
-        assert e[ok].max() <= TOL_F64
+        assert e.max() <= TOL_F64
     for k in ("status", "scp_iters", "pipg_iters"):
-        np.testing.assert_array_equal(g[k][ok], o[k][ok])
+        np.testing.assert_array_equal(g[k], o[k])
     _one_value(g, inst)
     np.testing.assert_allclose(g["t_f"], g["u"][:, 0, 3], rtol=1e-14)
 
 
 def test_scalar_dilation_fp32_monte_carlo_sample():
     # the 1,024-instance Monte Carlo configuration (15 SCP x 1,000 PIPG, fixed work) on a
-    # 32-instance sample, FP32 against the oracle with the per-output FP32 certificate
+    # 32-instance sample, FP32 against the oracle at the fixed FP32 bar
     # (runs the oracle itself leaves non-finite are dropped from the sample first)
     print("case: scalar dilation, C1 x 32, f32", flush=True)
     cfg = I.solver_settings("C1", scalar_dilation=1)
@@ -79,7 +74,7 @@ def test_scalar_dilation_fp32_monte_carlo_sample():
     g = _gpu(cfg, inst, "f32")
     _valid(g, inst)
     _one_value(g, inst)
-    check_fp32_against_oracle(cfg, inst, g, o, "C1 scalar dilation fp32")
+    assert check_fp32_bar(cfg, inst, g, o, "C1 scalar dilation fp32").all()
 
 
 @pytest.mark.parametrize("mode", [1, 2, 4])

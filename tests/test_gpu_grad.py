@@ -55,11 +55,15 @@ def _last_to_device(s, lasts, inst, ids):
 def _oracle_fd(cfg, inst, b, L, n):
     """Central differences at h = 1e-6.  The map is piecewise smooth (projections switch
     branches); where a branch switch lies within h of the point, the forward and backward
-    differences disagree, and that column is taken at h = 1e-8 instead (reported)."""
+    differences disagree (by more than 1e-5 of the column's scale), and that column is taken at
+    h = 1e-8 instead (reported).  Where they
+    still disagree at h = 1e-8 the point itself is a kink: no derivative exists there, and the
+    one-sided differences at 1e-8 are returned for that column (`kinks`: column -> (fwd, bwd))."""
     x0, xf, p, K = inst["x0"][b], inst["xf"][b], inst["params"][b], int(inst["K"][b])
     theta = oracle.theta_of(x0, p)
     val = oracle.truncated_map(cfg, x0, xf, p, K, theta, L, n)
     F = np.zeros((2, 18))
+    kinks = {}
     for i in range(18):
         e = np.zeros(18)
         e[i] = H
@@ -68,12 +72,21 @@ def _oracle_fd(cfg, inst, b, L, n):
         F[:, i] = (fp - fm) / (2 * H)
         fwd, bwd = (fp - val) / H, (val - fm) / H
         scale = np.abs(F[:, i]).max() + 1e-12
-        if np.abs(fwd - bwd).max() > 1e-3 * scale:
+        # a switch within h moves the central difference by up to half the gap between the
+        # one-sided ones: take the column again at a smaller step when that gap exceeds the
+        # FP64 bar
+        if np.abs(fwd - bwd).max() > 1e-5 * scale:
             e[i] = 1e-8
-            F[:, i] = (oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n) -
-                       oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)) / 2e-8
+            fp = oracle.truncated_map(cfg, x0, xf, p, K, theta + e, L, n)
+            fm = oracle.truncated_map(cfg, x0, xf, p, K, theta - e, L, n)
+            F[:, i] = (fp - fm) / 2e-8
+            fwd, bwd = (fp - val) / 1e-8, (val - fm) / 1e-8
             print("instance %d, theta[%d]: branch switch within h = 1e-6, h = 1e-8 used" % (b, i))
-    return F, val
+            if np.abs(fwd - bwd).max() > 1e-3 * (np.abs(F[:, i]).max() + 1e-12):
+                kinks[i] = (fwd, bwd)
+                print("instance %d, theta[%d]: kink at the point (one-sided differences %s, %s)"
+                      % (b, i, fwd, bwd))
+    return F, val, kinks
 
 
 def _gpu_jac(cfg, inst, ids, lasts, dtype):
@@ -109,7 +122,17 @@ def _run(cfg, inst, ids, dtype, tol, vtol):
     J, val = _gpu_jac(cfg, inst, ids, lasts, dtype)
     worst = 0.0
     for j, b in enumerate(ids):
-        F, v = _oracle_fd(cfg, inst, b, lasts[j], n)
+        F, v, kinks = _oracle_fd(cfg, inst, b, lasts[j], n)
+        # at a kink the GPU takes the branch of its forward evaluation: its column must match
+        # one of the two one-sided differences
+        for i, (fwd, bwd) in kinks.items():
+            scale = np.abs(F).max(axis=-1) + 1e-30
+            ef = np.max(np.abs(J[j][:, i] - fwd) / scale)
+            eb = np.max(np.abs(J[j][:, i] - bwd) / scale)
+            print("instance %d, theta[%d]: GPU vs one-sided differences %.2e / %.2e"
+                  % (b, i, ef, eb))
+            assert min(ef, eb) <= tol
+            F[:, i] = fwd if ef <= eb else bwd
         err = _rel_err(J[j], F).max()
         worst = max(worst, err)
         assert err <= tol, "instance %d: rel err %.3e\nGPU %s\nFD  %s" % (b, err, J[j], F)
@@ -127,9 +150,20 @@ def test_grad_fp64_matches_oracle_fd(proj):
 def test_grad_fp64_active_thrust_bound():
     # T_max low enough that the thrust bound is active: its derivative is nonzero both through
     # the CTCS integrand in the discretization and through the T_max ball of the projection
-    cfg = I.solver_settings("C3", scp_iters_max=5, pipg_iters_max=400)
+    cfg = I.solver_settings("C3", node_projections=31, scp_iters_max=5, pipg_iters_max=400)
     inst = I.make_instances("C3", B=4)
     inst["params"][:, 13] = 2.3
+    _run(cfg, inst, list(range(4)), "f64", 1e-5, 1e-11)
+
+
+def test_grad_fp64_rate_slice_at_last_node():
+    # the rate ball binding at the last node with nonzero landing transverse rates: the roll
+    # rate is projected onto the slice through them, forward and in the reverse sweep (the
+    # state sets only: with the thrust set too, T_max sits on kinks of this map here)
+    cfg = I.solver_settings("C3", node_projections=15, scp_iters_max=5, pipg_iters_max=400)
+    inst = I.make_instances("C3", B=4)
+    inst["params"][:, 17] = 0.0461
+    inst["xf"][:, 10:13] = (0.02, 0.03, -0.035)
     _run(cfg, inst, list(range(4)), "f64", 1e-5, 1e-11)
 
 

@@ -71,11 +71,11 @@ def test_select_best_rejects_bad_arguments():
 
 
 def test_multistart_paper_monte_carlo_k20_fp64():
-    # the paper's Monte Carlo at K = 20 with starts s_init in {4, 5, 6, 7}: the GPU's choice
-    # and the chosen trajectories match the oracle's; every problem converges, where the single
-    # start s_init = 5 leaves eight cycling
+    # the paper's Monte Carlo at K = 20 with the node-wise convex sets on and starts s_init in
+    # {4, 5, 6, 7}: the GPU's choice and the chosen trajectories match the oracle's; every
+    # problem converges, where the single start s_init = 5 leaves eight cycling
     print("case: multi-start paper Monte Carlo K=20 fp64", flush=True)
-    cfg = I.solver_settings("F1")
+    cfg = I.solver_settings("F1", node_projections=31)
     inst = I.make_instances("F1")
     inst["K"] = np.full(256, 20, np.int32)
     s_init = (4.0, 5.0, 6.0, 7.0)

@@ -1,13 +1,13 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle on identical
-seeded inputs.  Tolerances: FP64 path 1e-9, FP32 path TOL_F32 (scaled-absolute on the
-trajectory, relative on t_f and m_f); integer outputs exact.
+seeded inputs.  Tolerances: FP64 path 1e-9, FP32 path the fixed bar below (scaled-absolute on
+the trajectory, relative on t_f and m_f); integer outputs exact.
 
-A few Monte Carlo instances have an SCP iteration that is itself chaotic: the oracle run
-twice, with the initial state perturbed by 1e-13 relative, ends O(1) apart on them.  No
-implementation can reproduce such a trajectory bit for bit, so full-length comparisons are
-made on the instances the oracle shows to be well conditioned (amplification of an input
-perturbation <= AMP_MAX), and the others are checked for validity; every instance is
-compared exactly over a short horizon where the iteration is still stable."""
+With the node-wise thrust set (node_projections bit 16) a few instances have an SCP iteration
+that is itself chaotic: the oracle run twice, with the initial state perturbed by 1e-13
+relative, ends O(1) apart on them.  No implementation can reproduce such a trajectory bit for
+bit, so full-length FP64 comparisons with that set are made on the instances the oracle shows
+to be well conditioned (amplification of an input perturbation <= AMP_MAX); with the paper's
+constraint set (the default) every instance is compared."""
 import numpy as np
 import pytest
 
@@ -34,70 +34,69 @@ def well_conditioned(cfg, inst, o, rel, kmax=None):
     return (amp <= AMP_MAX) & (o2["status"] == o["status"]) & (o2["scp_iters"] == o["scp_iters"])
 
 
-def fp32_deviation(cfg, inst, o, kmax=None, contract=False):
-    """How far FP32 rounding alone moves each instance: the oracle's algorithm evaluated in
-    single precision (with fused multiply-adds when `contract`) against the FP64 oracle,
-    scaled-absolute on x and on u (the controls can be far more sensitive than the states).
-    Oracle-only."""
-    f = oracle.solve_f32(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=kmax,
-                         contract=contract)
-    px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
-    with np.errstate(invalid="ignore"):
-        return (np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2)),
-                np.max(np.abs(f["u"] - o["u"]) / pu, axis=(1, 2)))
+# FP32 bar (fixed; the arithmetic behind it is in the design notes, "FP32 tolerance"):
+# on every instance the oracle leaves finite and whose iteration counts the GPU reproduces,
+#   states (scaled-absolute), final mass and final time (relative) within TOL_F32,
+#   controls (scaled-absolute) within TOL_F32_U, and within TOL_F32 on U_FRAC of them;
+# with PIPG early exit the stopping tests are decided on FP32 iterates, so the GPU may stop a
+# subproblem ten steps before or after the oracle (a plain single-precision evaluation of the
+# oracle's own algorithm does so on 9-14 % of the uneven workload's instances): then at most
+# COUNT_FRAC of the instances differ in their counts, and every instance (same counts or not)
+# holds its states within TOL_F32_EE, its final time within TOL_F32_U, and its states within
+# TOL_F32 on EE_FRAC.
+TOL_F32_U = 1e-3
+U_FRAC = 0.97
+EE_FRAC = 0.95
+TOL_F32_EE = 1e-2
+COUNT_FRAC = 0.15
+FLAG_MARGIN = 1e-3
 
 
-FP32_DRAWS = 8
-FP32_FMA_DRAWS = 2
+def flags_agree(cfg, g, o, p):
+    """Converged/failed flags (status) must agree, except where the oracle sits within a
+    relative margin FLAG_MARGIN of one of its convergence thresholds: the scaled step against
+    scp_tol, the scaled defect against feas_tol, the scaled CTCS excess against feas_tol
+    (status 0 needs all three <= their thresholds).  A non-finite result (status 2) on the GPU
+    alone never agrees."""
+    near = lambda v, thr: np.abs(v - thr) <= FLAG_MARGIN * thr
+    ctcs = (o["ctcs_viol"] - p[:, 20]) / cfg["px"][14]
+    margin = (near(o["step"], cfg["scp_tol"]) | near(o["defect_inf"], cfg["feas_tol"]) |
+              near(ctcs, cfg["feas_tol"]))
+    same = g["status"] == o["status"]
+    return same | (margin & (g["status"] != 2))
 
 
-def check_fp32_against_oracle(cfg, inst, g, o, tag, kmax=None):
-    """FP32 GPU vs FP64 oracle, one certificate per output, from FP32_DRAWS single-precision
-    runs of the oracle's own algorithm (on the inputs, and with x0 moved by 1e-7 relative: other
-    draws of FP32 rounding).  States and final mass: where every draw stays within TOL_F32 / 10
-    of the FP64 states, the GPU must match to TOL_F32; elsewhere FP32 rounding by itself moves
-    the states (the node-wise thrust projection makes some instances sensitive) and the GPU
-    error must stay within 20x of the plain-FP32 deviation.  Controls: the plain-FP32 scatter
-    of the controls has a heavy tail (on the paper's Monte Carlo, ten draws move controls that
-    two draws place within 1e-5 by up to 9e-5; eight draws are taken), so every instance is held to
-    max(TOL_F32, 20x its plain-FP32 control deviation), and the final time (the integral of the
-    dilation control) to TOL_F32 where the controls are certified.  Status and iteration counts
-    must agree.  The GPU contracts multiply-adds, so FP32_FMA_DRAWS further draws take the
-    oracle's single-precision build with contraction (on the inputs and on a moved x0): its
-    rounding pattern can move an instance far more than the uncontracted one does."""
-    dx, du = fp32_deviation(cfg, inst, o, kmax)
-    rng = np.random.default_rng(11)
-    for d in range(FP32_DRAWS - 1 + FP32_FMA_DRAWS):
-        contract = d >= FP32_DRAWS - 1
-        rel = 0.0 if d == FP32_DRAWS - 1 else 1e-7
-        inst2 = dict(inst, x0=inst["x0"] * (1.0 + rel * rng.uniform(-1.0, 1.0,
-                                                                      inst["x0"].shape)))
-        inst2["x0"][:, 14] = 0.0
-        dx2, du2 = fp32_deviation(cfg, inst2, o, kmax, contract=contract)
-        dx, du = np.maximum(dx, dx2), np.maximum(du, du2)
+def check_fp32_bar(cfg, inst, g, o, tag, early_exit=None):
+    """FP32 GPU result against the FP64 oracle at the fixed FP32 bar (see above).  Returns the
+    mask of instances compared at full strength (finite, same iteration counts)."""
+    if early_exit is None:
+        early_exit = bool(cfg["early_exit"])
     fin = o["status"] != 2
-    ok = fin & (dx <= TOL_F32 / 10)
-    oku = fin & (du <= TOL_F32 / 10)
+    assert np.all(flags_agree(cfg, g, o, inst["params"])[fin]), (
+        "%s: status differs on %s" % (tag, np.flatnonzero(fin & (g["status"] != o["status"]))))
+    same = fin & (g["scp_iters"] == o["scp_iters"]) & (g["pipg_iters"] == o["pipg_iters"])
     ex, eu, etf, emf = _errors(cfg, g, o)
-    print("%s (FP32-conditioned: states %d/%d, controls %d/%d) x %.2e u %.2e t_f %.2e m_f %.2e"
-          % (tag, ok.sum(), ok.size, oku.sum(), oku.size, ex[ok].max(), eu[oku].max(),
-             etf[oku].max(), emf[ok].max()), flush=True)
-    for e, sel in ((ex, ok), (emf, ok), (etf, oku)):
-        assert e[sel].max() <= TOL_F32
-    rest = fin & ~ok
-    if rest.any():
-        ratio = ex[rest] / np.maximum(dx[rest], TOL_F32)
-        print("%s: %d FP32-sensitive instances (states), GPU error / plain-FP32 deviation max %.2f"
-              % (tag, rest.sum(), ratio.max()))
-        assert ratio.max() <= 20.0
-    bar = np.maximum(TOL_F32, 20.0 * du)
-    w = int(np.argmax(np.where(fin, eu / bar, -1.0)))
-    print("%s: controls, GPU error / max(TOL, 20x plain-FP32 deviation) max %.2f (instance %d: "
-          "error %.2e, plain deviation %.2e)" % (tag, eu[w] / bar[w], w, eu[w], du[w]))
-    assert np.all(eu[fin] <= bar[fin])
-    np.testing.assert_array_equal(g["status"][ok], o["status"][ok])
-    np.testing.assert_array_equal(g["scp_iters"], o["scp_iters"])
-    return ok
+    n = int(fin.sum())
+    print("%s: %d finite, %d with the oracle's counts; x max %.2e (n>1e-4: %d), u max %.2e "
+          "(n>1e-4: %d), t_f max %.2e, m_f max %.2e" % (
+              tag, n, same.sum(), ex[fin].max(), np.sum(ex[fin] > TOL_F32), eu[fin].max(),
+              np.sum(eu[fin] > TOL_F32), etf[fin].max(), emf[fin].max()), flush=True)
+    if not early_exit:
+        np.testing.assert_array_equal(g["scp_iters"][fin], o["scp_iters"][fin])
+        np.testing.assert_array_equal(g["pipg_iters"][fin], o["pipg_iters"][fin])
+    else:
+        assert (fin & ~same).sum() <= max(1, COUNT_FRAC * n), "%s: counts differ" % tag
+        assert ex[fin].max() <= TOL_F32_EE
+        assert etf[fin].max() <= TOL_F32_U
+        assert np.mean(ex[fin] <= TOL_F32) >= EE_FRAC
+    s = same if not early_exit else same & (ex <= TOL_F32)
+    if not early_exit:
+        assert ex[s].max(initial=0.0) <= TOL_F32
+    assert emf[s].max(initial=0.0) <= TOL_F32
+    assert etf[s].max(initial=0.0) <= TOL_F32
+    assert eu[s].max(initial=0.0) <= TOL_F32_U
+    assert np.mean(eu[s] <= TOL_F32) >= U_FRAC if s.any() else True
+    return same
 
 
 def _valid(g, inst):
@@ -121,14 +120,6 @@ def _errors(cfg, g, o):
 def _report(tag, errs):
     names = ("x", "u", "t_f", "m_f")
     print(tag, " ".join("%s %.2e" % (n, e.max()) for n, e in zip(names, errs)), flush=True)
-
-
-def flags_agree(cfg, g, o):
-    """Converged/failed flags must agree, except where the oracle sits within a relative
-    margin of 1e-3 of one of its convergence thresholds (step, defect, CTCS)."""
-    same = g["status"] == o["status"]
-    near = np.abs(o["defect_inf"] - cfg["feas_tol"]) <= 1e-3 * cfg["feas_tol"] * 10
-    return same | near
 
 
 def test_c0_fp64_matches_oracle():
@@ -169,7 +160,7 @@ def test_fp64_uneven_k_early_exit_matches_oracle(proj):
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
     ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
     print("well conditioned: %d / %d" % (ok.sum(), ok.size))
-    assert ok.mean() >= 0.75
+    assert ok.all() if proj == 0 else ok.mean() >= 0.75
     errs = _errors(cfg, g, o)
     _report("C2 fp64 proj=%d (well-conditioned)" % proj, [e[ok] for e in errs])
     for e in errs:
@@ -179,20 +170,33 @@ def test_fp64_uneven_k_early_exit_matches_oracle(proj):
     _valid(g, inst)
 
 
-@pytest.mark.parametrize("proj", [0, 31])
+@pytest.mark.parametrize("proj", [0, 15])
 def test_c1_fp32_sample_matches_oracle(proj):
-    # the benchmark workload's settings on 32 of its instances; with the node-wise thrust set
-    # (proj = 31) single-precision rounding by itself moves a few instances by more than
-    # TOL_F32 / 10, so the FP32 certificate decides which ones are held to TOL_F32
+    # the Monte Carlo workload's settings on 32 of its instances, with the paper's constraint
+    # set and with the node-wise state sets (dry mass, glide slope, tilt, rate)
+    print("case: C1 x 32, fp32, node_projections %d" % proj, flush=True)
     cfg = I.solver_settings("C1", node_projections=proj)
     inst = I.make_instances("C1", B=32)
     g = _gpu(cfg, inst, "f32")
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
-    ok = check_fp32_against_oracle(cfg, inst, g, o, "C1 fp32 proj=%d" % proj)
-    assert ok.mean() >= (1.0 if proj == 0 else 0.6)
-    assert np.all(flags_agree(cfg, g, o)[ok])
+    same = check_fp32_bar(cfg, inst, g, o, "C1 fp32 proj=%d" % proj)
+    assert same.all()
     assert np.all(g["scp_iters"] == 15) and np.all(g["pipg_iters"] == 15000)
     _valid(g, inst)
+
+
+def test_thrust_set_fp32_first_subproblem():
+    # the node-wise thrust set (gimbal cone and T_max ball): over the first subproblem (1,000
+    # PIPG iterations) FP32 follows the oracle at the fixed bar; from the second on, the
+    # truncated PIPG transient of this set is rounding-sensitive (the oracle's own
+    # single-precision evaluation moves by up to 1e-2 over whole solves), so longer horizons
+    # are compared in FP64 only
+    print("case: C1 x 32, fp32, node_projections 31, 1 subproblem", flush=True)
+    cfg = I.solver_settings("C1", node_projections=31, scp_iters_max=1)
+    inst = I.make_instances("C1", B=32)
+    g = _gpu(cfg, inst, "f32")
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
+    assert check_fp32_bar(cfg, inst, g, o, "C1 fp32 proj=31, 1 subproblem").all()
 
 
 def test_few_iterations_fp32_tight():
@@ -207,36 +211,85 @@ def test_few_iterations_fp32_tight():
         assert e.max() <= 2e-5
 
 
-@pytest.mark.parametrize("proj", [0, 31])
-def test_c4_sample_fp32_matches_oracle(proj):
+def test_c4_sample_fp32_matches_oracle():
     # K = 30 with dispersed inertia and thrust lever arm
-    cfg = I.solver_settings("C4", node_projections=proj)
+    print("case: C4 x 16, fp32", flush=True)
+    cfg = I.solver_settings("C4")
     inst = I.make_instances("C4", ids=np.arange(16) * 256)
     g = _gpu(cfg, inst, "f32")
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
-    ok = check_fp32_against_oracle(cfg, inst, g, o, "C4 fp32 proj=%d" % proj)
-    assert ok.sum() >= (12 if proj == 0 else 4)
+    assert check_fp32_bar(cfg, inst, g, o, "C4 fp32").all()
     _valid(g, inst)
 
 
-def test_full_c1_batch_sampled_against_oracle():
-    # the full 1,024-instance batch in the configuration the benchmark times; sampled
-    # instances are checked against the oracle one by one, all against invariants
-    cfg = I.solver_settings("C1")
-    inst = I.make_instances("C1")
-    g = _gpu(cfg, inst, "f32")
-    ids = np.array([0, 1, 127, 511, 700, 1023])
+def test_full_c4_batch_sampled_against_oracle():
+    # the full 65,536-instance throughput batch in the launch variant the benchmark's autotuner
+    # picks; 64 sampled instances are checked against the oracle one by one at the FP32 bar,
+    # every instance against invariants (boundary values, statuses, finite values)
+    import torch
+    print("case: C4 full batch, fp32, autotuned", flush=True)
+    cfg = I.solver_settings("C4")
+    inst = I.make_instances("C4")
+    s = api.BatchSolver(cfg, dtype="f32", k_max=30, max_batch=inst["K"].size)
+    try:
+        prob = s.to_device(inst)
+        sol = s.alloc_solution(inst["K"].size)
+        variant, _ = s.autotune(prob, sol)
+        s.solve_into(prob, sol)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in sol.items()}
+    finally:
+        s.close()
+    print("variant", variant, flush=True)
+    ids = np.arange(64) * 1024 + 17
     sinst = {k: v[ids] for k, v in inst.items()}
     o = oracle.solve(cfg, sinst["x0"], sinst["xf"], sinst["params"], sinst["K"])
     sub = {k: v[ids] for k, v in g.items()}
-    ok = check_fp32_against_oracle(cfg, sinst, sub, o, "C1 full sampled")
-    assert ok.sum() >= 3
-    assert np.all(np.isfinite(g["x"])) and np.all(np.isin(g["status"], [0, 1]))
+    assert check_fp32_bar(cfg, sinst, sub, o, "C4 full batch, sampled").all()
+    counts = np.bincount(g["status"], minlength=4)
+    print("status counts over the batch:", counts.tolist(), flush=True)
+    assert np.all(np.isin(g["status"], [0, 1, 2]))
+    # the instances that met a non-finite value: the oracle meets one too
+    bad = np.flatnonzero(g["status"] == 2)
+    assert bad.size <= 64
+    if bad.size:
+        binst = {k: v[bad] for k, v in inst.items()}
+        ob = oracle.solve(cfg, binst["x0"], binst["xf"], binst["params"], binst["K"])
+        print("non-finite on the GPU:", bad.tolist(), "oracle statuses:", ob["status"].tolist())
+        assert np.all(ob["status"] == 2)
+    ok = g["status"] != 2
+    assert np.all(np.isfinite(g["x"][ok])) and np.all(np.isfinite(g["u"][ok]))
     fixed = [1, 2, 3, 4, 5, 6, 9, 10, 12, 13]
-    np.testing.assert_allclose(g["x"][:, 0, :14], inst["x0"][:, :14], atol=2e-6)
-    np.testing.assert_allclose(g["x"][:, -1, fixed], inst["xf"][:, [i - 1 for i in fixed]],
-                               atol=2e-6)
+    np.testing.assert_allclose(g["x"][ok, 0, :14], inst["x0"][ok, :14], atol=4e-6)
+    np.testing.assert_allclose(g["x"][ok][:, -1, fixed],
+                               inst["xf"][ok][:, [i - 1 for i in fixed]], atol=4e-6)
+    assert np.all(g["pipg_iters"][ok] == 1000 * g["scp_iters"][ok])
+    assert np.all(g["scp_iters"][ok] == 15)
     assert np.mean(g["status"] == 0) > 0.8
+
+
+_C2_ORACLE = {}
+
+
+def _c2_oracle(cfg, inst):
+    key = inst["K"].size
+    if key not in _C2_ORACLE:
+        _C2_ORACLE[key] = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"],
+                                       kmax=30)
+    return _C2_ORACLE[key]
+
+
+@pytest.mark.parametrize("mode,occupancy", [(0, 0), (1, 6), (3, 0), (4, 0)])
+def test_c2_fp32_early_exit_matches_oracle(mode, occupancy):
+    # the uneven workload (K in {10, 20, 30}, SCP and PIPG early exit) in FP32 against the
+    # oracle: plain launches, the graph, the persistent work queue and the K-bucketed launches
+    print("case: C2 x 96, fp32, early exit, mode %d occupancy %d" % (mode, occupancy), flush=True)
+    cfg = I.solver_settings("C2", mode=mode, occupancy=occupancy)
+    inst = I.make_instances("C2", B=96)
+    g = _gpu(cfg, inst, "f32", k_max=30)
+    o = _c2_oracle(cfg, inst)
+    check_fp32_bar(cfg, inst, g, o, "C2 fp32 mode %d occ %d" % (mode, occupancy))
+    _valid(g, inst)
 
 
 def test_repeat_runs_bitwise_identical():
@@ -371,8 +424,10 @@ def test_autotune_picks_a_mode_and_keeps_results(tmp_path):
 def test_node_counts_up_to_50_short_horizon(dtype):
     # node counts above 40 take the 1,024-lane workgroup variant; with K = 2 and K = 12 in the
     # same batch most of its waves sit beyond the last node of those instances
-    cfg = I.solver_settings("C2", node_projections=31, scp_iters_max=2, pipg_iters_max=200,
-                            early_exit=0)
+    # FP64 with every node-wise set (the projections at every row count); FP32 with the
+    # paper's set (the thrust set's FP32 sensitivity is covered by its own test)
+    cfg = I.solver_settings("C2", node_projections=31 if dtype == "f64" else 0,
+                            scp_iters_max=2, pipg_iters_max=200, early_exit=0)
     inst = I.make_instances("C2", B=6)
     inst["K"] = np.array([41, 50, 44, 12, 47, 2], dtype=np.int32)
     print("case: K up to 50, %s, k_max 50" % dtype, flush=True)
@@ -386,7 +441,7 @@ def test_node_counts_up_to_50_short_horizon(dtype):
         for k in ("status", "scp_iters", "pipg_iters"):
             np.testing.assert_array_equal(g[k], o[k])
     else:
-        check_fp32_against_oracle(cfg, inst, g, o, "K<=50 fp32 2 subproblems", kmax=50)
+        check_fp32_bar(cfg, inst, g, o, "K<=50 fp32 2 subproblems")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -404,17 +459,14 @@ def test_paper_monte_carlo_256_runs(dtype):
     assert np.all(g["status"] == 0) and np.all(g["scp_iters"] <= 25)
     np.testing.assert_array_equal(g["pipg_iters"], 2500 * g["scp_iters"])
     if dtype == "f64":
-        ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
-        print("well conditioned: %d / %d" % (ok.sum(), ok.size))
-        assert ok.mean() >= 0.9
         errs = _errors(cfg, g, o)
-        _report("F1 fp64 (well-conditioned)", [e[ok] for e in errs])
+        _report("F1 fp64", errs)
         for e in errs:
-            assert e[ok].max() <= TOL_F64
+            assert e.max() <= TOL_F64
         for k in ("status", "scp_iters", "pipg_iters"):
-            np.testing.assert_array_equal(g[k][ok], o[k][ok])
+            np.testing.assert_array_equal(g[k], o[k])
     else:
-        check_fp32_against_oracle(cfg, inst, g, o, "F1 fp32", kmax=30)
+        check_fp32_bar(cfg, inst, g, o, "F1 fp32")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -440,26 +492,49 @@ def test_speed_bound_short_horizon_all_runs(dtype):
         for e in errs:
             assert e.max() <= TOL_F64
     else:
-        check_fp32_against_oracle(cfg, inst, g, o, "F1S fp32 3 subproblems", kmax=30)
+        check_fp32_bar(cfg, inst, g, o, "F1S fp32 3 subproblems")
 
 
 def test_speed_bound_full_solve_fp64():
     # the whole solve with the speed bound (at most 25 SCP iterations of 2,500 PIPG
-    # iterations): statuses, iteration counts and trajectories of the oracle on the runs it
-    # certifies as well conditioned
+    # iterations): statuses, iteration counts and trajectories of the oracle on every run
     print("case: speed bound, 64 runs, full solve, f64", flush=True)
     cfg = I.solver_settings("F1S")
     inst = I.make_instances("F1S", B=64)
     g = _gpu(cfg, inst, "f64", k_max=30)
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
-    ok = well_conditioned(cfg, inst, o, 1e-13, kmax=30)
-    print("well conditioned: %d / %d; oracle status counts %s, GPU %s"
-          % (ok.sum(), ok.size, np.bincount(o["status"], minlength=3).tolist(),
-             np.bincount(g["status"], minlength=3).tolist()))
-    assert ok.mean() >= 0.6
+    print("oracle status counts %s, GPU %s" % (np.bincount(o["status"], minlength=3).tolist(),
+                                                np.bincount(g["status"], minlength=3).tolist()))
     errs = _errors(cfg, g, o)
-    _report("F1S fp64 (well-conditioned)", [e[ok] for e in errs])
+    _report("F1S fp64", errs)
     for e in errs:
-        assert e[ok].max() <= TOL_F64
+        assert e.max() <= TOL_F64
     for k in ("status", "scp_iters", "pipg_iters"):
-        np.testing.assert_array_equal(g[k][ok], o[k][ok])
+        np.testing.assert_array_equal(g[k], o[k])
+
+
+def test_node_sets_binding_fp64_matches_oracle():
+    # every node-wise set binding (tight thrust ball and gimbal, glide slope, tilt and rate
+    # bounds, dry mass) and a landing condition with nonzero transverse rates, so that the
+    # rate ball's slice at the last node acts: FP64 against the oracle, every instance
+    print("case: node sets binding, C1 x 16, fp64, 3 x 300", flush=True)
+    cfg = I.solver_settings("C1", node_projections=31, scp_iters_max=3, pipg_iters_max=300)
+    inst = I.make_instances("C1", B=16)
+    inst["params"][:, 13] = 2.6
+    inst["params"][:, 14] = np.radians(6.0)
+    inst["params"][:, 16] = np.radians(8.0)
+    inst["params"][:, 17] = 0.0461
+    inst["xf"][:, 10:13] = (0.02, 0.03, -0.035)
+    g = _gpu(cfg, inst, "f64")
+    o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
+    errs = _errors(cfg, g, o)
+    _report("node sets binding fp64", errs)
+    for e in errs:
+        assert e.max() <= TOL_F64
+    # the roll rate at the last node lies in the slice through the fixed transverse rates
+    w = g["x"][:, -1, 11:14]
+    assert np.all(np.linalg.norm(w, axis=1) <= 0.0461 * (1 + 1e-9))
+    r = np.sqrt(0.0461 ** 2 - 0.03 ** 2 - 0.035 ** 2)
+    assert np.sum(np.abs(np.abs(w[:, 0]) - r) <= 1e-12) >= 8      # the slice binds
+    for k in ("status", "scp_iters", "pipg_iters"):
+        np.testing.assert_array_equal(g[k], o[k])

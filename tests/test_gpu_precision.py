@@ -1,56 +1,28 @@
-"""Per-output error of the FP32 path against the FP64 oracle (precision policy: FP32 bulk,
-FP64 state in RK4, power iteration, reductions and CTCS), on the throughput workload's
-256-instance sample (instance ids 256*i).  Every output is reported.  x and m_f (u and t_f)
-are held to the FP32 tolerance on the instances whose states (controls) FP32 rounding by
-itself does not move (eight single-precision runs of the oracle's own algorithm, on the
-inputs and with x0 moved by 1e-7 relative, stay within a tenth of the tolerance);
-over the rest of the sample the GPU's error distribution (median, 90th percentile) must be
-that of a plain FP32 evaluation within a factor 10.  Iteration counts must agree exactly
-(fixed-work solve), status on the FP32-conditioned instances."""
+"""Per-output error of the FP32 path against the FP64 oracle (precision policy: FP32 bulk;
+FP64 for the RK4 state, the power iteration, the SCP reductions and the CTCS accumulator), on
+the throughput workload's 256-instance sample (instance ids 256*i), at the benchmark's
+settings.  Every output is reported; trajectories, final mass and final time are held to the
+fixed FP32 bar of the parity tests, statuses and iteration counts must agree exactly."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2404_18034_amd import api
 from paper_2404_18034_amd import instances as I
+from test_gpu_parity import check_fp32_bar
 
 pytestmark = pytest.mark.gpu
 
-TOL_F32 = 1e-4
-
-
-DRAWS = 8
-
-
-def _plain_fp32_deviation(cfg, inst, o):
-    """Deviation from the FP64 oracle of DRAWS single-precision runs of the oracle's algorithm:
-    one on the given inputs, the others with x0 moved by 1e-7 relative (other draws of FP32
-    rounding).  Returns the largest over the draws on x and on u, and the first run's on x."""
-    px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
-    devs, devu = [], []
-    rng = np.random.default_rng(11)
-    for rel in (0.0,) + (1e-7,) * (DRAWS - 1):
-        x0 = inst["x0"] * (1.0 + rel * rng.uniform(-1.0, 1.0, inst["x0"].shape))
-        x0[:, 14] = 0.0
-        f = oracle.solve_f32(cfg, x0, inst["xf"], inst["params"], inst["K"], kmax=30)
-        with np.errstate(invalid="ignore"):
-            devs.append(np.max(np.abs(f["x"] - o["x"]) / px, axis=(1, 2)))
-            devu.append(np.max(np.abs(f["u"] - o["u"]) / pu, axis=(1, 2)))
-    return np.max(devs, axis=0), np.max(devu, axis=0), devs[0]
-
 
 def test_throughput_sample_error_report():
+    print("case: C4 sample of 256, fp32", flush=True)
     cfg = I.solver_settings("C4")
     ids = np.arange(256) * 256
     inst = I.make_instances("C4", ids=ids)
     g = api.solve(cfg, inst, dtype="f32", k_max=30)
     o = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"], kmax=30)
-    dev, devu, dev0 = _plain_fp32_deviation(cfg, inst, o)
     px, pu = np.array(cfg["px"]), np.array(cfg["pu"])
-    fin = (o["status"] != 2) & (g["status"] != 2)
-    ok = fin & (dev <= TOL_F32 / 10)
-    oku = fin & (devu <= TOL_F32 / 10)
-    cert = {"x (scaled abs)": ok, "u (scaled abs)": oku, "t_f (rel)": oku, "m_f (rel)": ok}
+    fin = o["status"] != 2
     rows = {
         "x (scaled abs)": np.max(np.abs(g["x"] - o["x"]) / px, axis=(1, 2)),
         "u (scaled abs)": np.max(np.abs(g["u"] - o["u"]) / pu, axis=(1, 2)),
@@ -60,29 +32,19 @@ def test_throughput_sample_error_report():
         "defect_inf (abs)": np.abs(g["defect_inf"] - o["defect_inf"]),
         "ctcs_viol (abs)": np.abs(g["ctcs_viol"] - o["ctcs_viol"]),
     }
-    print("\nFP32 GPU vs FP64 oracle, throughput sample: %d instances, %d finite, FP32-conditioned "
-          "%d (states) and %d (controls): %d plain single-precision runs within %.0e"
-          % (ids.size, fin.sum(), ok.sum(), oku.sum(), DRAWS, TOL_F32 / 10))
-    print("%-18s %11s %11s %11s %11s" % ("output", "median", "p90", "max(cond)", "max"))
+    print("\nFP32 GPU vs FP64 oracle, throughput sample: %d instances, %d finite"
+          % (ids.size, fin.sum()))
+    print("%-18s %11s %11s %11s %11s" % ("output", "median", "p90", "p99", "max"))
     for name, e in rows.items():
-        c = cert.get(name, ok)
         print("%-18s %11.3e %11.3e %11.3e %11.3e" % (name, np.median(e[fin]),
-                                                    np.quantile(e[fin], 0.9), e[c].max(),
-                                                    e[fin].max()))
-    print("%-18s %11.3e %11.3e %11s %11.3e" % ("plain FP32 x", np.median(dev0[fin]),
-                                               np.quantile(dev0[fin], 0.9), "",
-                                               dev0[fin].max()))
+                                                    np.quantile(e[fin], 0.9),
+                                                    np.quantile(e[fin], 0.99), e[fin].max()))
     for name in ("status", "scp_iters", "pipg_iters"):
         print("%-18s agree on %d / %d" % (name, np.sum(g[name] == o[name]), ids.size))
-    # where FP32 rounding does not move the result, the GPU matches the FP64 oracle
-    assert ok.sum() >= 16
-    assert oku.sum() >= 16
-    for name in ("x (scaled abs)", "u (scaled abs)", "t_f (rel)", "m_f (rel)"):
-        assert rows[name][cert[name]].max() <= TOL_F32, name
-    # elsewhere its deviation is that of a plain FP32 evaluation of the same algorithm
-    ex = rows["x (scaled abs)"][fin]
-    assert np.median(ex) <= 10 * max(np.median(dev0[fin]), TOL_F32 / 10)
-    assert np.quantile(ex, 0.9) <= 10 * max(np.quantile(dev0[fin], 0.9), TOL_F32 / 10)
-    np.testing.assert_array_equal(g["scp_iters"], o["scp_iters"])
-    np.testing.assert_array_equal(g["pipg_iters"], o["pipg_iters"])
-    np.testing.assert_array_equal(g["status"][ok], o["status"][ok])
+    assert fin.all()
+    assert check_fp32_bar(cfg, inst, g, o, "C4 sample of 256").all()
+    for name in ("status", "scp_iters", "pipg_iters"):
+        np.testing.assert_array_equal(g[name], o[name])
+    # the objective -m_f + w_ep * sum |scaled defect| is reported, not held to the bar: with
+    # w_ep = 100 over 435 defect entries it carries the FP32 rounding of the propagated states
+    # (the defect itself is an FP32-rounding-level quantity at convergence)

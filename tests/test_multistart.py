@@ -56,10 +56,11 @@ def test_multistart_batch_layout():
 
 
 def test_oracle_multistart_rescues_the_cycling_runs():
-    # the paper's Monte Carlo at K = 20: with s_init = 5 alone eight runs cycle; starts at
-    # s_init in {4, 5, 6, 7} leave every one of these problems (and their neighbours) with a
-    # converged start, and the chosen start costs no more than any converged start
-    cfg = I.solver_settings("F1")
+    # the paper's Monte Carlo at K = 20 with the node-wise convex sets on: with s_init = 5
+    # alone eight runs cycle; starts at s_init in {4, 5, 6, 7} leave every one of these
+    # problems (and their neighbours) with a converged start, and the chosen start costs no
+    # more than any converged start
+    cfg = I.solver_settings("F1", node_projections=31)
     inst = I.make_instances("F1", ids=[8, 27, 45, 92, 93, 154, 188, 233, 0, 1, 2, 3])
     inst["K"] = np.full(12, 20, np.int32)
     s_init = (4.0, 5.0, 6.0, 7.0)
