@@ -183,7 +183,8 @@ scp_status scp_batch_set_stream(scp_batch h, void *hip_stream);
 /* Message for the last failed call on this handle ("" if none); valid until the next call. */
 const char *scp_batch_last_error(scp_batch h);
 
-/* Message for the last failed scp_batch_create in this process. */
+/* Message for the last failed call without a handle in this process (scp_batch_create,
+ * scp_batch_solve_noalloc). */
 const char *scp_batch_create_error(void);
 
 /* Launch timing, for measurement tools.  With profiling enabled, every kernel launch of a
@@ -269,6 +270,24 @@ scp_status scp_batch_grad(scp_batch h, const scp_problem *problem, const scp_las
  * the solve on the same stream.  Asynchronous on the handle's stream. */
 scp_status scp_batch_select_best(scp_batch h, const scp_solution *solution, int32_t problems,
                                  int32_t starts, int32_t *best, scp_solution *out);
+
+/* Solve without allocating anything: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).  As
+ * scp_batch_solve for a handle created with `settings`, with plain kernel launches (workgroup
+ * b <-> instance b, whatever settings->mode says; gradients are not available here), but
+ * with no handle and no caller workspace: the workspace is a fixed device array inside the
+ * library, of SCP_NOALLOC_SCRATCH_BYTES (64 MiB) per device, which each device holds from the
+ * library's load until the process ends.  A batch whose workspace (scp_batch_workspace_bytes
+ * of these settings with max_batch = batch and no gradients) exceeds it is rejected with
+ * SCP_ERR_WORKSPACE before anything is launched: about 1,300 instances at k_max = 30 and
+ * 2,000 at k_max = 20 in FP32.  Every such call on a device shares that device's array, so
+ * calls that overlap on one device race (they must be ordered, e.g. on one stream); the
+ * kernels rewrite every part of the array they read, so no clearing is needed between calls.
+ * Enqueued on `hip_stream` (NULL: the default stream) of `device`, which becomes current for
+ * the call and is restored.  Errors as scp_batch_create (message: scp_batch_create_error). */
+#define SCP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+scp_status scp_batch_solve_noalloc(const scp_settings *settings, int device, void *hip_stream,
+                                   const scp_problem *problem, scp_solution *solution);
 
 /* Release the handle (not the caller's workspace).  Synchronizes its stream first. */
 scp_status scp_batch_destroy(scp_batch h);

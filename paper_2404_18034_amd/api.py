@@ -24,7 +24,7 @@ EXPORTS = ["scp_batch_workspace_bytes", "scp_batch_create", "scp_batch_solve",
            "scp_batch_set_stream", "scp_batch_last_error", "scp_batch_create_error",
            "scp_batch_profile", "scp_batch_profile_read", "scp_batch_autotune",
            "scp_batch_mode", "scp_batch_solve_record", "scp_batch_grad",
-           "scp_batch_select_best", "scp_batch_destroy"]
+           "scp_batch_select_best", "scp_batch_destroy", "scp_batch_solve_noalloc"]
 KERNEL_CLASSES = ("init", "discretize", "subproblem", "prepare")  # SCP_KERNEL_CLASSES order
 
 
@@ -127,6 +127,10 @@ def load():
         L.scp_batch_select_best.restype = ctypes.c_int
         L.scp_batch_destroy.argtypes = [ctypes.c_void_p]
         L.scp_batch_destroy.restype = ctypes.c_int
+        L.scp_batch_solve_noalloc.argtypes = [ctypes.POINTER(Settings), ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.POINTER(Problem),
+                                              ctypes.POINTER(Solution)]
+        L.scp_batch_solve_noalloc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -375,6 +379,28 @@ class BatchSolver:
         best = self.torch.empty(int(problems), dtype=self.torch.int32,
                                 device="cuda:%d" % self.device)
         return self.select_best_into(sol, problems, starts, best, self.alloc_solution(problems))
+
+
+def solve_noalloc_into(cfg, dtype, k_max, max_batch, prob, sol, device=0, stream=None):
+    """scp_batch_solve_noalloc: solve `prob` into `sol` (dicts of device tensors, as
+    BatchSolver.to_device / alloc_solution make them) with the library's fixed scratch as the
+    workspace; no handle, nothing allocated.  Asynchronous on `stream` (default: the current
+    stream of `device`)."""
+    import torch
+    L = load()
+    s = make_settings(cfg, dtype, k_max, max_batch)
+    B = int(prob["x0"].shape[0])
+    p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
+                prob["K"].data_ptr())
+    so = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status", "scp_iters",
+                                                 "pipg_iters", "defect_inf", "ctcs_viol",
+                                                 "objective")])
+    stream = torch.cuda.current_stream(device) if stream is None else stream
+    rc = L.scp_batch_solve_noalloc(ctypes.byref(s), int(device),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(p),
+                                   ctypes.byref(so))
+    if rc != 0:
+        raise ScpError(rc, L.scp_batch_create_error().decode())
 
 
 def solve(cfg, inst, dtype="f32", k_max=None, device=0):

@@ -725,6 +725,83 @@ scp_status scp_batch_select_best(scp_batch h, const scp_solution *sol, int32_t p
     return SCP_OK;
 }
 
+// Allocation-free solve: the workspace is the library's fixed device scratch array.
+static_assert(scp::SCRATCH_BYTES == SCP_NOALLOC_SCRATCH_BYTES, "scratch size of the header");
+scp_status scp_batch_solve_noalloc(const scp_settings *settings, int device, void *hip_stream,
+                                   const scp_problem *prob, scp_solution *sol)
+{
+    g_create_error.clear();
+    std::string why;
+    if (!settings_ok(settings, why)) { g_create_error = why; return SCP_ERR_ARG; }
+    if (!prob || !sol) { g_create_error = "problem or solution is NULL"; return SCP_ERR_ARG; }
+    if (prob->batch < 0 || prob->batch > settings->max_batch) {
+        g_create_error = "batch must be in [0, max_batch]";
+        return SCP_ERR_SHAPE;
+    }
+    if (prob->batch == 0) return SCP_OK;
+    const void *in_ptrs[] = {prob->x0, prob->xf, prob->params, prob->K};
+    const void *out_ptrs[] = {sol->x, sol->u, sol->t_f, sol->m_f, sol->status,
+                              sol->scp_iters, sol->pipg_iters, sol->defect_inf,
+                              sol->ctcs_viol, sol->objective};
+    for (const void *p : in_ptrs)
+        if (!p || !aligned16(p)) { g_create_error = "a problem array is NULL or not 16-byte aligned"; return SCP_ERR_ARG; }
+    for (const void *p : out_ptrs)
+        if (!p || !aligned16(p)) { g_create_error = "a solution array is NULL or not 16-byte aligned"; return SCP_ERR_ARG; }
+    // the workspace of this batch (no gradient scratch), carved from the fixed array
+    scp_settings s = *settings;
+    s.max_batch = prob->batch;
+    s.grad_pipg_steps = 0;
+    const Layout L = layout_of(&s);
+    if (L.total > scp::SCRATCH_BYTES) {
+        g_create_error = "this batch needs " + std::to_string(L.total) +
+                         " bytes of workspace; the fixed scratch holds " +
+                         std::to_string(scp::SCRATCH_BYTES);
+        return SCP_ERR_WORKSPACE;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) { g_create_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(e); return SCP_ERR_HIP; }
+    if (device < 0 || device >= ndev) { g_create_error = "no such device"; return SCP_ERR_DEVICE; }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { g_create_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e); return SCP_ERR_HIP; }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950";
+        return SCP_ERR_DEVICE;
+    }
+    if (scp::qp_smem_bytes(s.k_max, s.dtype == SCP_F64 ? 8 : 4) > (size_t)prop.sharedMemPerBlock) {
+        g_create_error = "subproblem workgroup of this k_max does not fit the device's LDS";
+        return SCP_ERR_UNSUPPORTED;
+    }
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) { g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e); return SCP_ERR_HIP; }
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) {
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return SCP_ERR_HIP;
+    }
+    void *ws = nullptr;
+    e = scp::scratch_address(device, &ws);
+    if (e == hipSuccess) {
+        scp::Config cfg;
+        fill_config_from(s, prob->batch, cfg);
+        // plain launches, workgroup b <-> instance b, whatever the mode setting
+        cfg.ordered = 0;
+        cfg.bucketed = 0;
+        cfg.persistent_blocks = 0;
+        const scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+        const scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
+                              sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
+        e = scp::launch_solve(cfg, P, S, workspace_at(static_cast<char *>(ws), L), nullptr,
+                              static_cast<hipStream_t>(hip_stream), nullptr);
+        if (e != hipSuccess) g_create_error = std::string("kernel launch: ") + hipGetErrorString(e);
+    } else {
+        g_create_error = std::string("scratch address: ") + hipGetErrorString(e);
+    }
+    if (cur != device) (void)hipSetDevice(cur);
+    return e == hipSuccess ? SCP_OK : SCP_ERR_HIP;
+}
+
 scp_status scp_batch_destroy(scp_batch h)
 {
     if (!h) return SCP_ERR_ARG;

@@ -18,6 +18,7 @@
 // order, so repeated runs are bitwise identical.
 #include <math.h>
 
+#include <mutex>
 #include <utility>
 
 #include "lander_model.hpp"
@@ -1786,4 +1787,28 @@ int qp_blocks_per_cu(int dtype, int kmax)
                                        : persistent_blocks<float, 1024>(&n, kmax));
     return (e == hipSuccess && n > 0) ? n : 1;
 }
+// ------------------------------------------------------------------------------------------
+// Fixed device scratch for callers that cannot allocate device memory: every allocation-free
+// solve on a device uses this one array as its workspace, so such calls that overlap on a
+// device race.  Each device holds its own copy, at its own address.
+// ------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+hipError_t scratch_address(int device, void **out)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
 }  // namespace scp

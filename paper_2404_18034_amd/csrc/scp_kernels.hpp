@@ -132,4 +132,13 @@ size_t qp_smem_bytes(int kmax, size_t rsize);
 // Resident workgroups per compute unit of the persistent subproblem kernel (occupancy query).
 int qp_blocks_per_cu(int dtype, int kmax);
 
+// Bytes of the library's fixed device scratch array (the workspace of the allocation-free
+// solve).
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+
+// Device address of the fixed scratch array on `device`, which must be the current device.
+// Looked up once per device (the array's name is a host-side stand-in, not an address) and
+// kept until the process ends.
+hipError_t scratch_address(int device, void **out);
+
 }  // namespace scp
