@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed issue)
+NX = 15                           # state entries per node
 WORKLOAD = "C4"
 WORKLOAD_NAMES = {
     "C1": "Monte Carlo 1,024 x K=20, 15 SCP x 1,000 PIPG iterations, seeded dispersions (seed 1)",
@@ -33,17 +34,21 @@ WORKLOAD_NAMES = {
     "C4": "throughput 65,536 x K=30, 15 SCP x 1,000 PIPG iterations, J and r_T dispersed (seed 4)",
     "F1": "paper's Monte Carlo: 256 runs, r0 ~ U(6,9) x U(3,6) x U(1,2), K=30, at most 25 SCP x "
           "2,500 PIPG iterations, SCP early exit (seed 5)",
+    "F2": "paper's Monte Carlo with the reaction-control torque (n_u = 7): 256 runs, r0 ~ "
+          "U(6,9) x U(3,6) x U(1,2), K=30, at most 25 SCP x 2,500 PIPG iterations, SCP early "
+          "exit (seed 5)",
 }
 SWEEP_SIZES = (1, 4, 16, 64, 256, 1024, 4096, 16384, 65536)
 
 
-def pipg_flops_per_iter(K):
-    """Algorithmic flops of one PIPG_custom iteration of one instance with K nodes: the
-    block products A^-_k, B^-_k, B^+_k and their transposes (A^-_k has 196 free entries: its
-    mass row and y column are fixed), plus the vector updates of the primal/dual steps and
-    the extrapolation."""
+def pipg_flops_per_iter(K, n_u=4):
+    """Algorithmic flops of one PIPG_custom iteration of one instance with K nodes and n_u
+    controls per node: the block products A^-_k, B^-_k, B^+_k and their transposes (A^-_k has
+    196 free entries: its mass row and y column are fixed; B^-_k and B^+_k 15 n_u each), 2
+    flops per multiply-add, plus the vector updates of the primal/dual steps and the
+    extrapolation (428 flops per interval, 9 per state or control entry of a node)."""
     M = K - 1
-    return M * (4 * 316 + 428) + 171 * K
+    return M * (4 * (196 + 30 * n_u) + 428) + 9 * (NX + n_u) * K
 
 
 KERNEL_SOURCES = ("paper_2404_18034_amd/csrc/scp_kernels.hip",
@@ -293,11 +298,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1", "F2"],
                     help="C4 (default): the 65,536 x K=30 throughput Monte Carlo, the largest "
                          "single-GPU configuration of the metric's 1k-64k range; C1 (1,024 x "
-                         "K=20), C2 (16,384 uneven K, early exit) and F1 (the paper's 256-run "
-                         "Monte Carlo) for reference")
+                         "K=20), C2 (16,384 uneven K, early exit), F1 (the paper's 256-run "
+                         "Monte Carlo) and F2 (the same with the torque control) for reference")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed solves of the same workload on the FP64 path (0: skip)")
     ap.add_argument("--grad", action="store_true",
@@ -395,7 +400,7 @@ def main():
     sub_launches = per["subproblem"][1] / nprof
     Ks = inst["K"].astype(np.int64)
     flops_per_solve = float(np.sum(pipg_iters.astype(np.float64) *
-                                   np.array([pipg_flops_per_iter(k) for k in Ks])))
+                                   np.array([pipg_flops_per_iter(k, solver.n_u) for k in Ks])))
     achieved = flops_per_solve / (sub_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
@@ -419,6 +424,7 @@ def main():
                    "early_exit": bool(cfg["early_exit"]), "node_projections": cfg["node_projections"],
                    "scalar_dilation": bool(args.scalar_dilation),
                    "power_iteration": "f32" if cfg.get("power_fp32", 0) else "f64",
+                   "n_u": solver.n_u,
                    "mode": solver.mode(), "parallelism": "single GPU"},
         "converged": converged, "solves_per_s_all": round(B / (ms_per_step * 1e-3), 2),
         "roofline": roofline,

@@ -12,7 +12,9 @@
  * Conventions
  *   state   x = (m, r[3], v[3], q[4], w[3], y)  n_x = 15, q a Hamilton quaternion, scalar
  *           first, body to inertial; y the CTCS constraint-violation integrator.
- *   control u = (T[3], s)                         n_u = 4, T body-frame thrust, s dilation.
+ *   control u = (T[3], s)                         n_u = 4, T body-frame thrust, s dilation;
+ *           or u = (T[3], gamma[3], s)            n_u = 7 with the reaction-control torque
+ *           gamma (body frame) of the paper's full control set (scp_settings.n_u).
  *   "real"  is float when scp_settings.dtype == SCP_F32 and double when SCP_F64.
  *   All arrays are dense, row-major, device-resident (allocated by the caller on the
  *   device the handle was created for), and 16-byte aligned.
@@ -116,6 +118,13 @@ typedef struct {
                                    ignored (the FP32 variant is bounded to six waves per
                                    SIMD) and scp_batch_autotune times modes 1, 2 and 4
                                    only (the other entries of ms_out stay -1)             */
+    int32_t n_u;                /* controls per node: 4 = (T, s); 7 = (T, gamma, s), the
+                                   reaction-control torque gamma of section "6-DoF Powered
+                                   Descent Guidance" adding J^-1 gamma to w_dot and the
+                                   path constraint ||gamma||^2 <= gamma_max^2 (params
+                                   column 23) to the CTCS integrand.  With 7: not with
+                                   scalar_dilation or grad_pipg_steps > 0
+                                   (SCP_ERR_UNSUPPORTED)                                  */
     int32_t power_fp32;         /* precision of the customized power iteration (Algorithm
                                    "Customized power iteration") on the FP32 path: 0 = the
                                    iterate and the block products in FP64 over the FP32
@@ -127,21 +136,24 @@ typedef struct {
     double pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
-    double px[15], pu[4];
+    double px[15], pu[7];       /* pu: the first n_u entries are read                       */
 } scp_settings;
 
-/* A batch of B problems.  params columns: m_wet, m_dry, alpha_mdot, g[3], J_diag[3],
+/* A batch of B problems.  params columns (24): m_wet, m_dry, alpha_mdot, g[3], J_diag[3],
  * r_T[3], T_min, T_max, delta_max, gamma_gs, theta_max, omega_max, s_min, s_max, eps_ctcs,
- * s_init, v_max (angles in radians; v_max = +inf for no speed bound, otherwise the path
- * constraint ||v||^2 <= v_max^2 of section "6-DoF Powered Descent Guidance" joins the CTCS
- * integrand).  x0 is the initial state (its y entry is ignored: y(0) = 0);
+ * s_init, v_max, gamma_max (angles in radians; v_max = +inf for no speed bound, otherwise the
+ * path constraint ||v||^2 <= v_max^2 of section "6-DoF Powered Descent Guidance" joins the
+ * CTCS integrand; gamma_max bounds the torque likewise and is read only with n_u = 7, +inf
+ * for no bound).  x0 is the initial state (its y entry is ignored: y(0) = 0);
  * xf = (r, v, q, w) is the landing condition, of which r, v, the tilt part (q2, q3) of q and
- * w are imposed.  An instance whose K is outside [2, k_max] is not solved (status 3). */
+ * the transverse rates (w2, w3) are imposed (the roll angle and rate are free: thrust alone
+ * exerts no torque about the thrust axis).  An instance whose K is outside [2, k_max] is not
+ * solved (status 3). */
 typedef struct {
     int32_t batch;              /* B >= 0                                                  */
     const void *x0;             /* real [B][15]                                            */
     const void *xf;             /* real [B][13]                                            */
-    const void *params;         /* real [B][23]                                            */
+    const void *params;         /* real [B][24]                                            */
     const int32_t *K;           /* int32 [B] node counts                                   */
 } scp_problem;
 
@@ -150,7 +162,7 @@ typedef struct {
  * frozen, the others are unaffected), 3 invalid instance (K out of range). */
 typedef struct {
     void *x;                    /* real [B][k_max][15]                                     */
-    void *u;                    /* real [B][k_max][4]                                      */
+    void *u;                    /* real [B][k_max][n_u]                                    */
     void *t_f;                  /* real [B] time of flight = integral of s                 */
     void *m_f;                  /* real [B] final mass                                     */
     int32_t *status;            /* int32 [B]                                               */
@@ -221,7 +233,7 @@ scp_status scp_batch_mode(scp_batch h, int32_t *mode_out, int32_t *occupancy_out
  * the handle's dtype. */
 typedef struct {
     void *xbar;                 /* real [B][k_max][15]                                     */
-    void *ubar;                 /* real [B][k_max][4]                                      */
+    void *ubar;                 /* real [B][k_max][4] (n_u = 4)                            */
     void *mup, *mum, *phi;      /* real [B][k_max-1][15]                                   */
     void *th;                   /* real [B][k_max-1]                                       */
     double *sigma;              /* f64  [B]                                                */

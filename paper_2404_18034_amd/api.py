@@ -11,6 +11,7 @@ import os
 import numpy as np
 
 NX, NU, NP, NXF = 15, 4, 24, 13
+NU_MAX = 7  # controls with the reaction-control torque: (T, gamma, s)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscp_batch.so")
 
@@ -47,13 +48,14 @@ class Settings(ctypes.Structure):
         ("node_projections", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("grad_pipg_steps", ctypes.c_int32), ("grad_ckpt_every", ctypes.c_int32),
         ("occupancy", ctypes.c_int32), ("grad_rk4_tangent", ctypes.c_int32),
-        ("scalar_dilation", ctypes.c_int32), ("power_fp32", ctypes.c_int32),
+        ("scalar_dilation", ctypes.c_int32), ("n_u", ctypes.c_int32),
+        ("power_fp32", ctypes.c_int32),
         ("scp_tol", ctypes.c_double), ("feas_tol", ctypes.c_double),
         ("pipg_eps_abs", ctypes.c_double), ("pipg_eps_rel", ctypes.c_double),
         ("power_eps_abs", ctypes.c_double), ("power_eps_rel", ctypes.c_double),
         ("power_buff", ctypes.c_double), ("w_cost", ctypes.c_double),
         ("w_prox", ctypes.c_double), ("w_ep", ctypes.c_double), ("omega", ctypes.c_double),
-        ("rho", ctypes.c_double), ("px", ctypes.c_double * NX), ("pu", ctypes.c_double * NU),
+        ("rho", ctypes.c_double), ("px", ctypes.c_double * NX), ("pu", ctypes.c_double * NU_MAX),
     ]
 
 
@@ -151,6 +153,7 @@ def make_settings(cfg, dtype="f32", k_max=None, max_batch=0):
     s.grad_rk4_tangent = int(cfg.get("grad_rk4_tangent", 1))
     s.scalar_dilation = int(cfg.get("scalar_dilation", 0))
     s.power_fp32 = int(cfg.get("power_fp32", 0))
+    s.n_u = int(cfg.get("n_u", NU))
     s.grad_pipg_steps = int(cfg.get("grad_pipg_steps", 0))
     s.grad_ckpt_every = int(cfg.get("grad_ckpt_every", 0))
     for name in ("scp_tol", "feas_tol", "pipg_eps_abs", "pipg_eps_rel", "power_eps_abs",
@@ -179,6 +182,7 @@ class BatchSolver:
         self.settings = make_settings(cfg, dtype, k_max, max_batch)
         self.dtype = torch.float64 if self.settings.dtype == SCP_F64 else torch.float32
         self.k_max, self.max_batch, self.device = int(k_max), int(max_batch), int(device)
+        self.n_u = int(self.settings.n_u)
         nbytes = workspace_bytes(self.settings)
         if nbytes == 0:
             raise ScpError(1, "invalid settings")
@@ -216,7 +220,7 @@ class BatchSolver:
         dev = "cuda:%d" % self.device
         return dict(
             x=t.empty((B, self.k_max, NX), dtype=self.dtype, device=dev),
-            u=t.empty((B, self.k_max, NU), dtype=self.dtype, device=dev),
+            u=t.empty((B, self.k_max, self.n_u), dtype=self.dtype, device=dev),
             t_f=t.empty(B, dtype=self.dtype, device=dev),
             m_f=t.empty(B, dtype=self.dtype, device=dev),
             status=t.empty(B, dtype=t.int32, device=dev),
@@ -281,9 +285,23 @@ class BatchSolver:
         if tuple(v.shape) != tuple(shape) or v.dtype != dtype or not v.is_contiguous():
             raise ScpError(2, "%s must be a contiguous %s tensor of shape %s" % (name, dtype, shape))
 
+    def _check_solution(self, sol, B):
+        t = self.torch
+        for k, tail, dtype in (("x", (self.k_max, NX), self.dtype),
+                               ("u", (self.k_max, self.n_u), self.dtype),
+                               ("t_f", (), self.dtype), ("m_f", (), self.dtype),
+                               ("status", (), t.int32), ("scp_iters", (), t.int32),
+                               ("pipg_iters", (), t.int32), ("defect_inf", (), t.float64),
+                               ("ctcs_viol", (), t.float64), ("objective", (), t.float64)):
+            v = sol[k]
+            if (v.dim() != 1 + len(tail) or v.shape[0] < B or tuple(v.shape[1:]) != tail
+                    or v.dtype != dtype or not v.is_contiguous()):
+                raise ScpError(2, "solution array %s must be a contiguous %s tensor of shape "
+                                  "(>= %d,) + %s" % (k, dtype, B, tail))
+
     def solve_into(self, prob, sol):
         """Enqueue a solve of device problem tensors into preallocated solution tensors."""
-        self._check_problem(prob)
+        self._check_solution(sol, self._check_problem(prob))
         p, s = self._structs(prob, sol)
         self._check(load().scp_batch_solve(self.handle, ctypes.byref(p), ctypes.byref(s)))
         return sol

@@ -10,7 +10,8 @@
 namespace scp {
 
 constexpr int NX = 15;
-constexpr int NU = 4;
+constexpr int NU = 4;      // controls (T, s); the full control set adds the torque (NU_MAX)
+constexpr int NU_MAX = 7;  // (T, gamma, s) with the reaction-control torque gamma
 constexpr int NP = 24;
 constexpr int NXF = 13;
 constexpr int IY = 14;
@@ -23,6 +24,8 @@ struct Vehicle {
     R sec_delta, tan_gamma, tilt_c, w_max2;
     R v_max2;       // squared speed bound (used when has_vmax)
     bool has_vmax;  // v_max finite: the speed row joins the path constraints
+    R g_max2;       // squared torque bound (used when has_gmax, full control set only)
+    bool has_gmax;
 };
 
 template <typename R>
@@ -46,19 +49,24 @@ __device__ __forceinline__ Vehicle<R> load_vehicle(const R *p)
     v.w_max2 = p[17] * p[17];
     v.has_vmax = isfinite(double(p[22]));
     v.v_max2 = v.has_vmax ? p[22] * p[22] : R(0);
+    v.has_gmax = isfinite(double(p[23]));
+    v.g_max2 = v.has_gmax ? p[23] * p[23] : R(0);
     return v;
 }
 
 // f(x,u) and its derivative along (dx, du).  `want_d` = false skips the derivative.
-// The y entry of f is returned in double: it feeds the CTCS accumulator.
-template <typename R, bool WantD>
+// The y entry of f is returned in double: it feeds the CTCS accumulator.  NUC controls: 4
+// (T, s) or 7 (T, gamma, s), the torque gamma adding J^-1 gamma to w_dot and the row
+// ||gamma||^2 - gamma_max^2 to the path constraints.
+template <typename R, bool WantD, int NUC = NU>
 __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *u, const R *dx,
                                       const R *du, R *f, double &fy, R *df)
 {
+    static_assert(NUC == NU || NUC == NU_MAX, "4 or 7 controls");
     const R m = x[0];
     const R q0 = x[7], q1 = x[8], q2 = x[9], q3 = x[10];
     const R w0 = x[11], w1 = x[12], w2 = x[13];
-    const R T0 = u[0], T1 = u[1], T2 = u[2], s = u[3];
+    const R T0 = u[0], T1 = u[1], T2 = u[2], s = u[NUC - 1];
 
     // rotation C(q) (body -> inertial) applied to T
     const R C00 = q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3;
@@ -95,11 +103,13 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     F[11] = V.Jinv[0] * ((V.rT[1] * T2 - V.rT[2] * T1) - (w1 * Jw2 - w2 * Jw1));
     F[12] = V.Jinv[1] * ((V.rT[2] * T0 - V.rT[0] * T2) - (w2 * Jw0 - w0 * Jw2));
     F[13] = V.Jinv[2] * ((V.rT[0] * T1 - V.rT[1] * T0) - (w0 * Jw1 - w1 * Jw0));
+    if constexpr (NUC == NU_MAX)
+        for (int i = 0; i < 3; ++i) F[11 + i] += V.Jinv[i] * u[3 + i];
 
     // path constraints g (mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed; the
     // speed row is the constant -1 without a speed bound)
     const R lat = sqrt(x[2] * x[2] + x[3] * x[3]);
-    R g[8];
+    R g[9];
     g[0] = V.m_dry - m;
     g[1] = V.tan_gamma * lat - x[1];
     g[2] = R(2) * (q2 * q2 + q3 * q3) - V.tilt_c;
@@ -108,10 +118,14 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     g[5] = Tn - V.T_max;
     g[6] = V.T_min - Tn;
     g[7] = V.has_vmax ? x[4] * x[4] + x[5] * x[5] + x[6] * x[6] - V.v_max2 : R(-1);
-    R gp[8];
+    g[8] = (NUC == NU_MAX && V.has_gmax)
+               ? u[3] * u[3] + u[4 % NUC] * u[4 % NUC] + u[5 % NUC] * u[5 % NUC] - V.g_max2
+               : R(-1);
+    constexpr int NGC = NUC == NU_MAX ? 9 : 8;  // the torque row is -1 without the torque
+    R gp[9];
     R Fy = R(0);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NGC; ++i) {
         gp[i] = g[i] > R(0) ? g[i] : R(0);
         Fy += gp[i] * gp[i];
     }
@@ -122,7 +136,7 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
 
     if (!WantD) return;
 
-    const R ds = du[3];
+    const R ds = du[NUC - 1];
     const R dT0 = du[0], dT1 = du[1], dT2 = du[2];
     const R dq0 = dx[7], dq1 = dx[8], dq2 = dx[9], dq3 = dx[10];
     const R dw0 = dx[11], dw1 = dx[12], dw2 = dx[13];
@@ -164,7 +178,9 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
                           (dw2 * Jw0 + w2 * dJw0 - dw0 * Jw2 - w0 * dJw2));
     dF[13] = V.Jinv[2] * ((V.rT[0] * dT1 - V.rT[1] * dT0) -
                           (dw0 * Jw1 + w0 * dJw1 - dw1 * Jw0 - w1 * dJw0));
-    R dg[8];
+    if constexpr (NUC == NU_MAX)
+        for (int i = 0; i < 3; ++i) dF[11 + i] += V.Jinv[i] * du[3 + i];
+    R dg[9];
     dg[0] = -dm;
     dg[1] = (lat > R(NORM_EPS) ? V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]) / lat : R(0)) - dx[1];
     dg[2] = R(4) * (q2 * dq2 + q3 * dq3);
@@ -173,9 +189,11 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     dg[5] = dTn;
     dg[6] = -dTn;
     dg[7] = V.has_vmax ? R(2) * (x[4] * dx[4] + x[5] * dx[5] + x[6] * dx[6]) : R(0);
+    if constexpr (NUC == NU_MAX)
+        dg[8] = V.has_gmax ? R(2) * (u[3] * du[3] + u[4] * du[4] + u[5] * du[5]) : R(0);
     R dFy = R(0);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) dFy += R(2) * gp[i] * dg[i];
+    for (int i = 0; i < NGC; ++i) dFy += R(2) * gp[i] * dg[i];
 #pragma unroll
     for (int i = 0; i < 14; ++i) df[i] = ds * F[i] + s * dF[i];
     df[IY] = ds * Fy + s * dFy;

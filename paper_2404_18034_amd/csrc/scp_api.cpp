@@ -49,6 +49,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
     if (s->grad_rk4_tangent != 0 && s->grad_rk4_tangent != 1) { why = "grad_rk4_tangent must be 0 or 1"; return false; }
     if (s->scalar_dilation != 0 && s->scalar_dilation != 1) { why = "scalar_dilation must be 0 or 1"; return false; }
     if (s->power_fp32 != 0 && s->power_fp32 != 1) { why = "power_fp32 must be 0 or 1"; return false; }
+    if (s->n_u != 4 && s->n_u != 7) { why = "n_u must be 4 (thrust, dilation) or 7 (with the torque)"; return false; }
     if (!(s->w_prox > 0.0) || !(s->omega > 0.0) || !(s->rho > 0.0) || !(s->rho < 2.0) ||
         !(s->w_ep >= 0.0) || !isfinite(s->w_cost)) {
         why = "weights out of range (w_prox > 0, omega > 0, 0 < rho < 2, w_ep >= 0)";
@@ -56,7 +57,7 @@ bool settings_ok(const scp_settings *s, std::string &why)
     }
     for (int i = 0; i < 15; ++i)
         if (!(s->px[i] > 0.0) || !isfinite(s->px[i])) { why = "px entries must be > 0"; return false; }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < s->n_u; ++i)
         if (!(s->pu[i] > 0.0) || !isfinite(s->pu[i])) { why = "pu entries must be > 0"; return false; }
     if (s->grad_pipg_steps < 0 ||
         (s->grad_pipg_steps > 0 &&
@@ -85,7 +86,7 @@ Layout layout_of(const scp_settings *s)
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-    L.blocks = take(B * M * 23 * 16 * rs);
+    L.blocks = take(B * M * (size_t)(15 + 2 * s->n_u) * 16 * rs);
     L.what = take(B * M * 16 * rs);
     L.dy = take(B * M * 8);
     L.mup = take(B * M * 16 * rs);
@@ -190,6 +191,11 @@ scp_status scp_batch_create(const scp_settings *settings, int device, void *hip_
         g_create_error = "scalar_dilation is not implemented with mode 3 or with gradients";
         return SCP_ERR_UNSUPPORTED;
     }
+    if (settings->n_u == 7 && (settings->scalar_dilation || settings->grad_pipg_steps > 0)) {
+        g_create_error = "the torque input (n_u = 7) is not implemented with scalar_dilation or "
+                         "with gradients";
+        return SCP_ERR_UNSUPPORTED;
+    }
     const Layout L = layout_of(settings);
     if (!workspace || workspace_bytes < L.total) {
         g_create_error = "workspace missing or smaller than scp_batch_workspace_bytes()";
@@ -282,6 +288,7 @@ static void fill_config_from(const scp_settings &s, int batch, scp::Config &cfg)
     cfg.grad_rk4_tangent = s.grad_rk4_tangent;
     cfg.scalar_dilation = s.scalar_dilation;
     cfg.power_fp32 = s.power_fp32;
+    cfg.nu = s.n_u;
     cfg.scp_tol = s.scp_tol;
     cfg.feas_tol = s.feas_tol;
     cfg.pipg_eps_abs = s.pipg_eps_abs;
@@ -381,7 +388,8 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
             hipDeviceProp_t prop;
             e = hipGetDeviceProperties(&prop, h->device);
             if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
-            h->persistent_grid = prop.multiProcessorCount * scp::qp_blocks_per_cu(cfg.dtype, h->st.k_max);
+            h->persistent_grid =
+                prop.multiProcessorCount * scp::qp_blocks_per_cu(cfg.dtype, h->st.k_max, h->st.n_u);
         }
         cfg.persistent_blocks = h->persistent_grid;
     }
@@ -562,7 +570,8 @@ static std::string tune_key(scp_batch h, int batch)
     std::ostringstream k;
     k << arch << ":kmax=" << h->st.k_max << ":dtype=" << (h->st.dtype == SCP_F64 ? "f64" : "f32")
       << ":early_exit=" << h->st.early_exit << ":proj=" << h->st.node_projections
-      << ":sd=" << h->st.scalar_dilation << ":pw32=" << h->st.power_fp32 << ":batch=" << batch;
+      << ":sd=" << h->st.scalar_dilation << ":pw32=" << h->st.power_fp32 << ":nu=" << h->st.n_u
+      << ":batch=" << batch;
     return k.str();
 }
 
@@ -718,8 +727,8 @@ scp_status scp_batch_select_best(scp_batch h, const scp_solution *sol, int32_t p
                           sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
     const scp::Solution O{out->x, out->u, out->t_f, out->m_f, out->status, out->scp_iters,
                           out->pipg_iters, out->defect_inf, out->ctcs_viol, out->objective};
-    e = scp::launch_select_best(h->st.dtype == SCP_F64 ? 1 : 0, h->st.k_max, S, O, problems,
-                                starts, best, h->stream);
+    e = scp::launch_select_best(h->st.dtype == SCP_F64 ? 1 : 0, h->st.k_max, h->st.n_u, S, O,
+                                problems, starts, best, h->stream);
     if (cur != h->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SCP_OK;
@@ -733,6 +742,10 @@ scp_status scp_batch_solve_noalloc(const scp_settings *settings, int device, voi
     g_create_error.clear();
     std::string why;
     if (!settings_ok(settings, why)) { g_create_error = why; return SCP_ERR_ARG; }
+    if (settings->n_u == 7 && settings->scalar_dilation) {
+        g_create_error = "the torque input (n_u = 7) is not implemented with scalar_dilation";
+        return SCP_ERR_UNSUPPORTED;
+    }
     if (!prob || !sol) { g_create_error = "problem or solution is NULL"; return SCP_ERR_ARG; }
     if (prob->batch < 0 || prob->batch > settings->max_batch) {
         g_create_error = "batch must be in [0, max_batch]";

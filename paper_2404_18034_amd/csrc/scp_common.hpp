@@ -7,9 +7,16 @@
 
 namespace scp {
 
-constexpr int COLS = 23;         // columns of [A^- | B^- | B^+]
 constexpr int CST = 16;          // stride of one column (15 rows + pad)
-constexpr int BLK = COLS * CST;  // entries per interval
+// Block layout of one interval for NUC controls: the columns of [A^- | B^- | B^+], each
+// stored with stride CST
+template <int NUC>
+struct Blk {
+    static constexpr int COLS = NX + 2 * NUC;  // 23 with (T, s), 29 with the torque
+    static constexpr int SIZE = COLS * CST;     // entries per interval
+};
+constexpr int COLS = Blk<NU>::COLS;  // thrust-and-dilation layout (the gradient kernels)
+constexpr int BLK = Blk<NU>::SIZE;
 constexpr int VST = 20;          // node stride of (x, u) vectors in LDS (15 + 4 + pad)
 constexpr int DST = 16;          // interval stride of dual vectors
 

@@ -36,7 +36,7 @@ struct Args {
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
-    double px[NX], pu[NU];
+    double px[NX], pu[NU_MAX];
     const R *x0, *xf, *params;
     const int32_t *K;
     R *x, *u, *t_f, *m_f;
@@ -65,7 +65,7 @@ struct Args {
 // Initial guess (straight-line interpolation of r, v, w, normalized interpolation of q,
 // constant mass, hover thrust along the body axis, s = s_init) and state reset.
 // ------------------------------------------------------------------------------------------
-template <typename R>
+template <typename R, int NUC = NU>
 __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
 {
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
     const int K = a.K[b];
     const bool valid = K >= 2 && K <= a.kmax;
     R *x = a.x + ((long)b * a.kmax + k) * NX;
-    R *u = a.u + ((long)b * a.kmax + k) * NU;
+    R *u = a.u + ((long)b * a.kmax + k) * NUC;
     if (k < a.kmax - 1) {
         const long o = ((long)b * (a.kmax - 1) + k) * DST;
         for (int i = 0; i < DST; ++i) a.mup[o + i] = a.mum[o + i] = a.phi[o + i] = R(0);
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
     }
     if (!valid || k >= K) {
         for (int i = 0; i < NX; ++i) x[i] = R(0);
-        for (int i = 0; i < NU; ++i) u[i] = R(0);
+        for (int i = 0; i < NUC; ++i) u[i] = R(0);
         return;
     }
     const R *x0 = a.x0 + (long)b * NX, *xf = a.xf + (long)b * NXF, *p = a.params + (long)b * NP;
@@ -115,10 +115,9 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
     xd[IY] = 0.0;
     for (int i = 0; i < NX; ++i) x[i] = R(xd[i]);
     const double g0 = p[3], g1 = p[4], g2 = p[5];
+    for (int i = 1; i < NUC - 1; ++i) u[i] = R(0);  // the torque guess is zero
     u[0] = R(double(x0[0]) * sqrt(g0 * g0 + g1 * g1 + g2 * g2));
-    u[1] = R(0);
-    u[2] = R(0);
-    u[3] = p[21];
+    u[NUC - 1] = p[21];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -126,9 +125,10 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
 // interval k with rk4_substeps RK4 steps; every lane of an interval integrates the same x
 // (identical instruction stream, so identical bits).
 // ------------------------------------------------------------------------------------------
-template <typename R>
+template <typename R, int NUC = NU>
 __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blocks)
 {
+    constexpr int COLS = Blk<NUC>::COLS, BLK = Blk<NUC>::SIZE;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long per_b = (long)(a.kmax - 1) * COLS;
     const int b = (int)(gid / per_b);
@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const Vehicle<R> V = load_vehicle<R>(p);
     const R *xk = a.x + ((long)b * a.kmax + k) * NX;
     const R *xk1 = xk + NX;
-    const R *uk = a.u + ((long)b * a.kmax + k) * NU;
-    const R *uk1 = uk + NU;
+    const R *uk = a.u + ((long)b * a.kmax + k) * NUC;
+    const R *uk1 = uk + NUC;
 
     // the state is accumulated in double (the model and the variational columns run in R),
     // which keeps the propagated endpoint -- and so the defect w^_k -- free of R-rounding
@@ -155,14 +155,14 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
         x[i] = double(xk[i]);
         col[i] = (c < NX && i == c) ? R(1) : R(0);
     }
-    R ua[NU], ub[NU];
-    for (int i = 0; i < NU; ++i) {
+    R ua[NUC], ub[NUC];
+    for (int i = 0; i < NUC; ++i) {
         ua[i] = uk[i];
         ub[i] = uk1[i];
     }
     // direction of the control perturbation: e_j scaled by lambda- (B- columns) or lambda+
-    const int uj = c < NX ? -1 : (c - NX) % NU;
-    const bool plus = c >= NX + NU;
+    const int uj = c < NX ? -1 : (c - NX) % NUC;
+    const bool plus = c >= NX + NUC;
 
     const R dtau = R(1.0 / double(K - 1));
     const int nsub = a.rk4_substeps;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const double hd = double(h), hhd = double(hh), h6d = double(h6);
 
     double xs[NX], accx[NX];
-    R xin[NX], cs[NX], accc[NX], fx[NX], fc[NX], u[NU], du[NU];
+    R xin[NX], cs[NX], accc[NX], fx[NX], fc[NX], u[NUC], du[NUC];
     double fy;
 
     for (int n = 0; n < nsub; ++n) {
@@ -180,13 +180,13 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
         for (int st = 0; st < 4; ++st) {
             const R sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
             const R lp = sg / dtau, lm = R(1) - lp;
-            for (int i = 0; i < NU; ++i) {
+            for (int i = 0; i < NUC; ++i) {
                 u[i] = lm * ua[i] + lp * ub[i];
                 du[i] = (i == uj) ? (plus ? lp : lm) : R(0);
             }
             for (int i = 0; i < NX; ++i) xin[i] = R(st == 0 ? x[i] : xs[i]);
             const R *cin = st == 0 ? col : cs;
-            f_jvp<R, true>(V, xin, u, cin, du, fx, fy, fc);
+            f_jvp<R, true, NUC>(V, xin, u, cin, du, fx, fy, fc);
             fx[IY] = R(0);  // y is advanced with the double-precision fy below
             if (st == 0) {
                 for (int i = 0; i < IY; ++i) accx[i] = double(fx[i]);
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const long ib = (long)b * (a.kmax - 1) + k;
     if (need_blocks) {
         R *dst = a.blocks + ib * BLK + c * CST;
-        const double pc = c < NX ? a.px[c] : a.pu[(c - NX) % NU];
+        const double pc = c < NX ? a.px[c] : a.pu[(c - NX) % NUC];
         for (int i = 0; i < NX; ++i) dst[i] = R(double(col[i]) * pc / a.px[i]);
         dst[NX] = R(0);
     }
@@ -724,10 +724,11 @@ __device__ __forceinline__ double wave_sum(R v)
 // power-iteration blocks) do not count against the register budget of the PIPG iteration.
 // ------------------------------------------------------------------------------------------
 // P: precision of the power iteration (iterate and block products); FP64 unless the FP32
-// variant is selected on the FP32 path.
-template <typename R, typename P, int MAXT>
+// variant is selected on the FP32 path.  NUC: controls per node (4, or 7 with the torque).
+template <typename R, typename P, int MAXT, int NUC = NU>
 __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsigned char *smem_raw)
 {
+    constexpr int BLK = Blk<NUC>::SIZE;
     if (b >= a.B) return;
     if (a.status[b] >= 0) return;  // uniform over the workgroup
     const int K = a.K[b], M = K - 1, kmax = a.kmax;
@@ -742,7 +743,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     const bool isx = node && i < NX;       // lane holds a state variable
     const bool dual = k < M && i < NX;     // lane holds a dynamics row
     const long xoff = ((long)b * kmax + (node ? k : 0)) * NX;
-    const long uoff = ((long)b * kmax + (node ? k : 0)) * NU;
+    const long uoff = ((long)b * kmax + (node ? k : 0)) * NUC;
     const R *p = a.params + (long)b * NP;
 
     // -------------------- convergence test of the current reference --------------------
@@ -758,7 +759,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             if (!isfinite(e)) sm[1] = 1.0;
         }
         if (isx && !isfinite(double(a.x[xoff + i]))) sm[1] = 1.0;
-        if (node && i < NU && !isfinite(double(a.u[uoff + i]))) sm[1] = 1.0;
+        if (node && i < NUC && !isfinite(double(a.u[uoff + i]))) sm[1] = 1.0;
         block_reduce<2, true>(mx, red);
         block_reduce<2, false>(sm, red);
         const double d = mx[0], c = mx[1];
@@ -780,8 +781,8 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
                 const double dtau = 1.0 / M;
                 for (int q = 0; q < M; ++q)
                     tf += dtau * 0.5 *
-                          (double(a.u[((long)b * kmax + q) * NU + 3]) +
-                           double(a.u[((long)b * kmax + q + 1) * NU + 3]));
+                          (double(a.u[((long)b * kmax + q) * NUC + NUC - 1]) +
+                           double(a.u[((long)b * kmax + q + 1) * NUC + NUC - 1]));
                 a.t_f[b] = R(tf);
                 a.m_f[b] = R(mN);
             }
@@ -791,7 +792,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
 
     // -------------------- load the subproblem's blocks --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
-    R rowA[NX], rowBm[NU], rowBp[NU], rowBq[NU];
+    R rowA[NX], rowBm[NUC], rowBp[NUC], rowBq[NUC];
     ColStore<R> colA{reinterpret_cast<R *>(smem_raw + Lds::BYTES) + t * ColStore<R>::LDS_STRIDE};
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
     // (forward product); rowBq: row i of B^+_{k-1} (control part of the transposed product)
@@ -799,11 +800,29 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
         colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
         rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
     }
-    for (int q = 0; q < NU; ++q) {
+    for (int q = 0; q < NUC; ++q) {
         rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
-        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
-        rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
+        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NUC + q) * CST + i] : R(0);
+        rowBq[q] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NUC + q) * CST + i]
                                              : R(0);
+    }
+    // with the torque (NUC = 7) the controls of node k sit as in the subproblem kernel: lane i
+    // holds component ci = (i & 3) + 4 (i >> 3) (component 7 is padding), read copies on lanes
+    // 4..7 (components 0..3) and 8..10 (4..6); the transposed product gathers them by two
+    // interleaved reduce-scatters, whose addends are the B entries in exchange order
+    const int ci = (i & 3) + ((i >> 3) << 2);
+    const bool uval = node && (NUC == NU || ci < NUC);  // lane holds a control component
+    R rowBmXA[4], rowBqXA[4], rowBmXB[4], rowBqXB[4];
+    if constexpr (NUC == NU_MAX) {
+        for (int s = 0; s < 4; ++s) {
+            const int qa = xpermi(i, s), qb = 4 + xpermi(i, s);
+            const bool bq = node && k > 0 && i < NX;
+            rowBmXA[s] = dual ? blk[(long)k * BLK + (NX + qa) * CST + i] : R(0);
+            rowBqXA[s] = bq ? blk[(long)(k - 1) * BLK + (NX + NUC + qa) * CST + i] : R(0);
+            rowBmXB[s] = (dual && qb < NUC) ? blk[(long)k * BLK + (NX + qb) * CST + i] : R(0);
+            rowBqXB[s] = (bq && qb < NUC) ? blk[(long)(k - 1) * BLK + (NX + NUC + qb) * CST + i]
+                                          : R(0);
+        }
     }
 
     // -------------------- customized power iteration --------------------
@@ -818,11 +837,11 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     // and multiplied.
     const int KR = (kmax + 3) / 4 * 4;
     const bool thlane = dual && i == IY;
-    P zx = isx ? P(1) : P(0), zu = node ? P(1) : P(0);
+    P zx = isx ? P(1) : P(0), zu = uval ? P(1) : P(0);
     P dmu = P(0);  // mu+ - mu- of this dynamics row
     double sigma;
     {
-        double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NU) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
+        double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NUC) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
         block_reduce<1, false>(acc, red);
         sigma = sqrt(acc[0]);
     }
@@ -843,6 +862,12 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             keep_narrow(rowBm);
             keep_narrow(rowBp);
             keep_narrow(rowBq);
+            if constexpr (NUC == NU_MAX) {
+                keep_narrow(rowBmXA);
+                keep_narrow(rowBqXA);
+                keep_narrow(rowBmXB);
+                keep_narrow(rowBqXB);
+            }
         }
         P ph = P(0), thv = P(0);
         if (wact) {
@@ -850,8 +875,15 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             const P zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
             P r = pw_dot<R, P, 0, 1, NX>(rowA, zx, P(0));
             r -= zxn;
-            r = pw_dot<R, P, 0, 4, NU>(rowBm, zu, r);
-            r = pw_dot<R, P, 0, 4, NU>(rowBp, zun, r);
+            if constexpr (NUC == NU) {
+                r = pw_dot<R, P, 0, 4, NU>(rowBm, zu, r);
+                r = pw_dot<R, P, 0, 4, NU>(rowBp, zun, r);
+            } else {
+                r = pw_dot<R, P, 4, 1, 4>(rowBm, zu, r);
+                r = pw_dot<R, P, 8, 1, 3>(rowBm + 4, zu, r);
+                r = pw_dot<R, P, 4, 1, 4>(rowBp, zun, r);
+                r = pw_dot<R, P, 8, 1, 3>(rowBp + 4, zun, r);
+            }
             r += dmu;
             if constexpr (sizeof(P) == 8) {
                 ph = dual ? r / sigma : 0.0;
@@ -885,12 +917,25 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             r += thm;
             zx = isx ? r : P(0);
             // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
-            P gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = P(rowBm[q]) * ph + P(rowBq[q]) * phm;
-            const P zq = row_reduce_scatter4<P>(gq, i);
-            zu = node ? zq : P(0);
+            if constexpr (NUC == NU) {
+                P gq[NU];
+                for (int q = 0; q < NU; ++q) gq[q] = P(rowBm[q]) * ph + P(rowBq[q]) * phm;
+                const P zq = row_reduce_scatter4<P>(gq, i);
+                zu = node ? zq : P(0);
+            } else {
+                P ga[4], gb[4];
+                for (int q = 0; q < 4; ++q) {
+                    ga[q] = P(rowBmXA[q]) * ph + P(rowBqXA[q]) * phm;
+                    gb[q] = P(rowBmXB[q]) * ph + P(rowBqXB[q]) * phm;
+                }
+                const P za = row_reduce_scatter4i<P>(ga), zb = row_reduce_scatter4i<P>(gb);
+                zu = uval ? (i >= 8 ? zb : za) : P(0);
+            }
             dmu = ph + ph;
-            q2 = zx * zx + (((i & 3) == 0) ? zu * zu : P(0)) + (ph * ph + ph * ph);
+            // each control component counted once: lanes 4q of the 4-copy layout, the read
+            // copies of the torque layout
+            const bool ucount = NUC == NU ? (i & 3) == 0 : (uval && (i >> 2) >= 1 && (i >> 2) <= 2);
+            q2 = zx * zx + (ucount ? zu * zu : P(0)) + (ph * ph + ph * ph);
         }
         sl[Lds::Z] = zx;
         sl[Lds::U] = zu;
@@ -916,12 +961,12 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
 }
 
 // FP32: registers bounded for five waves per SIMD (four 5-wave workgroups per CU)
-template <typename R, typename P, int MAXT>
+template <typename R, typename P, int MAXT, int NUC = NU>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 prepare_kernel(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prepare_body<R, P, MAXT>(a, blockIdx.x, smem_raw);
+    prepare_body<R, P, MAXT, NUC>(a, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -938,10 +983,16 @@ prepare_kernel(Args<R> a)
 // and so the same box).  Each wave publishes the sum of its rows' values through LDS before
 // the step's barrier; after it every lane adds the partials in wave order, so all nodes take
 // a bit-identical mean, and the s lanes finish their primal update there.
-template <typename R, int MAXT, bool FAIR = false, bool SD = false>
+// NUC: controls per node.  With the reaction-control torque (NUC = 7) lane i of a node row
+// holds control component ci = (i & 3) + 4 (i >> 3) (component 7 is padding, zero): the thrust
+// and the first torque component on lanes 0..7 (read copy 4..7, as with thrust alone), the rest
+// of the torque and the dilation on lanes 8..15 (read copy 8..10).
+template <typename R, int MAXT, bool FAIR = false, bool SD = false, int NUC = NU>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
 {
+    static_assert(NUC == NU || !SD, "one dilation value with thrust and dilation only");
+    constexpr int BLK = Blk<NUC>::SIZE;
     if (b >= a.B) return;
     if (a.status[b] >= 0) return;  // uniform over the workgroup
     const int K = a.K[b], M = K - 1, kmax = a.kmax;
@@ -968,12 +1019,12 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const bool isx = node && i < NX;       // lane holds a state variable
     const bool dual = k < M && i < NX;     // lane holds a dynamics row
     const long xoff = ((long)b * kmax + (node ? k : 0)) * NX;
-    const long uoff = ((long)b * kmax + (node ? k : 0)) * NU;
+    const long uoff = ((long)b * kmax + (node ? k : 0)) * NUC;
     const R *p = a.params + (long)b * NP;
 
     // -------------------- load the subproblem into registers --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
-    R rowA[NX], rowBm[NU], rowBp[NU];
+    R rowA[NX], rowBm[NUC], rowBp[NUC];
     ColStore<R> colA{myCol};
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
     // (forward product)
@@ -981,18 +1032,25 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
         rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
     }
-    for (int q = 0; q < NU; ++q) {
+    for (int q = 0; q < NUC; ++q) {
         rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
-        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NU + q) * CST + i] : R(0);
+        rowBp[q] = dual ? blk[(long)k * BLK + (NX + NUC + q) * CST + i] : R(0);
     }
     // coefficients of the control gradient (row i of B^-_k and of B^+_{k-1}) in this lane's
     // exchange order (see row_reduce_scatter4i): slot s holds control component xpermi(i, s)
-    R rowBmX[NU], rowBqX[NU];
-    for (int s = 0; s < NU; ++s) {
+    // (with the torque a second set for components 4 + xpermi(i, s))
+    R rowBmX[4], rowBqX[4], rowBmY[4], rowBqY[4];
+    for (int s = 0; s < 4; ++s) {
         const int q = xpermi(i, s);
+        const bool bq = node && k > 0 && i < NX;
         rowBmX[s] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
-        rowBqX[s] = (node && k > 0 && i < NX) ? blk[(long)(k - 1) * BLK + (NX + NU + q) * CST + i]
-                                              : R(0);
+        rowBqX[s] = bq ? blk[(long)(k - 1) * BLK + (NX + NUC + q) * CST + i] : R(0);
+        if constexpr (NUC == NU_MAX) {
+            const int qb = 4 + q;
+            rowBmY[s] = (dual && qb < NUC) ? blk[(long)k * BLK + (NX + qb) * CST + i] : R(0);
+            rowBqY[s] = (bq && qb < NUC) ? blk[(long)(k - 1) * BLK + (NX + NUC + qb) * CST + i]
+                                         : R(0);
+        }
     }
 
     const double sigma = a.sigma[b];  // buffered spectral estimate (preparation kernel)
@@ -1000,10 +1058,13 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // boundary values, bounds, reference values
     const R xb = isx ? a.x[xoff + i] : R(0);
     // control component of this lane (interleaved: lanes q, q+4, q+8, q+12 hold u_q; the
-    // copy on lanes 4..7 is the one the products, the projections and the outputs use)
-    const int qi = i & 3;
-    const R ubq = node ? a.u[uoff + qi] : R(0);
-    const R ub3 = node ? a.u[uoff + 3] : R(0);
+    // copy on lanes 4..7 is the one the products, the projections and the outputs use; with
+    // the torque lanes 8..15 hold components 4..7 and the copy on lanes 8..10 is read)
+    const int qi = NUC == NU ? (i & 3) : (i & 3) + ((i >> 3) << 2);
+    const bool uval = node && qi < NUC;  // lane holds a control component
+    const bool uread = uval && ((i >> 2) == 1 || (NUC == NU_MAX && (i >> 2) == 2));
+    const R ubq = uval ? a.u[uoff + qi] : R(0);
+    const R ub3 = node ? a.u[uoff + NUC - 1] : R(0);  // dilation of the reference
     bool fixed = false;
     R fixv = R(0);
     if (isx) {
@@ -1016,8 +1077,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             fixv = R((double(a.xf[(long)b * NXF + i - 1]) - double(xb)) / a.px[i]);
         }
     }
-    const R slo = R((double(p[18]) - double(ub3)) / a.pu[3]);
-    const R shi = R((double(p[19]) - double(ub3)) / a.pu[3]);
+    const R slo = R((double(p[18]) - double(ub3)) / a.pu[NUC - 1]);
+    const R shi = R((double(p[19]) - double(ub3)) / a.pu[NUC - 1]);
     R wk = R(0), epsk = R(0);
     if (dual) {
         wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
@@ -1071,7 +1132,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     }
     if (a.rec_x) {
         if (isx) a.rec_x[xoff + i] = xb;
-        if (node && i < NU) a.rec_u[uoff + i] = a.u[uoff + i];
+        if (node && i < NUC) a.rec_u[uoff + i] = a.u[uoff + i];
         if (dual) {
             const long ro = ((long)b * (kmax - 1) + k) * NX + i;
             a.rec_mup[ro] = nup;
@@ -1136,8 +1197,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     if (!isx) xlo = xhi = R(0);
     else if (fixed) xlo = xhi = fixv;
     else if (grp == 1) xlo = (mdry - xb) * ipxi;
-    if (!node) ulo = uhi = R(0);
-    else if (qi == 3) { ulo = slo; uhi = shi; }
+    if (!uval) ulo = uhi = R(0);
+    else if (qi == NUC - 1) { ulo = slo; uhi = shi; }
     // theta lives on the CTCS lane of the dynamics rows; elsewhere an infinite epsilon keeps
     // max(0, .) of its update at zero
     if (!(dual && i == IY)) epsk = INF;
@@ -1171,9 +1232,16 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         // with the coefficients in this lane's exchange order (computed while the column of
         // A^-_k is on its way from LDS)
         {
-            R gq[NU];
-            for (int q = 0; q < NU; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
-            const R gu = wprox * ut + row_reduce_scatter4i<R>(gq);
+            R gq[4];
+            for (int q = 0; q < 4; ++q) gq[q] = rowBmX[q] * vphi + rowBqX[q] * phm1;
+            R gs = row_reduce_scatter4i<R>(gq);
+            if constexpr (NUC == NU_MAX) {
+                R gy[4];
+                for (int q = 0; q < 4; ++q) gy[q] = rowBmY[q] * vphi + rowBqY[q] * phm1;
+                const R gsy = row_reduce_scatter4i<R>(gy);
+                gs = i >= 8 ? gsy : gs;
+            }
+            const R gu = wprox * ut + gs;
             un = ut - alpha * gu;
         }
         // (A^-_k)^T phi_k, column i, in two halves of the column (fewer live registers)
@@ -1223,7 +1291,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             sv += __shfl_xor(sv, 32);
             if ((t & 63) == 7) sdil[t >> 6] = sv;
         }
-        un = clampbox(un, ulo, uhi);  // rows without a node: ulo = uhi = 0
+        un = clampbox(un, ulo, uhi);  // lanes without a control: ulo = uhi = 0
         // extrapolation 2z^ - z~ and relaxation z~ += rho (z^ - z~), in place
         vx = R(2) * xn - xt;
         xt += rho * (xn - xt);
@@ -1258,6 +1326,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         r -= vnext;
         r = rowdot4c<R>(rowBm, vu, r);      // B^-_k (2u^ - u~)_k
         r = rowdot4c<R>(rowBp, vunext, r);  // B^+_k (2u^ - u~)_{k+1}
+        if constexpr (NUC == NU_MAX) {      // torque components 1, 2 and the dilation
+            r = rowdot_part<R, 8, 3>(rowBm + 4, vu, r);
+            r = rowdot_part<R, 8, 3>(rowBp + 4, vunext, r);
+        }
         // (2 mu+^ - nu+) - (2 mu-^ - nu-)
         r += R(2) * (mupn - mumn) - (nup - num);
         const R phn = vphi + beta * r;
@@ -1276,7 +1348,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         // patterns (monotone for non-negative values); the slot set alternates between tests,
         // the other set is cleared for the next one.
         if (test) {
-            const bool ucopy = (i >> 2) == 1;
+            const bool ucopy = uread;
             const R xh = sl[Lds::PX], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
             const R uh = ucopy ? sl[Lds::PU] : R(0), unr = ucopy ? un : R(0);
             const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
@@ -1324,7 +1396,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         st[0] = fabs(double(xh));
         a.x[xoff + i] = R(double(a.x[xoff + i]) + a.px[i] * double(xh));
     }
-    if (node && (i >> 2) == 1) {  // the read copy of the controls
+    if (uread) {  // the read copy of the controls
         st[0] = fmax(st[0], fabs(double(uh)));
         a.u[uoff + qi] = R(double(ubq) + a.pu[qi] * double(uh));
     }
@@ -1344,7 +1416,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 // ------------------------------------------------------------------------------------------
 
 // WPE: minimum waves per SIMD the register allocation must allow (1: no constraint).
-template <typename R, int MAXT, int WPE, bool SD = false>
+template <typename R, int MAXT, int WPE, bool SD = false, int NUC = NU>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE)))
 subproblem_kernel(Args<R> a)
 {
@@ -1367,14 +1439,14 @@ subproblem_kernel(Args<R> a)
     }
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
-    subproblem_body<R, MAXT, (WPE >= 6), SD>(a, b, smem_raw);
+    subproblem_body<R, MAXT, (WPE >= 6), SD, NUC>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
 // counter per SCP iteration, the only atomic) in the order of `order` (node count
 // descending, so the longest instances start first).  Which workgroup solves which instance
 // does not change any result.
-template <typename R, int MAXT>
+template <typename R, int MAXT, int NUC = NU>
 __global__ void __launch_bounds__(MAXT) subproblem_persistent(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1383,7 +1455,8 @@ __global__ void __launch_bounds__(MAXT) subproblem_persistent(Args<R> a)
     __syncthreads();
     int idx = s_next;
     while (idx < a.B) {
-        subproblem_body<R, MAXT>(a, __builtin_amdgcn_readfirstlane(a.order[idx]), smem_raw);
+        subproblem_body<R, MAXT, false, false, NUC>(a, __builtin_amdgcn_readfirstlane(a.order[idx]),
+                                                    smem_raw);
         __syncthreads();
         if (threadIdx.x == 0) s_next = atomicAdd(&a.queue[a.j], 1);
         __syncthreads();
@@ -1454,25 +1527,25 @@ static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
     return stage + rsize * KR * 16 * col;
 }
 
-template <typename R, typename P>
+template <typename R, typename P, int NUC = NU>
 static void launch_prepare(int maxt, int B, int threads, size_t smem, hipStream_t stream,
                            const Args<R> &a)
 {
     if (maxt == 320)
-        prepare_kernel<R, P, 320><<<dim3(B), dim3(threads), smem, stream>>>(a);
+        prepare_kernel<R, P, 320, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
     else if (maxt == 640)
-        prepare_kernel<R, P, 640><<<dim3(B), dim3(threads), smem, stream>>>(a);
+        prepare_kernel<R, P, 640, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
     else
-        prepare_kernel<R, P, 1024><<<dim3(B), dim3(threads), smem, stream>>>(a);
+        prepare_kernel<R, P, 1024, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
 
 // Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
 // to that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
-template <typename R, int MAXT>
+template <typename R, int MAXT, int NUC = NU>
 static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
                               const Args<R> &a)
 {
-    if (a.scalar_dilation) {
+    if (NUC == NU && a.scalar_dilation) {
         // one variant: FP32 bounded to six waves per SIMD (with the priority rotation), FP64
         // the compiler's choice
         subproblem_kernel<R, MAXT, (sizeof(R) == 4 ? 6 : 1), true>
@@ -1481,24 +1554,24 @@ static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hi
     }
     if constexpr (sizeof(R) == 4) {
         if (occupancy == 6) {
-            subproblem_kernel<R, MAXT, 6><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            subproblem_kernel<R, MAXT, 6, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
             return;
         }
         if (occupancy == 5) {
-            subproblem_kernel<R, MAXT, 5><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            subproblem_kernel<R, MAXT, 5, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
             return;
         }
         if constexpr (MAXT < 1024) {
             if (occupancy == 4) {
-                subproblem_kernel<R, MAXT, 4><<<dim3(B), dim3(threads), smem, stream>>>(a);
+                subproblem_kernel<R, MAXT, 4, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
                 return;
             }
         }
     }
-    subproblem_kernel<R, MAXT, 1><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    subproblem_kernel<R, MAXT, 1, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
 
-template <typename R>
+template <typename R, int NUC = NU>
 static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Solution &sol,
                                const Workspace &ws, const Record *rec, hipStream_t stream,
                                LaunchTimer *timer)
@@ -1528,7 +1601,7 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.omega = cfg.omega;
     a.rho = cfg.rho;
     for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
-    for (int i = 0; i < NU; ++i) a.pu[i] = cfg.pu[i];
+    for (int i = 0; i < NU_MAX; ++i) a.pu[i] = i < NUC ? cfg.pu[i] : 1.0;
     a.x0 = static_cast<const R *>(prob.x0);
     a.xf = static_cast<const R *>(prob.xf);
     a.params = static_cast<const R *>(prob.params);
@@ -1582,11 +1655,11 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     {
         const long n = (long)cfg.B * cfg.kmax;
         if ((e = mark(0, true)) != hipSuccess) return e;
-        init_kernel<R><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(a);
+        init_kernel<R, NUC><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(0, false)) != hipSuccess) return e;
     }
-    const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
+    const long nd = (long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS;
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
     const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
@@ -1610,26 +1683,26 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         a.j = j;
         const int need_blocks = j <= cfg.scp_iters_max ? 1 : 0;
         if ((e = mark(1, true)) != hipSuccess) return e;
-        discretize_kernel<R><<<dim3((unsigned)((nd + 127) / 128)), dim3(128), 0, stream>>>(
+        discretize_kernel<R, NUC><<<dim3((unsigned)((nd + 127) / 128)), dim3(128), 0, stream>>>(
             a, need_blocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(1, false)) != hipSuccess) return e;
         if ((e = mark(3, true)) != hipSuccess) return e;
         if (pw32)
-            launch_prepare<R, R>(maxt, cfg.B, qthreads, psmem, stream, a);
+            launch_prepare<R, R, NUC>(maxt, cfg.B, qthreads, psmem, stream, a);
         else
-            launch_prepare<R, double>(maxt, cfg.B, qthreads, psmem, stream, a);
+            launch_prepare<R, double, NUC>(maxt, cfg.B, qthreads, psmem, stream, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(3, false)) != hipSuccess) return e;
         if (j > cfg.scp_iters_max) break;  // the last test has set every remaining status
         if ((e = mark(2, true)) != hipSuccess) return e;
         if (persistent) {
             if (maxt == 320)
-                subproblem_persistent<R, 320><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 320, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
             else if (maxt == 640)
-                subproblem_persistent<R, 640><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 640, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
             else
-                subproblem_persistent<R, 1024><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 1024, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
         } else if (bucketed) {
             // the two launches touch disjoint instances; on two streams they run side by side
             hipStream_t s2 = cfg.aux_stream ? cfg.aux_stream : stream;
@@ -1638,13 +1711,13 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
                 if ((e = hipStreamWaitEvent(s2, cfg.ev_fork, 0)) != hipSuccess) return e;
             }
             a.split = 2;
-            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
+            launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 1;
             if (maxt == 640)
-                launch_subproblem<R, 640>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                launch_subproblem<R, 640, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
             else
-                launch_subproblem<R, 1024>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 0;
             if (cfg.aux_stream) {
@@ -1652,11 +1725,11 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
                 if ((e = hipStreamWaitEvent(stream, cfg.ev_join, 0)) != hipSuccess) return e;
             }
         } else if (maxt == 320) {
-            launch_subproblem<R, 320>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else if (maxt == 640) {
-            launch_subproblem<R, 640>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 640, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else {
-            launch_subproblem<R, 1024>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(2, false)) != hipSuccess) return e;
@@ -1668,6 +1741,11 @@ hipError_t launch_solve(const Config &cfg, const Problem &prob, const Solution &
                         const Workspace &ws, const Record *rec, hipStream_t stream,
                         LaunchTimer *timer)
 {
+    if (cfg.nu == NU_MAX) {
+        if (cfg.dtype == 1)
+            return launch_typed<double, NU_MAX>(cfg, prob, sol, ws, rec, stream, timer);
+        return launch_typed<float, NU_MAX>(cfg, prob, sol, ws, rec, stream, timer);
+    }
     if (cfg.dtype == 1) return launch_typed<double>(cfg, prob, sol, ws, rec, stream, timer);
     return launch_typed<float>(cfg, prob, sol, ws, rec, stream, timer);
 }
@@ -1684,7 +1762,7 @@ static hipError_t discretize_at_typed(const Config &cfg, const void *x, const vo
     a.kmax = cfg.kmax;
     a.rk4_substeps = cfg.rk4_substeps;
     for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
-    for (int i = 0; i < NU; ++i) a.pu[i] = cfg.pu[i];
+    for (int i = 0; i < NU_MAX; ++i) a.pu[i] = i < NU ? cfg.pu[i] : 1.0;
     a.params = static_cast<const R *>(prob.params);
     a.K = prob.K;
     a.x = const_cast<R *>(static_cast<const R *>(x));
@@ -1714,7 +1792,7 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
 // same choice without an exchange), lane 0 writes the choice and the scalar outputs, and the
 // workgroup copies the chosen trajectory.
 // ------------------------------------------------------------------------------------------
-template <typename R>
+template <typename R, int NUC = NU>
 __global__ void __launch_bounds__(64) select_best_kernel(Solution in, Solution out, int problems,
                                                           int starts, int kmax, int32_t *best)
 {
@@ -1742,49 +1820,58 @@ __global__ void __launch_bounds__(64) select_best_kernel(Solution in, Solution o
         out.objective[p] = in.objective[src];
     }
     const R *xs = static_cast<const R *>(in.x) + src * kmax * NX;
-    const R *us = static_cast<const R *>(in.u) + src * kmax * NU;
+    const R *us = static_cast<const R *>(in.u) + src * kmax * NUC;
     R *xd = static_cast<R *>(out.x) + (long)p * kmax * NX;
-    R *ud = static_cast<R *>(out.u) + (long)p * kmax * NU;
+    R *ud = static_cast<R *>(out.u) + (long)p * kmax * NUC;
     for (int e = threadIdx.x; e < kmax * NX; e += blockDim.x) xd[e] = xs[e];
-    for (int e = threadIdx.x; e < kmax * NU; e += blockDim.x) ud[e] = us[e];
+    for (int e = threadIdx.x; e < kmax * NUC; e += blockDim.x) ud[e] = us[e];
 }
 
-hipError_t launch_select_best(int dtype, int kmax, const Solution &in, const Solution &out,
-                              int problems, int starts, int32_t *best, hipStream_t stream)
+hipError_t launch_select_best(int dtype, int kmax, int nu, const Solution &in,
+                              const Solution &out, int problems, int starts, int32_t *best,
+                              hipStream_t stream)
 {
     if (problems == 0) return hipSuccess;
-    if (dtype == 1)
-        select_best_kernel<double><<<dim3((unsigned)problems), dim3(64), 0, stream>>>(
-            in, out, problems, starts, kmax, best);
+    const dim3 g((unsigned)problems), t(64);
+    if (dtype == 1 && nu == NU_MAX)
+        select_best_kernel<double, NU_MAX><<<g, t, 0, stream>>>(in, out, problems, starts, kmax, best);
+    else if (dtype == 1)
+        select_best_kernel<double><<<g, t, 0, stream>>>(in, out, problems, starts, kmax, best);
+    else if (nu == NU_MAX)
+        select_best_kernel<float, NU_MAX><<<g, t, 0, stream>>>(in, out, problems, starts, kmax, best);
     else
-        select_best_kernel<float><<<dim3((unsigned)problems), dim3(64), 0, stream>>>(
-            in, out, problems, starts, kmax, best);
+        select_best_kernel<float><<<g, t, 0, stream>>>(in, out, problems, starts, kmax, best);
     return hipGetLastError();
 }
 
 }  // namespace scp
 
 namespace scp {
-template <typename R, int MAXT>
+template <typename R, int MAXT, int NUC>
 static hipError_t persistent_blocks(int *n, int kmax)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, subproblem_persistent<R, MAXT>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, subproblem_persistent<R, MAXT, NUC>,
                                                         qp_block_threads(kmax),
                                                         qp_smem_bytes(kmax, sizeof(R)));
 }
-int qp_blocks_per_cu(int dtype, int kmax)
+template <typename R, int NUC>
+static hipError_t persistent_blocks_of(int *n, int kmax)
 {
     const int maxt = qp_maxt(kmax);
+    return maxt == 320 ? persistent_blocks<R, 320, NUC>(n, kmax)
+                       : (maxt == 640 ? persistent_blocks<R, 640, NUC>(n, kmax)
+                                      : persistent_blocks<R, 1024, NUC>(n, kmax));
+}
+int qp_blocks_per_cu(int dtype, int kmax, int nu)
+{
     int n = 0;
     hipError_t e;
     if (dtype == 1)
-        e = maxt == 320 ? persistent_blocks<double, 320>(&n, kmax)
-                        : (maxt == 640 ? persistent_blocks<double, 640>(&n, kmax)
-                                       : persistent_blocks<double, 1024>(&n, kmax));
+        e = nu == NU_MAX ? persistent_blocks_of<double, NU_MAX>(&n, kmax)
+                         : persistent_blocks_of<double, NU>(&n, kmax);
     else
-        e = maxt == 320 ? persistent_blocks<float, 320>(&n, kmax)
-                        : (maxt == 640 ? persistent_blocks<float, 640>(&n, kmax)
-                                       : persistent_blocks<float, 1024>(&n, kmax));
+        e = nu == NU_MAX ? persistent_blocks_of<float, NU_MAX>(&n, kmax)
+                         : persistent_blocks_of<float, NU>(&n, kmax);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 // ------------------------------------------------------------------------------------------

@@ -9,7 +9,7 @@ namespace scp {
 // allocated for the dtype of the handle; the blocks of one interval are stored column by
 // column, 23 columns [A^- | B^- | B^+] of 16 entries (15 rows + 1 pad).
 struct Workspace {
-    void *blocks;       // R  [B][kmax-1][23][16]  scaled A^-_k, B^-_k, B^+_k
+    void *blocks;       // R  [B][kmax-1][15 + 2 nu][16]  scaled A^-_k, B^-_k, B^+_k
     void *what;         // R  [B][kmax-1][16]      scaled defect w^_k
     double *dy;         // f64 [B][kmax-1]          CTCS increment y^k(tau_k+1) - y_k
     void *mup;          // R  [B][kmax-1][16]      warm start mu+
@@ -42,10 +42,11 @@ struct Config {
     int scalar_dilation;    // 1: one dilation value over the horizon (PIPG projects the
                             //   dilation controls of all nodes onto their mean)
     int power_fp32;         // 1 (FP32 path): power iteration in FP32 instead of FP64
+    int nu;                 // controls per node: 4 (T, s) or 7 (T, gamma, s)
     double scp_tol, feas_tol, pipg_eps_abs, pipg_eps_rel;
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
-    double px[15], pu[4];
+    double px[15], pu[7];   // pu: the first nu entries
 };
 
 struct Problem {
@@ -106,8 +107,9 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
 // problem p at p*starts .. p*starts + starts - 1.  best[p] = the start with status 0 and the
 // smallest objective (ties: the smallest index), -1 if none converged; `out` (problems
 // instances) receives that start's results, start 0's when none converged.
-hipError_t launch_select_best(int dtype, int kmax, const Solution &in, const Solution &out,
-                              int problems, int starts, int32_t *best, hipStream_t stream);
+hipError_t launch_select_best(int dtype, int kmax, int nu, const Solution &in,
+                              const Solution &out, int problems, int starts, int32_t *best,
+                              hipStream_t stream);
 
 // Gradient of (m_f, t_f) of the truncated last-iteration map (discretization at the
 // recorded reference, QP build, `nsteps` PIPG steps from the recorded warm start) with
@@ -130,7 +132,7 @@ int qp_block_threads(int kmax);
 size_t qp_smem_bytes(int kmax, size_t rsize);
 
 // Resident workgroups per compute unit of the persistent subproblem kernel (occupancy query).
-int qp_blocks_per_cu(int dtype, int kmax);
+int qp_blocks_per_cu(int dtype, int kmax, int nu);
 
 // Bytes of the library's fixed device scratch array (the workspace of the allocation-free
 // solve).

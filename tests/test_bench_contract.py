@@ -19,3 +19,5 @@ def test_flop_count_matches_the_block_structure():
     # per interval: a forward and a transposed product of 196 + 2 * 60 MACs, 2 flops each
     assert bench.pipg_flops_per_iter(20) == 19 * (4 * 316 + 428) + 171 * 20
     assert bench.pipg_flops_per_iter(2) == 1 * (4 * 316 + 428) + 171 * 2
+    # with the torque: B^-_k and B^+_k have 15 x 7 entries, a node 22 entries
+    assert bench.pipg_flops_per_iter(30, 7) == 29 * (4 * (196 + 2 * 105) + 428) + 9 * 22 * 30
