@@ -34,6 +34,8 @@ WORKLOAD_NAMES = {
     "C4": "throughput 65,536 x K=30, 15 SCP x 1,000 PIPG iterations, J and r_T dispersed (seed 4)",
     "F1": "paper's Monte Carlo: 256 runs, r0 ~ U(6,9) x U(3,6) x U(1,2), K=30, at most 25 SCP x "
           "2,500 PIPG iterations, SCP early exit (seed 5)",
+    "F1S": "paper's Monte Carlo with the speed bound ||v|| <= 2.5: 256 runs, r0 ~ U(6,9) x "
+           "U(3,6) x U(1,2), K=30, at most 25 SCP x 2,500 PIPG iterations, SCP early exit (seed 5)",
     "F2": "paper's Monte Carlo with the reaction-control torque (n_u = 7): 256 runs, r0 ~ "
           "U(6,9) x U(3,6) x U(1,2), K=30, at most 25 SCP x 2,500 PIPG iterations, SCP early "
           "exit (seed 5)",
@@ -298,11 +300,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1", "F2"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=["C1", "C2", "C4", "F1", "F1S", "F2"],
                     help="C4 (default): the 65,536 x K=30 throughput Monte Carlo, the largest "
                          "single-GPU configuration of the metric's 1k-64k range; C1 (1,024 x "
                          "K=20), C2 (16,384 uneven K, early exit), F1 (the paper's 256-run "
-                         "Monte Carlo) and F2 (the same with the torque control) for reference")
+                         "Monte Carlo), F1S (with the speed bound) and F2 (with the torque control) for "
+                         "reference")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed solves of the same workload on the FP64 path (0: skip)")
     ap.add_argument("--grad", action="store_true",

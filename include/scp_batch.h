@@ -155,6 +155,13 @@ typedef struct {
     const void *xf;             /* real [B][13]                                            */
     const void *params;         /* real [B][24]                                            */
     const int32_t *K;           /* int32 [B] node counts                                   */
+    /* Optional first reference trajectory of the SCP iteration (NULL: the built-in guess,
+     * straight-line r, v, w, interpolated q, constant m, y = 0, hover thrust, s = s_init).
+     * Rows k < K_b of instance b are taken as given, all 15 state entries (y too) and all
+     * n_u controls; e.g. an earlier solution warm-starts the solve.  Either may be NULL
+     * independently; 16-byte aligned like the other arrays. */
+    const void *x_init;         /* real [B][k_max][15] or NULL                             */
+    const void *u_init;         /* real [B][k_max][n_u] or NULL                            */
 } scp_problem;
 
 /* Per-instance results.  x, u hold the trajectory on the K nodes (rows >= K are zero).

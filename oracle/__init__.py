@@ -151,7 +151,7 @@ def _bind(L, settings_cls):
             "orc_pipg": [S, c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, c_double,
                          c_int, c_int, _D, _D, _D, _D, _D, _D],
             "orc_solve_batch": [S, c_int, c_int, _D, _D, _D, _I, c_int, _D, _D, _D, _D, _I, _I,
-                                _I, _D, _D, _D, _D],
+                                _I, _D, _D, _D, _D, _D, _D],
             "orc_solve_trace": [S, c_int, _D, _D, _D, _D, _D, _D, _I, c_int, _D],
             "orc_lastiter_state": [S, c_int, _D, _D, _D, _D, _D, _D, _D],
             "orc_iter_len": [c_int],
@@ -288,14 +288,25 @@ def pipg(cfg, qp, sigma, jmax, check, ws=None, ref=None):
 
 
 # ----------------------------------------------------------------------------- SCP -------
-def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
-    """Solve a batch; returns a dict of numpy arrays (same names as the GPU library)."""
+def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None, x_init=None, u_init=None):
+    """Solve a batch; returns a dict of numpy arrays (same names as the GPU library).
+    x_init [B][kmax][15] and u_init [B][kmax][n_u] (each optional) replace the initial guess
+    on the first K_b nodes of instance b."""
     st = make_settings(cfg)
     x0, a = _d(x0); xf, b = _d(xf); params, c = _d(params)
     K = np.ascontiguousarray(K, dtype=np.int32)
     B = x0.shape[0]
     nu = n_u(cfg)
     kmax = int(K.max()) if kmax is None else int(kmax)
+    xi = ui = None
+    if x_init is not None:
+        xi = np.ascontiguousarray(x_init, dtype=np.float64)
+        if xi.shape != (B, kmax, NX):
+            raise ValueError("oracle: x_init must have shape (B, kmax, 15)")
+    if u_init is not None:
+        ui = np.ascontiguousarray(u_init, dtype=np.float64)
+        if ui.shape != (B, kmax, nu):
+            raise ValueError("oracle: u_init must have shape (B, kmax, n_u)")
     nthreads = os.cpu_count() if nthreads is None else int(nthreads)
     out = dict(x=np.zeros((B, kmax, NX)), u=np.zeros((B, kmax, nu)), t_f=np.zeros(B),
                m_f=np.zeros(B), status=np.zeros(B, np.int32), scp_iters=np.zeros(B, np.int32),
@@ -306,7 +317,8 @@ def solve(cfg, x0, xf, params, K, kmax=None, nthreads=None):
         _p(out["x"]), _p(out["u"]), _p(out["t_f"]), _p(out["m_f"]),
         out["status"].ctypes.data_as(_I), out["scp_iters"].ctypes.data_as(_I),
         out["pipg_iters"].ctypes.data_as(_I), _p(out["defect_inf"]), _p(out["ctcs_viol"]),
-        _p(out["objective"]), _p(out["step"]))
+        _p(out["objective"]), _p(out["step"]), None if xi is None else _p(xi),
+        None if ui is None else _p(ui))
     if rc != 0:
         raise ValueError("oracle: invalid node count")
     return out
@@ -342,7 +354,7 @@ def solve_f32(cfg, x0, xf, params, K, kmax=None, nthreads=None, contract=False):
         ctypes.byref(st), B, kmax, v(x0), v(xf), v(params), v(K), nthreads, v(out["x"]),
         v(out["u"]), v(out["t_f"]), v(out["m_f"]), v(out["status"]), v(out["scp_iters"]),
         v(out["pipg_iters"]), v(out["defect_inf"]), v(out["ctcs_viol"]), v(out["objective"]),
-        v(out["step"]))
+        v(out["step"]), None, None)
     if rc != 0:
         raise ValueError("oracle: invalid node count")
     return {k: (a.astype(np.float64) if a.dtype == np.float32 else a) for k, a in out.items()}

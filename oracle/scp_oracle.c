@@ -1047,9 +1047,12 @@ static int finite_arr(const double *a, int n)
     return 1;
 }
 
+/* One instance.  xinit / uinit (NULL: the initial guess of orc_init_guess), when given, are
+ * the first reference trajectory, [K][NX] and [K][NU]. */
 static void scp_solve_one(const orc_settings *st, int K, const double *x0, const double *xf,
-                          const double *p, double *xbar, double *ubar, orc_result *res,
-                          orc_lastiter *last, int trace_n, double *trace)
+                          const double *p, const double *xinit, const double *uinit,
+                          double *xbar, double *ubar, orc_result *res, orc_lastiter *last,
+                          int trace_n, double *trace)
 {
     int M = K - 1, j, k, i, total_pipg = 0, solves = 0, status = 1;
     double dtau = 1.0 / M, step = INFINITY, d = 0.0, c = 0.0, obj = 0.0;
@@ -1062,6 +1065,8 @@ static void scp_solve_one(const orc_settings *st, int K, const double *x0, const
     qp_alloc(&qp, K);
     iter_alloc(&ws, K);
     orc_init_guess(K, x0, xf, p, xbar, ubar);
+    if (xinit) memcpy(xbar, xinit, sizeof(double) * K * NX);
+    if (uinit) memcpy(ubar, uinit, sizeof(double) * K * NU);
 
     for (j = 1; j <= st->scp_iters_max + 1; j++) {
         int pit, conv;
@@ -1152,6 +1157,7 @@ typedef struct {
     double *x, *u, *tf, *mf, *defect, *ctcs, *objective;
     int32_t *status, *scp_iters, *pipg_iters;
     double *step; /* optional (NULL): scaled step of the last subproblem solved */
+    const double *xinit, *uinit; /* optional (NULL): first reference, [B][kmax][NX], [NU] */
 } batch_job;
 
 static void *batch_worker(void *arg)
@@ -1165,7 +1171,10 @@ static void *batch_worker(void *arg)
         memset(xb, 0, sizeof(double) * jb->kmax * NX);
         memset(ub, 0, sizeof(double) * jb->kmax * NU);
         scp_solve_one(jb->st, K, jb->x0 + (size_t)b * NX, jb->xf + (size_t)b * NXF,
-                      jb->p + (size_t)b * NP, xb, ub, &r, NULL, 0, NULL);
+                      jb->p + (size_t)b * NP,
+                      jb->xinit ? jb->xinit + (size_t)b * jb->kmax * NX : NULL,
+                      jb->uinit ? jb->uinit + (size_t)b * jb->kmax * NU : NULL, xb, ub, &r, NULL,
+                      0, NULL);
         jb->tf[b] = r.tf;
         jb->mf[b] = r.mf;
         jb->defect[b] = r.defect;
@@ -1183,7 +1192,7 @@ int orc_solve_batch(const orc_settings *st, int B, int kmax, const double *x0, c
                     const double *p, const int32_t *K, int nthreads, double *x, double *u,
                     double *tf, double *mf, int32_t *status, int32_t *scp_iters,
                     int32_t *pipg_iters, double *defect, double *ctcs, double *objective,
-                    double *step)
+                    double *step, const double *xinit, const double *uinit)
 {
     pthread_t th[256];
     batch_job jobs[256];
@@ -1194,7 +1203,7 @@ int orc_solve_batch(const orc_settings *st, int B, int kmax, const double *x0, c
         if (K[t] < 2 || K[t] > kmax) return -1;
     for (t = 0; t < nthreads; t++) {
         batch_job jb = {st, B, kmax, nthreads, t, x0, xf, p, K, x, u, tf, mf, defect, ctcs,
-                        objective, status, scp_iters, pipg_iters, step};
+                        objective, status, scp_iters, pipg_iters, step, xinit, uinit};
         jobs[t] = jb;
     }
     if (nthreads == 1) {
@@ -1212,7 +1221,7 @@ int orc_solve_trace(const orc_settings *st, int K, const double *x0, const doubl
                     int32_t *ints, int trace_n, double *trace)
 {
     orc_result r;
-    scp_solve_one(st, K, x0, xf, p, xbar, ubar, &r, NULL, trace_n, trace);
+    scp_solve_one(st, K, x0, xf, p, NULL, NULL, xbar, ubar, &r, NULL, trace_n, trace);
     scalars[0] = r.tf; scalars[1] = r.mf; scalars[2] = r.defect; scalars[3] = r.ctcs;
     scalars[4] = r.objective; scalars[5] = r.step;
     ints[0] = r.status; ints[1] = r.scp_iters; ints[2] = r.pipg_iters;
@@ -1238,7 +1247,7 @@ int orc_lastiter_state(const orc_settings *st, int K, const double *x0, const do
     last.ubar = ubar_last;
     last.ws = ws_last;
     last.valid = 0;
-    scp_solve_one(&s2, K, x0, xf, p, xb, ub, &r, &last, 0, NULL);
+    scp_solve_one(&s2, K, x0, xf, p, NULL, NULL, xb, ub, &r, &last, 0, NULL);
     *sigma_last = last.sigma;
     free(xb);
     free(ub);

@@ -61,7 +61,16 @@ class Settings(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("x0", ctypes.c_void_p), ("xf", ctypes.c_void_p),
-                ("params", ctypes.c_void_p), ("K", ctypes.c_void_p)]
+                ("params", ctypes.c_void_p), ("K", ctypes.c_void_p), ("x_init", ctypes.c_void_p),
+                ("u_init", ctypes.c_void_p)]
+
+
+def _problem_struct(prob):
+    """scp_problem of a dict of device tensors (x_init / u_init optional)."""
+    opt = lambda k: prob[k].data_ptr() if prob.get(k) is not None else None
+    return Problem(int(prob["x0"].shape[0]), prob["x0"].data_ptr(), prob["xf"].data_ptr(),
+                   prob["params"].data_ptr(), prob["K"].data_ptr(), opt("x_init"),
+                   opt("u_init"))
 
 
 class Solution(ctypes.Structure):
@@ -231,19 +240,21 @@ class BatchSolver:
             objective=t.empty(B, dtype=t.float64, device=dev))
 
     def to_device(self, inst):
-        """Problem dict of numpy arrays -> device tensors of the handle's dtype."""
+        """Problem dict of numpy arrays -> device tensors of the handle's dtype (x_init and
+        u_init, the optional first reference [B, k_max, 15] and [B, k_max, n_u], when
+        present)."""
         t = self.torch
         dev = "cuda:%d" % self.device
-        return dict(x0=t.as_tensor(np.ascontiguousarray(inst["x0"]), dtype=self.dtype).to(dev),
-                    xf=t.as_tensor(np.ascontiguousarray(inst["xf"]), dtype=self.dtype).to(dev),
-                    params=t.as_tensor(np.ascontiguousarray(inst["params"]),
-                                       dtype=self.dtype).to(dev),
-                    K=t.as_tensor(np.ascontiguousarray(inst["K"]), dtype=t.int32).to(dev))
+        real = lambda a: t.as_tensor(np.ascontiguousarray(a), dtype=self.dtype).to(dev)
+        out = dict(x0=real(inst["x0"]), xf=real(inst["xf"]), params=real(inst["params"]),
+                   K=t.as_tensor(np.ascontiguousarray(inst["K"]), dtype=t.int32).to(dev))
+        for k in ("x_init", "u_init"):
+            if inst.get(k) is not None:
+                out[k] = real(inst[k])
+        return out
 
     def _structs(self, prob, sol):
-        B = int(prob["x0"].shape[0])
-        p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
-                    prob["K"].data_ptr())
+        p = _problem_struct(prob)
         if sol is None:
             return p, None
         s = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status",
@@ -278,6 +289,12 @@ class BatchSolver:
                                (k, self.dtype, shape))
         if tuple(prob["K"].shape) != (B,) or prob["K"].dtype != self.torch.int32:
             raise ScpError(2, "K must be an int32 tensor of shape (B,)")
+        for k, shape in (("x_init", (B, self.k_max, NX)), ("u_init", (B, self.k_max, self.n_u))):
+            v = prob.get(k)
+            if v is not None and (tuple(v.shape) != shape or v.dtype != self.dtype or
+                                  not v.is_contiguous()):
+                raise ScpError(2, "%s must be a contiguous %s tensor of shape %s" %
+                               (k, self.dtype, shape))
         return B
 
     def _check_real(self, name, v, shape, dtype=None):
@@ -408,8 +425,7 @@ def solve_noalloc_into(cfg, dtype, k_max, max_batch, prob, sol, device=0, stream
     L = load()
     s = make_settings(cfg, dtype, k_max, max_batch)
     B = int(prob["x0"].shape[0])
-    p = Problem(B, prob["x0"].data_ptr(), prob["xf"].data_ptr(), prob["params"].data_ptr(),
-                prob["K"].data_ptr())
+    p = _problem_struct(prob)
     so = Solution(*[sol[n].data_ptr() for n in ("x", "u", "t_f", "m_f", "status", "scp_iters",
                                                  "pipg_iters", "defect_inf", "ctcs_viol",
                                                  "objective")])

@@ -136,7 +136,7 @@ struct scp_batch_s {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    const void *graph_key[22] = {};
+    const void *graph_key[24] = {};
 };
 
 static void drop_graph(scp_batch h)
@@ -354,6 +354,8 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
         if (!aligned16(p)) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
     for (const void *p : out_ptrs)
         if (!aligned16(p)) return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
+    if ((prob->x_init && !aligned16(prob->x_init)) || (prob->u_init && !aligned16(prob->u_init)))
+        return fail(h, SCP_ERR_ARG, "arrays must be 16-byte aligned");
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return fail(h, SCP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
@@ -394,7 +396,7 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
         cfg.persistent_blocks = h->persistent_grid;
     }
 
-    scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+    scp::Problem P{prob->x0, prob->xf, prob->params, prob->K, prob->x_init, prob->u_init};
     scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
                     sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
     const scp::Workspace W = workspace_of(h);
@@ -403,11 +405,12 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
     const scp::Record *RP = rec ? &Rc : nullptr;
     if (h->st.mode >= 1 && !h->profiling) {
         // replay a captured graph of the whole launch sequence when the arguments match
-        const void *key[22] = {reinterpret_cast<const void *>((intptr_t)prob->batch), prob->x0,
+        const void *key[24] = {reinterpret_cast<const void *>((intptr_t)prob->batch), prob->x0,
                                prob->xf, prob->params, prob->K, sol->x, sol->u, sol->t_f,
                                sol->m_f, sol->status, sol->scp_iters, sol->pipg_iters,
                                sol->defect_inf, sol->ctcs_viol, sol->objective,
-                               Rc.xbar, Rc.ubar, Rc.mup, Rc.mum, Rc.phi, Rc.th, Rc.sigma};
+                               Rc.xbar, Rc.ubar, Rc.mup, Rc.mum, Rc.phi, Rc.th, Rc.sigma,
+                               prob->x_init, prob->u_init};
         if (!h->graph_exec || memcmp(key, h->graph_key, sizeof(key)) != 0) {
             drop_graph(h);
             if (!h->cap_stream) {
@@ -760,6 +763,10 @@ scp_status scp_batch_solve_noalloc(const scp_settings *settings, int device, voi
         if (!p || !aligned16(p)) { g_create_error = "a problem array is NULL or not 16-byte aligned"; return SCP_ERR_ARG; }
     for (const void *p : out_ptrs)
         if (!p || !aligned16(p)) { g_create_error = "a solution array is NULL or not 16-byte aligned"; return SCP_ERR_ARG; }
+    if ((prob->x_init && !aligned16(prob->x_init)) || (prob->u_init && !aligned16(prob->u_init))) {
+        g_create_error = "x_init and u_init must be 16-byte aligned";
+        return SCP_ERR_ARG;
+    }
     // the workspace of this batch (no gradient scratch), carved from the fixed array
     scp_settings s = *settings;
     s.max_batch = prob->batch;
@@ -802,7 +809,8 @@ scp_status scp_batch_solve_noalloc(const scp_settings *settings, int device, voi
         cfg.ordered = 0;
         cfg.bucketed = 0;
         cfg.persistent_blocks = 0;
-        const scp::Problem P{prob->x0, prob->xf, prob->params, prob->K};
+        const scp::Problem P{prob->x0, prob->xf, prob->params, prob->K, prob->x_init,
+                             prob->u_init};
         const scp::Solution S{sol->x, sol->u, sol->t_f, sol->m_f, sol->status, sol->scp_iters,
                               sol->pipg_iters, sol->defect_inf, sol->ctcs_viol, sol->objective};
         e = scp::launch_solve(cfg, P, S, workspace_at(static_cast<char *>(ws), L), nullptr,

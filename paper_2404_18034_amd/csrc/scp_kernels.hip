@@ -38,6 +38,7 @@ struct Args {
     double w_cost, w_prox, w_ep, omega, rho;
     double px[NX], pu[NU_MAX];
     const R *x0, *xf, *params;
+    const R *x_init, *u_init;  // optional first reference ([B][kmax][NX], [B][kmax][NUC])
     const int32_t *K;
     R *x, *u, *t_f, *m_f;
     int32_t *status, *scp_iters, *pipg_iters;
@@ -118,6 +119,15 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
     for (int i = 1; i < NUC - 1; ++i) u[i] = R(0);  // the torque guess is zero
     u[0] = R(double(x0[0]) * sqrt(g0 * g0 + g1 * g1 + g2 * g2));
     u[NUC - 1] = p[21];
+    // a caller-supplied first reference replaces the guess on the instance's nodes
+    if (a.x_init) {
+        const R *xi = a.x_init + ((long)b * a.kmax + k) * NX;
+        for (int i = 0; i < NX; ++i) x[i] = xi[i];
+    }
+    if (a.u_init) {
+        const R *ui = a.u_init + ((long)b * a.kmax + k) * NUC;
+        for (int i = 0; i < NUC; ++i) u[i] = ui[i];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -413,7 +423,7 @@ __device__ __forceinline__ R rowdot_part(const R *c, R v, R acc)
 {
     return rowdot_part_impl<R, J0, N>(c, v, acc, std::make_integer_sequence<int, N>{});
 }
-// FP32: lanes 0..7 and 8..14, one v_fmac_f32 with a DPP row_newbcast source each
+// FP32: lanes 0..7 and 8..15, one v_fmac_f32 with a DPP row_newbcast source each
 template <>
 __device__ __forceinline__ float rowdot_part<float, 0, 8>(const float *c, float v, float acc)
 {
@@ -433,7 +443,7 @@ __device__ __forceinline__ float rowdot_part<float, 0, 8>(const float *c, float 
     return acc;
 }
 template <>
-__device__ __forceinline__ float rowdot_part<float, 8, 7>(const float *c, float v, float acc)
+__device__ __forceinline__ float rowdot_part<float, 8, 8>(const float *c, float v, float acc)
 {
     asm volatile(
         "s_nop 4\n\t"
@@ -444,11 +454,12 @@ __device__ __forceinline__ float rowdot_part<float, 8, 7>(const float *c, float 
         "v_fmac_f32_dpp %0, %1, %6 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %7 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %9 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
         : "+v"(acc)
-        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]));
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]));
     return acc;
 }
-
 // Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
 // specialization below uses the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ double proj_sqrt(double x) { return sqrt(x); }
@@ -508,7 +519,7 @@ struct ColStore<float> {
     static constexpr int LDS_STRIDE = 20;
     float *slot;
     __device__ __forceinline__ void put(int q, float v) { slot[q] = v; }
-    // entries 0..7 and 8..15 (the last is padding)
+    // entries 0..7 and 8..15
     __device__ __forceinline__ void get_lo(float (&c)[8]) const
     {
         const float4 *p = reinterpret_cast<const float4 *>(slot);
@@ -528,7 +539,7 @@ template <>
 struct ColStore<double> {
     static constexpr int LDS_STRIDE = 0;
     double *unused;
-    double c[NX];
+    double c[16];
     __device__ __forceinline__ void put(int q, double v) { c[q] = v; }
     __device__ __forceinline__ void get_lo(double (&o)[8]) const
     {
@@ -536,24 +547,24 @@ struct ColStore<double> {
     }
     __device__ __forceinline__ void get_hi(double (&o)[8]) const
     {
-        for (int q = 0; q < 7; ++q) o[q] = c[8 + q];
-        o[7] = 0.0;
+        for (int q = 0; q < 8; ++q) o[q] = c[8 + q];
     }
 };
 
 // Exchange arrays of the PIPG iteration for a workgroup of at most MAXT lanes, one value per
-// lane (row stride 16), so that every access of the iteration is this lane's slot or the
-// slot one row up or down, at a compile-time offset from a single address register:
-// phi and theta (rows -1 .. ROWS-1, row -1 zero), the extrapolated primal values
-// 2x^ - x~ and 2u^ - u~ (rows 0 .. ROWS, the row after the last workgroup row zero).
+// lane (row stride 16), so that every access of the iteration is this lane's slot or a slot
+// of the row above or below, at a compile-time offset from a per-lane address register:
+// the duals (phi on lanes 0..14, -theta on lane 15; rows -1 .. ROWS-1, row -1 zero), the
+// extrapolated primal values 2x^ - x~ and 2u^ - u~ (rows 0 .. ROWS, the row after the last
+// workgroup row zero).
 template <typename R, int MAXT>
 struct QpLds {
     static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
-    static constexpr int PHI = 0, TH = SLOTS, VX = 2 * SLOTS, VU = 3 * SLOTS;
-    // previous fresh iterate (x^, u^, mu+, mu-, phi, theta), this lane's slot only
-    static constexpr int PX = 4 * SLOTS, PU = 5 * SLOTS, PMP = 6 * SLOTS, PMM = 7 * SLOTS,
-                         PPH = 8 * SLOTS, PTH = 9 * SLOTS;
-    static constexpr int ARRAYS = 10;
+    static constexpr int PHI = 0, VX = SLOTS, VU = 2 * SLOTS;
+    // previous fresh iterate (x^, u^, mu+, mu-, phi and -theta), this lane's slot only
+    static constexpr int PX = 3 * SLOTS, PU = 4 * SLOTS, PMP = 5 * SLOTS, PMM = 6 * SLOTS,
+                         PPH = 7 * SLOTS;
+    static constexpr int ARRAYS = 8;
     static constexpr size_t BYTES = (ARRAYS * SLOTS * sizeof(R) + 15) / 16 * 16;
 };
 // workgroup size bound of the subproblem kernel variant that runs k_max nodes
@@ -571,6 +582,15 @@ __device__ __forceinline__ double clampbox(double v, double lo, double hi)
 {
     return fmin(fmax(v, lo), hi);
 }
+// upper bound: min(v, hi) for hi >= v or hi = 0 on the lanes it binds; FP32 as one v_min
+// (fminf would canonicalize hi on every call)
+__device__ __forceinline__ float upper(float v, float hi)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(v), "v"(hi));
+    return r;
+}
+__device__ __forceinline__ double upper(double v, double hi) { return fmin(v, hi); }
 // maximum over the 16 lanes of a row, on every lane (max is exact in any order)
 template <typename R>
 __device__ __forceinline__ R row_max(R v)
@@ -972,8 +992,9 @@ prepare_kernel(Args<R> a)
 // ------------------------------------------------------------------------------------------
 // Subproblem kernel: one workgroup per instance, 16 lanes (one DPP row) per node.
 //   lane i of row k:  state variable (k, i) for i < 15 (primal step), dynamics row (k, i)
-//                     of interval k for i < 15, k < K-1 (dual step); the four controls of
-//                     node k are held, bitwise identical, by all 16 lanes of the row.
+//                     of interval k for i < 15, k < K-1, and the CTCS row of interval k on
+//                     lane 15 (dual step); each control of node k is held, bitwise
+//                     identical, by four lanes of the row.
 // The block products inside an interval use row broadcasts of register values (DPP);
 // only the values a row needs from its neighbouring rows pass through LDS.
 // ------------------------------------------------------------------------------------------
@@ -1018,6 +1039,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const bool node = k < K;               // row holds a node
     const bool isx = node && i < NX;       // lane holds a state variable
     const bool dual = k < M && i < NX;     // lane holds a dynamics row
+    // lane 15 of interval k holds the CTCS dual theta_k, negated, in the phi registers: its
+    // constraint y^_{k+1} - y^_k <= eps^_k enters the dual step as one more row of the block
+    // product (coefficient +1 on y^_k, the row's "w" the bound, y^_{k+1} from node k+1's y
+    // lane) and its projection onto theta >= 0 is a bound on phi
+    const bool thl = k < M && i == 15;
     const long xoff = ((long)b * kmax + (node ? k : 0)) * NX;
     const long uoff = ((long)b * kmax + (node ? k : 0)) * NUC;
     const R *p = a.params + (long)b * NP;
@@ -1026,12 +1052,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
     R rowA[NX], rowBm[NUC], rowBp[NUC];
     ColStore<R> colA{myCol};
-    // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
-    // (forward product)
+    // colA: column i of [A^-_k ; e_y^T] (transposed product: entry 15 is the coefficient of
+    // -theta_k in the y lane's gradient); row*: row i of [A^-_k | B^-_k | B^+_k] (forward
+    // product; on lane 15 the CTCS row)
     for (int q = 0; q < NX; ++q) {
         colA.put(q, dual ? blk[(long)k * BLK + i * CST + q] : R(0));
-        rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : R(0);
+        rowA[q] = dual ? blk[(long)k * BLK + q * CST + i] : ((thl && q == IY) ? R(1) : R(0));
     }
+    colA.put(15, (dual && i == IY) ? R(1) : R(0));
     for (int q = 0; q < NUC; ++q) {
         rowBm[q] = dual ? blk[(long)k * BLK + (NX + q) * CST + i] : R(0);
         rowBp[q] = dual ? blk[(long)k * BLK + (NX + NUC + q) * CST + i] : R(0);
@@ -1079,19 +1107,23 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     }
     const R slo = R((double(p[18]) - double(ub3)) / a.pu[NUC - 1]);
     const R shi = R((double(p[19]) - double(ub3)) / a.pu[NUC - 1]);
-    R wk = R(0), epsk = R(0);
+    // the row's constant: the defect w^_k on the dynamics lanes, the scaled CTCS bound
+    // eps^_k = (eps - (y_{k+1} - y_k)) / p_y on lane 15
+    R wk = R(0);
     if (dual) {
         wk = a.what[((long)b * (kmax - 1) + k) * DST + i];
-        if (i == IY) {
-            const double y0 = double(a.x[((long)b * kmax + k) * NX + IY]);
-            const double y1 = double(a.x[((long)b * kmax + k + 1) * NX + IY]);
-            epsk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
-        }
+    } else if (thl) {
+        const double y0 = double(a.x[((long)b * kmax + k) * NX + IY]);
+        const double y1 = double(a.x[((long)b * kmax + k + 1) * NX + IY]);
+        wk = R((double(p[20]) - (y1 - y0)) / a.px[IY]);
     }
 
     // workgroup-uniform step sizes (from the preparation kernel) and weights: scalar registers
     const R alpha = a.stepsz[2 * b], beta = a.stepsz[2 * b + 1];
     const R rho = a.rho_r, wprox = a.wprox_r, wep = a.wep_r;
+    // mu+- of lane 15 stay zero (an infinite penalty), its phi (-theta) stays <= 0
+    const R wepv = thl ? R(INFINITY) : wep;
+    const R phhi = thl ? R(0) : R(INFINITY);
     const R cost = (isx && k == K - 1 && i == 0) ? R(-a.w_cost) : R(0);  // e_cost = -e_m
 
     // -------------------- PIPG_custom --------------------
@@ -1100,33 +1132,36 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // test; the extrapolated ones are x~, u~, nu, varphi, vartheta.  Lanes that hold no
     // dynamics row start at zero and, with zero blocks and zero neighbour values, stay there.
     R xt = R(0), ut = R(0);  // ut: control component qi of node k
-    R vphi = R(0), nup = R(0), num = R(0);
-    R vth = R(0);  // theta_k on lane IY, zero on the other lanes
+    R vphi = R(0), nup = R(0), num = R(0);  // vphi: phi_k[i], or -theta_k on lane 15
     const long doff = ((long)b * (kmax - 1) + (dual ? k : 0)) * DST + i;
     if (dual) {
         nup = a.mup[doff];
         num = a.mum[doff];
         vphi = a.phi[doff];
-        if (i == IY) vth = a.th[(long)b * kmax + k];
+    } else if (thl) {
+        vphi = -a.th[(long)b * kmax + k];
     }
-    // this lane's exchange slots; row -1 of phi/theta and row KR of the extrapolated primal
+    // this lane's exchange slots; row -1 of the duals and row KR of the extrapolated primal
     // values are zero rows.  The fresh iterate of the step before a stopping test, and of the
     // last step, goes to this lane's previous-iterate slots; they start with the warm start.
     R *sl = reinterpret_cast<R *>(smem_raw) + t;
+    // -theta_{k-1} for the y lane (lane 15 of the row above), a zero slot of row -1 for the
+    // other lanes (lane i's, lane 15 taking lane 14's: they stay clear of the LDS banks of the
+    // y lanes' reads); y of node k+1 for lane 15 of a CTCS row (the y lane of the row below)
+    const R *slth = i == IY ? sl + 1
+                            : reinterpret_cast<R *>(smem_raw) + Lds::PHI + (i == 15 ? IY : i);
+    const R *slv = thl ? sl - 1 : sl;
     sl[Lds::PX] = R(0);
     sl[Lds::PU] = R(0);
     sl[Lds::PMP] = nup;
     sl[Lds::PMM] = num;
     sl[Lds::PPH] = vphi;
-    sl[Lds::PTH] = vth;
     sl[Lds::PHI + 16] = vphi;
-    sl[Lds::TH + 16] = vth;
     sl[Lds::VX] = R(0);
     sl[Lds::VU] = R(0);
     if (t < 16) {
         reinterpret_cast<uint64_t *>(chk)[t] = 0;
         sl[Lds::PHI] = R(0);
-        sl[Lds::TH] = R(0);
         sl[Lds::VX + KR * 16] = R(0);
         sl[Lds::VU + KR * 16] = R(0);
     }
@@ -1138,8 +1173,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             a.rec_mup[ro] = nup;
             a.rec_mum[ro] = num;
             a.rec_phi[ro] = vphi;
-            if (i == IY) a.rec_th[(long)b * (kmax - 1) + k] = vth;
         }
+        if (thl) a.rec_th[(long)b * (kmax - 1) + k] = -vphi;
         if (t == 0) a.rec_sigma[b] = sigma;
     }
     __syncthreads();
@@ -1199,9 +1234,6 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     else if (grp == 1) xlo = (mdry - xb) * ipxi;
     if (!uval) ulo = uhi = R(0);
     else if (qi == NUC - 1) { ulo = slo; uhi = shi; }
-    // theta lives on the CTCS lane of the dynamics rows; elsewhere an infinite epsilon keeps
-    // max(0, .) of its update at zero
-    if (!(dual && i == IY)) epsk = INF;
 
     int iters = 0;
     int since = 0;  // steps since the last stopping test
@@ -1226,8 +1258,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         R xn, un, vx, vu;
         if (wact) {
         // ---- projected gradient step on the primal variables ----
-        const R phm1 = sl[Lds::PHI];  // phi_{k-1}[i] (zero row above the first node)
-        const R thm1 = sl[Lds::TH];   // theta_{k-1} on lane IY
+        const R phm1 = sl[Lds::PHI];    // phi_{k-1}[i] (zero row above the first node)
+        const R thm1 = slth[Lds::PHI];  // -theta_{k-1} on the y lane, zero elsewhere
         // control gradient: sum over rows i of B^-_k[i][j] phi_k[i] + B^+_{k-1}[i][j] phi_{k-1}[i],
         // with the coefficients in this lane's exchange order (computed while the column of
         // A^-_k is on its way from LDS)
@@ -1244,7 +1276,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             const R gu = wprox * ut + gs;
             un = ut - alpha * gu;
         }
-        // (A^-_k)^T phi_k, column i, in two halves of the column (fewer live registers)
+        // (A^-_k)^T phi_k, column i, in two halves of the column (fewer live registers); the
+        // y lane also gathers -theta_k from lane 15 (the CTCS rows give it theta_{k-1} -
+        // theta_k; theta is zero beyond the last interval)
         R g = wprox * xt + cost;
         {
             R c[8];
@@ -1254,10 +1288,10 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         {
             R c[8];
             colA.get_hi(c);
-            g = rowdot_part<R, 8, 7>(c, vphi, g);
+            g = rowdot_part<R, 8, 8>(c, vphi, g);
         }
         g -= phm1;
-        g += thm1 - vth;  // y lane: theta_{k-1} - theta_k (theta_k is zero on the last node)
+        g -= thm1;
         xn = xt - alpha * g;
         if (pmask) {
             // every lane forms its physical value (the thrust lanes 4..6 that of their control
@@ -1303,7 +1337,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         __syncthreads();
         if (wact) {
         // ---- dual (proportional-integral) step ----
-        const R vnext = sl[Lds::VX + 16];   // 2x^ - x~ of node k+1 (zero beyond the last node)
+        const R vnext = slv[Lds::VX + 16];  // 2x^ - x~ of node k+1 (zero beyond the last node)
         R vunext = sl[Lds::VU + 16];        // 2u^ - u~ of node k+1
         if constexpr (SD) {
             // the mean of the active waves' partials, then the box, the extrapolation and the
@@ -1318,11 +1352,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                 vunext = vu;
             }
         }
-        R mupn = nup - alpha * (wep + vphi);
-        R mumn = num - alpha * (wep - vphi);
+        R mupn = nup - alpha * (wepv + vphi);
+        R mumn = num - alpha * (wepv - vphi);
         mupn = mupn > R(0) ? mupn : R(0);
         mumn = mumn > R(0) ? mumn : R(0);
-        R r = rowdot15<R>(rowA, vx, wk);   // w^_k + A^-_k (2x^ - x~)_k
+        // (2 mu+^ - nu+) - (2 mu-^ - nu-) + w^_k, then + A^-_k (2x^ - x~)_k - (2x^ - x~)_{k+1};
+        // on lane 15: eps^_k + (2y^ - y~)_k - (2y^ - y~)_{k+1}
+        R r = R(2) * (mupn - mumn) - (nup - num) + wk;
+        r = rowdot15<R>(rowA, vx, r);
         r -= vnext;
         r = rowdot4c<R>(rowBm, vu, r);      // B^-_k (2u^ - u~)_k
         r = rowdot4c<R>(rowBp, vunext, r);  // B^+_k (2u^ - u~)_{k+1}
@@ -1330,17 +1367,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             r = rowdot_part<R, 8, 3>(rowBm + 4, vu, r);
             r = rowdot_part<R, 8, 3>(rowBp + 4, vunext, r);
         }
-        // (2 mu+^ - nu+) - (2 mu-^ - nu-)
-        r += R(2) * (mupn - mumn) - (nup - num);
-        const R phn = vphi + beta * r;
-        // theta: max(0, .) on the CTCS lane, zero on the others
-        const R thn = fmax(vth + beta * ((vnext - vx) - epsk), R(0));
+        const R phn = upper(vphi + beta * r, phhi);  // lane 15: theta >= 0
         vphi += rho * (phn - vphi);
         nup += rho * (mupn - nup);
         num += rho * (mumn - num);
-        vth += rho * (thn - vth);
         sl[Lds::PHI + 16] = vphi;
-        sl[Lds::TH + 16] = vth;
         // stopping test every `check` steps: infinity norms of (x, u, mu+, mu-) and of
         // (phi, theta) at j+1 and j and of their differences.  Lanes without a variable hold
         // zeros; the controls enter from their read copy (lanes 4..7) only, the other copies
@@ -1351,14 +1382,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             const bool ucopy = uread;
             const R xh = sl[Lds::PX], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
             const R uh = ucopy ? sl[Lds::PU] : R(0), unr = ucopy ? un : R(0);
-            const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
+            const R ph = sl[Lds::PPH];
             R m[6];
             m[0] = fmax(fmax(fabs(xn), fabs(unr)), fmax(fabs(mupn), fabs(mumn)));
             m[1] = fmax(fmax(fabs(xh), fabs(uh)), fmax(fabs(mup), fabs(mum)));
             m[2] = fmax(fmax(fabs(xn - xh), fabs(unr - uh)), fmax(fabs(mupn - mup), fabs(mumn - mum)));
-            m[3] = fmax(fabs(phn), fabs(thn));
-            m[4] = fmax(fabs(ph), fabs(th));
-            m[5] = fmax(fabs(phn - ph), fabs(thn - th));
+            m[3] = fabs(phn);
+            m[4] = fabs(ph);
+            m[5] = fabs(phn - ph);
             for (int q = 0; q < 6; ++q) m[q] = row_max<R>(m[q]);
             if (i == 0)
                 for (int q = 0; q < 6; ++q) atomicMax(&chk[8 * cset + q], max_bits(m[q]));
@@ -1371,7 +1402,6 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             sl[Lds::PMP] = mupn;
             sl[Lds::PMM] = mumn;
             sl[Lds::PPH] = phn;
-            sl[Lds::PTH] = thn;
         }
         }  // wact
         __syncthreads();
@@ -1390,7 +1420,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // -------------------- reference update and warm start --------------------
     // the subproblem's solution: the fresh iterate of the last step
     const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
-    const R ph = sl[Lds::PPH], th = sl[Lds::PTH];
+    const R ph = sl[Lds::PPH];
     double st[1] = {0.0};
     if (isx) {
         st[0] = fabs(double(xh));
@@ -1404,7 +1434,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         a.mup[doff] = mup;
         a.mum[doff] = mum;
         a.phi[doff] = ph;
-        if (i == IY) a.th[(long)b * kmax + k] = th;
+    } else if (thl) {
+        a.th[(long)b * kmax + k] = -ph;
     }
     block_reduce<1, true>(st, red);
     if (t == 0) {
@@ -1603,6 +1634,8 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
     for (int i = 0; i < NU_MAX; ++i) a.pu[i] = i < NUC ? cfg.pu[i] : 1.0;
     a.x0 = static_cast<const R *>(prob.x0);
+    a.x_init = static_cast<const R *>(prob.x_init);
+    a.u_init = static_cast<const R *>(prob.u_init);
     a.xf = static_cast<const R *>(prob.xf);
     a.params = static_cast<const R *>(prob.params);
     a.K = prob.K;

@@ -52,6 +52,7 @@ struct Config {
 struct Problem {
     const void *x0, *xf, *params;
     const int32_t *K;
+    const void *x_init = nullptr, *u_init = nullptr;  // optional first reference
 };
 
 struct Solution {
