@@ -93,9 +93,11 @@ typedef struct {
                                    3: as 1, with a persistent subproblem grid (resident
                                    workgroups pop instances from an atomic queue in that
                                    order);
-                                   4: as 2, and when k_max > 20 the instances with K <= 20
-                                   are solved by the 320-lane subproblem kernel (a second
-                                   launch per SCP iteration) instead of the k_max-sized one */
+                                   4: as 2, and when k_max > 12 the subproblem launch is
+                                   split by node count: K <= 12 in 192-lane workgroups,
+                                   12 < K <= 20 in 320-lane ones, the rest in the
+                                   k_max-sized kernel (up to three launches per SCP
+                                   iteration, on two streams) */
     int32_t grad_pipg_steps;    /* PIPG steps of the differentiated last iteration (0: the
                                    handle computes no gradients and carves no scratch)     */
     int32_t grad_ckpt_every;    /* checkpoint period of the reverse sweep (1..steps)       */

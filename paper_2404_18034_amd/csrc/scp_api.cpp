@@ -366,7 +366,7 @@ static scp_status solve_impl(scp_batch h, const scp_problem *prob, scp_solution 
 
     scp::Config cfg;
     fill_config(h, prob->batch, cfg);
-    if (h->st.mode == 4 && h->st.k_max > 20) {
+    if (h->st.mode == 4 && h->st.k_max > 12) {
         // the second stream and the fork/join events of the K-bucketed launches (created once)
         if (!h->aux_stream) {
             e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking);

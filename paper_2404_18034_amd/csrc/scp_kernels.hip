@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "lander_model.hpp"
@@ -54,7 +55,7 @@ struct Args {
     int32_t *bucket;  // [kmax + 1] counting-sort buckets
     int32_t *order;   // [B] instances by node count, descending
     int use_order;    // subproblem workgroup w solves instance order[w]
-    int split;        // 0: every instance; 1: the first n_big of `order` (K > 20); 2: the rest
+    int split;        // 0: every instance; K-bucketed launches: 1 K > 20, 2 12 < K <= 20, 3 the rest
     // optional record of each subproblem's starting point (the last one solved remains):
     // reference [B][kmax][15], [B][kmax][4]; warm-start duals [B][kmax-1][15], [B][kmax-1];
     // buffered power-iteration estimate [B]
@@ -460,6 +461,180 @@ __device__ __forceinline__ float rowdot_part<float, 8, 8>(const float *c, float 
           "v"(c[7]));
     return acc;
 }
+// FP64 (and the remaining FP32 shapes): the same broadcast chains, one v_fmac_f64 (f32) with a
+// DPP row_newbcast source per term instead of two 32-bit DPP moves and an FMA
+template <>
+__device__ __forceinline__ double rowdot15<double>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]), "v"(c[8]), "v"(c[9]), "v"(c[10]), "v"(c[11]), "v"(c[12]), "v"(c[13]),
+          "v"(c[14]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot4c<double>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot4q<double>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot_part<double, 0, 8>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot_part<double, 8, 8>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %6 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %7 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %9 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+          "v"(c[7]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot_part<double, 8, 7>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %6 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %7 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot_part<double, 8, 3>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ double rowdot_part<double, 4, 4>(const double *c, double v, double acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ float rowdot_part<float, 8, 3>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ float rowdot_part<float, 4, 4>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+template <>
+__device__ __forceinline__ float rowdot_part<float, 8, 7>(const float *c, float v, float acc)
+{
+    asm volatile(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %6 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %7 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(acc)
+        : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]));
+    return acc;
+}
+
+
 // Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
 // specialization below uses the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ double proj_sqrt(double x) { return sqrt(x); }
@@ -571,7 +746,7 @@ struct QpLds {
 __host__ __device__ inline int qp_maxt(int kmax)
 {
     const int threads = (kmax + 3) / 4 * 64;
-    return threads <= 320 ? 320 : (threads <= 640 ? 640 : 1024);
+    return threads <= 320 ? 320 : (threads <= 512 ? 512 : 1024);
 }
 // clamp to [lo, hi] (lo <= hi), one median-of-three in FP32
 __device__ __forceinline__ float clampbox(float v, float lo, float hi)
@@ -845,6 +1020,19 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
         }
     }
 
+    // FP64 iteration over FP32 blocks with the thrust-only layout: the row coefficients are
+    // widened once (exactly) and kept in FP64 registers; the column of A^-_k is widened term
+    // by term from LDS.  Otherwise (the torque layout: its register budget) every term widens.
+    constexpr bool WIDEN = sizeof(R) < sizeof(P) && NUC == NU;
+    using RW = std::conditional_t<WIDEN, P, R>;
+    RW rowAw[NX], rowBmw[NUC], rowBpw[NUC], rowBqw[NUC];
+    for (int q = 0; q < NX; ++q) rowAw[q] = RW(rowA[q]);
+    for (int q = 0; q < NUC; ++q) {
+        rowBmw[q] = RW(rowBm[q]);
+        rowBpw[q] = RW(rowBp[q]);
+        rowBqw[q] = RW(rowBq[q]);
+    }
+
     // -------------------- customized power iteration --------------------
     // z = (x, u, mu+, mu-) starts at all ones: x_k on lane i of row k, u_k[q] on lanes
     // 4q..4q+3 of row k, mu+- of dynamics row (k, i) on the dual lanes.  Each step forms
@@ -877,11 +1065,11 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     double sstar = sigma;
     const int nw = (blockDim.x + 63) >> 6;
     for (int it = 1; it <= a.power_iters_max; ++it) {
-        if constexpr (sizeof(R) < sizeof(P)) {
-            keep_narrow(rowA);
-            keep_narrow(rowBm);
-            keep_narrow(rowBp);
-            keep_narrow(rowBq);
+        if constexpr (sizeof(R) < sizeof(P) && !WIDEN) {
+            keep_narrow(rowAw);
+            keep_narrow(rowBmw);
+            keep_narrow(rowBpw);
+            keep_narrow(rowBqw);
             if constexpr (NUC == NU_MAX) {
                 keep_narrow(rowBmXA);
                 keep_narrow(rowBqXA);
@@ -893,16 +1081,16 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
         if (wact) {
             // A^-_k z_k - z_{k+1} + B^-_k u_k + B^+_k u_{k+1} + (mu+ - mu-), divided by sigma
             const P zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
-            P r = pw_dot<R, P, 0, 1, NX>(rowA, zx, P(0));
+            P r = pw_dot<RW, P, 0, 1, NX>(rowAw, zx, P(0));
             r -= zxn;
             if constexpr (NUC == NU) {
-                r = pw_dot<R, P, 0, 4, NU>(rowBm, zu, r);
-                r = pw_dot<R, P, 0, 4, NU>(rowBp, zun, r);
+                r = pw_dot<RW, P, 0, 4, NU>(rowBmw, zu, r);
+                r = pw_dot<RW, P, 0, 4, NU>(rowBpw, zun, r);
             } else {
-                r = pw_dot<R, P, 4, 1, 4>(rowBm, zu, r);
-                r = pw_dot<R, P, 8, 1, 3>(rowBm + 4, zu, r);
-                r = pw_dot<R, P, 4, 1, 4>(rowBp, zun, r);
-                r = pw_dot<R, P, 8, 1, 3>(rowBp + 4, zun, r);
+                r = pw_dot<RW, P, 4, 1, 4>(rowBmw, zu, r);
+                r = pw_dot<RW, P, 8, 1, 3>(rowBmw + 4, zu, r);
+                r = pw_dot<RW, P, 4, 1, 4>(rowBpw, zun, r);
+                r = pw_dot<RW, P, 8, 1, 3>(rowBpw + 4, zun, r);
             }
             r += dmu;
             if constexpr (sizeof(P) == 8) {
@@ -939,7 +1127,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
             if constexpr (NUC == NU) {
                 P gq[NU];
-                for (int q = 0; q < NU; ++q) gq[q] = P(rowBm[q]) * ph + P(rowBq[q]) * phm;
+                for (int q = 0; q < NU; ++q) gq[q] = P(rowBmw[q]) * ph + P(rowBqw[q]) * phm;
                 const P zq = row_reduce_scatter4<P>(gq, i);
                 zu = node ? zq : P(0);
             } else {
@@ -1455,18 +1643,18 @@ subproblem_kernel(Args<R> a)
     // with ordered dispatch, workgroup w takes the w-th instance by node count (descending):
     // the hardware issues workgroups as earlier ones retire, so the longest instances start
     // first and the short ones fill in behind them
-    // with bucketed launches the K-descending order is split after the n_big instances with
-    // K > 20 (the end of the K = 21 bucket once the order is built): one launch of the k_max
-    // sized kernel takes those, one of the 320-lane kernel the rest
+    // with bucketed launches the K-descending order is cut after the instances with K > 20
+    // and after those with K > 12 (the ends of the K = 21 and K = 13 buckets once the order is
+    // built): the k_max-sized kernel takes the first part, the 320-lane kernel the second, the
+    // 192-lane kernel the rest
     int idx = blockIdx.x;
     if (a.split) {
-        const int nbig = a.kmax > 20 ? a.bucket[a.kmax - 21] : 0;
-        if (a.split == 1) {
-            if (idx >= nbig) return;
-        } else {
-            idx += nbig;
-            if (idx >= a.B) return;
-        }
+        const int n20 = a.kmax > 20 ? a.bucket[a.kmax - 21] : 0;
+        const int n12 = a.kmax > 12 ? a.bucket[a.kmax - 13] : 0;
+        const int lo = a.split == 1 ? 0 : (a.split == 2 ? n20 : n12);
+        const int hi = a.split == 1 ? n20 : (a.split == 2 ? n12 : a.B);
+        idx += lo;
+        if (idx >= hi) return;
     }
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
@@ -1529,19 +1717,23 @@ __global__ void order_scatter(Args<R> a)
 // ------------------------------------------------------------------------------------------
 int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
-size_t qp_smem_bytes(int kmax, size_t rsize)
+// dynamic LDS bytes of the subproblem kernel variant `maxt` running k_max nodes
+static size_t qp_smem_bytes_at(int maxt, int kmax, size_t rsize)
 {
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
-    const int maxt = qp_maxt(kmax);
-    const size_t stage = rsize == 4 ? (maxt == 320 ? QpLds<float, 320>::BYTES
-                                                   : (maxt == 640 ? QpLds<float, 640>::BYTES
-                                                                  : QpLds<float, 1024>::BYTES))
-                                    : (maxt == 320 ? QpLds<double, 320>::BYTES
-                                                   : (maxt == 640 ? QpLds<double, 640>::BYTES
-                                                                  : QpLds<double, 1024>::BYTES));
+    size_t stage;
+    if (rsize == 4)
+        stage = maxt == 192 ? QpLds<float, 192>::BYTES
+              : maxt == 320 ? QpLds<float, 320>::BYTES
+              : maxt == 512 ? QpLds<float, 512>::BYTES : QpLds<float, 1024>::BYTES;
+    else
+        stage = maxt == 192 ? QpLds<double, 192>::BYTES
+              : maxt == 320 ? QpLds<double, 320>::BYTES
+              : maxt == 512 ? QpLds<double, 512>::BYTES : QpLds<double, 1024>::BYTES;
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
     return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
 }
+size_t qp_smem_bytes(int kmax, size_t rsize) { return qp_smem_bytes_at(qp_maxt(kmax), kmax, rsize); }
 // dynamic LDS bytes of the preparation kernel (rsize: the working precision, psize: that of
 // the power iteration)
 static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
@@ -1550,10 +1742,10 @@ static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
     const size_t stage = psize == 4 ? (maxt == 320 ? PrepLds<float, 320>::BYTES
-                                                   : (maxt == 640 ? PrepLds<float, 640>::BYTES
+                                                   : (maxt == 512 ? PrepLds<float, 512>::BYTES
                                                                   : PrepLds<float, 1024>::BYTES))
                                     : (maxt == 320 ? PrepLds<double, 320>::BYTES
-                                                   : (maxt == 640 ? PrepLds<double, 640>::BYTES
+                                                   : (maxt == 512 ? PrepLds<double, 512>::BYTES
                                                                   : PrepLds<double, 1024>::BYTES));
     return stage + rsize * KR * 16 * col;
 }
@@ -1564,8 +1756,8 @@ static void launch_prepare(int maxt, int B, int threads, size_t smem, hipStream_
 {
     if (maxt == 320)
         prepare_kernel<R, P, 320, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
-    else if (maxt == 640)
-        prepare_kernel<R, P, 640, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    else if (maxt == 512)
+        prepare_kernel<R, P, 512, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
     else
         prepare_kernel<R, P, 1024, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
@@ -1702,8 +1894,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
     a.split = 0;
-    const bool bucketed = cfg.bucketed && cfg.ordered && cfg.kmax > 20;
+    const bool bucketed = cfg.bucketed && cfg.ordered && cfg.kmax > 12;
     const size_t smem20 = qp_smem_bytes(20, sizeof(R));
+    const size_t smem12 = qp_smem_bytes_at(192, 12, sizeof(R));
     if (persistent || cfg.ordered) {
         const unsigned nb = (unsigned)((cfg.B + 255) / 256);
         order_histogram<R><<<dim3(nb), dim3(256), 0, stream>>>(a);
@@ -1732,25 +1925,35 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if (persistent) {
             if (maxt == 320)
                 subproblem_persistent<R, 320, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
-            else if (maxt == 640)
-                subproblem_persistent<R, 640, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+            else if (maxt == 512)
+                subproblem_persistent<R, 512, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
             else
                 subproblem_persistent<R, 1024, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
         } else if (bucketed) {
-            // the two launches touch disjoint instances; on two streams they run side by side
+            // the launches touch disjoint instances; on two streams they run side by side
             hipStream_t s2 = cfg.aux_stream ? cfg.aux_stream : stream;
             if (cfg.aux_stream) {
                 if ((e = hipEventRecord(cfg.ev_fork, stream)) != hipSuccess) return e;
                 if ((e = hipStreamWaitEvent(s2, cfg.ev_fork, 0)) != hipSuccess) return e;
             }
-            a.split = 2;
-            launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
+            // K <= 12 in 192-lane workgroups (three waves: six of them fit a CU where the
+            // 320-lane kernel holds four with two idle waves each), 12 < K <= 20 in 320-lane
+            // ones, the rest in the k_max-sized kernel
+            a.split = 3;
+            launch_subproblem<R, 192, NUC>(cfg.occupancy, cfg.B, qp_block_threads(12), smem12, s2, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            a.split = 1;
-            if (maxt == 640)
-                launch_subproblem<R, 640, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
-            else
-                launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            a.split = 2;
+            if (cfg.kmax > 20) {
+                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                a.split = 1;
+                if (maxt == 512)
+                    launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                else
+                    launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            } else {
+                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            }
             if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 0;
             if (cfg.aux_stream) {
@@ -1759,8 +1962,8 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
             }
         } else if (maxt == 320) {
             launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
-        } else if (maxt == 640) {
-            launch_subproblem<R, 640, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+        } else if (maxt == 512) {
+            launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         } else {
             launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
         }
@@ -1892,7 +2095,7 @@ static hipError_t persistent_blocks_of(int *n, int kmax)
 {
     const int maxt = qp_maxt(kmax);
     return maxt == 320 ? persistent_blocks<R, 320, NUC>(n, kmax)
-                       : (maxt == 640 ? persistent_blocks<R, 640, NUC>(n, kmax)
+                       : (maxt == 512 ? persistent_blocks<R, 512, NUC>(n, kmax)
                                       : persistent_blocks<R, 1024, NUC>(n, kmax));
 }
 int qp_blocks_per_cu(int dtype, int kmax, int nu)

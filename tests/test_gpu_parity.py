@@ -349,8 +349,8 @@ def test_invalid_arguments_raise():
                                             (4, 0), (4, 5), (4, 6)])
 def test_dispatch_modes_match_plain_launches(mode, occupancy):
     # graph replay, K-ordered dispatch, the persistent work queue and the K-bucketed launches
-    # (K <= 20 in the 320-lane kernel) compute the same thing as plain launches, bit for bit,
-    # on a mixed-K batch with early exit; repeated replays too
+    # (K <= 12 and K <= 20 in the 192- and 320-lane kernels) compute the same thing as plain
+    # launches, bit for bit, on a mixed-K batch with early exit; repeated replays too
     import torch
     cfg = I.solver_settings("C2")
     inst = I.make_instances("C2", B=40)
@@ -373,6 +373,31 @@ def test_dispatch_modes_match_plain_launches(mode, occupancy):
     for k in ref:
         np.testing.assert_array_equal(sol7[k].cpu().numpy(), ref[k][:7])
     s.close()
+
+
+@pytest.mark.parametrize("occupancy", [0, 5, 6])
+def test_bucketed_short_instances_match_plain_launches(occupancy):
+    # K-bucketed launches with k_max <= 20: K <= 12 in the 192-lane kernel, the rest in the
+    # 320-lane one, both buckets and the boundary counts (12, 13) present, with early exit
+    import torch
+    print("case: mode 4 occupancy %d, k_max 20" % occupancy, flush=True)
+    cfg = I.solver_settings("C2", scp_iters_max=6, pipg_iters_max=400)
+    inst = I.make_instances("C2", B=36)
+    inst["K"] = np.array([2, 5, 12, 13, 20, 9, 17, 12, 13, 4, 20, 11] * 3, dtype=np.int32)
+    ref = _gpu(cfg, inst, "f32", k_max=20)
+    s = api.BatchSolver(dict(cfg, mode=4, occupancy=occupancy), dtype="f32", k_max=20,
+                        max_batch=36)
+    try:
+        prob = s.to_device(inst)
+        sol = s.alloc_solution(36)
+        for rep in range(2):
+            s.solve_into(prob, sol)
+            torch.cuda.synchronize()
+            for k in ref:
+                np.testing.assert_array_equal(sol[k].cpu().numpy(), ref[k],
+                                              err_msg="%s rep %d" % (k, rep))
+    finally:
+        s.close()
 
 
 @pytest.mark.parametrize("mode,occupancy", [(1, 6), (1, 5), (0, 6)])
