@@ -732,14 +732,15 @@ struct ColStore<double> {
 // the duals (phi on lanes 0..14, -theta on lane 15; rows -1 .. ROWS-1, row -1 zero), the
 // extrapolated primal values 2x^ - x~ and 2u^ - u~ (rows 0 .. ROWS, the row after the last
 // workgroup row zero).
-template <typename R, int MAXT>
+// LEAN (no node-wise sets, no stopping test): the exchange arrays only.
+template <typename R, int MAXT, bool LEAN = false>
 struct QpLds {
     static constexpr int SLOTS = (MAXT / 16 + 1) * 16;
     static constexpr int PHI = 0, VX = SLOTS, VU = 2 * SLOTS;
     // previous fresh iterate (x^, u^, mu+, mu-, phi and -theta), this lane's slot only
     static constexpr int PX = 3 * SLOTS, PU = 4 * SLOTS, PMP = 5 * SLOTS, PMM = 6 * SLOTS,
                          PPH = 7 * SLOTS;
-    static constexpr int ARRAYS = 8;
+    static constexpr int ARRAYS = LEAN ? 3 : 8;
     static constexpr size_t BYTES = (ARRAYS * SLOTS * sizeof(R) + 15) / 16 * 16;
 };
 // workgroup size bound of the subproblem kernel variant that runs k_max nodes
@@ -1196,7 +1197,13 @@ prepare_kernel(Args<R> a)
 // holds control component ci = (i & 3) + 4 (i >> 3) (component 7 is padding, zero): the thrust
 // and the first torque component on lanes 0..7 (read copy 4..7, as with thrust alone), the rest
 // of the torque and the dilation on lanes 8..15 (read copy 8..10).
-template <typename R, int MAXT, bool FAIR = false, bool SD = false, int NUC = NU>
+// LEAN: the variant for the paper's constraint set without a PIPG stopping test (node-wise
+// sets off; no early exit, or a check period beyond the iteration budget), bit for bit the
+// general one there: the projection and stopping-test code and their LDS slots are compiled
+// out, which takes the FP32 kernel from 95 to 79 VGPRs and its LDS from 59 to 48 KB at
+// K = 30, three workgroups per CU instead of two.
+template <typename R, int MAXT, bool FAIR = false, bool SD = false, int NUC = NU,
+          bool LEAN = false>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
 {
@@ -1212,7 +1219,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const bool wact = ((t >> 6) << 2) < K;
 
     // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
-    using Lds = QpLds<R, MAXT>;
+    using Lds = QpLds<R, MAXT, LEAN>;
     const int KR = blockDim.x >> 4;  // rows of this workgroup (a multiple of 4)
     double *red = reinterpret_cast<double *>(smem_raw + Lds::BYTES);  // [16 waves * 8]
     // stopping-test maxima: two sets of six bit patterns (32-bit for FP32, 64-bit for FP64)
@@ -1339,11 +1346,15 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const R *slth = i == IY ? sl + 1
                             : reinterpret_cast<R *>(smem_raw) + Lds::PHI + (i == 15 ? IY : i);
     const R *slv = thl ? sl - 1 : sl;
-    sl[Lds::PX] = R(0);
-    sl[Lds::PU] = R(0);
-    sl[Lds::PMP] = nup;
-    sl[Lds::PMM] = num;
-    sl[Lds::PPH] = vphi;
+    // LEAN keeps the last step's fresh iterate in registers
+    R fxh = R(0), fuh = R(0), fmup = nup, fmum = num, fph = vphi;
+    if constexpr (!LEAN) {
+        sl[Lds::PX] = R(0);
+        sl[Lds::PU] = R(0);
+        sl[Lds::PMP] = nup;
+        sl[Lds::PMM] = num;
+        sl[Lds::PPH] = vphi;
+    }
     sl[Lds::PHI + 16] = vphi;
     sl[Lds::VX] = R(0);
     sl[Lds::VU] = R(0);
@@ -1368,8 +1379,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     __syncthreads();
 
     const int jmax = a.pipg_iters_max;
-    const int check = a.early_exit ? a.pipg_check_every : 0;
-    const int pmask = a.node_projections;
+    const int check = LEAN ? 0 : (a.early_exit ? a.pipg_check_every : 0);
+    const int pmask = LEAN ? 0 : a.node_projections;
     // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
     // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
     // Each set is projected once, by its leader lane: glide slope by lane 1 (r), tilt by lane
@@ -1584,7 +1595,15 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             if (t == 0)
                 for (int q = 0; q < 6; ++q) chk[8 * (cset ^ 1) + q] = 0;
         }
-        if (test || before_test || it == jmax) {
+        if constexpr (LEAN) {
+            if (it == jmax) {
+                fxh = xn;
+                fuh = un;
+                fmup = mupn;
+                fmum = mumn;
+                fph = phn;
+            }
+        } else if (test || before_test || it == jmax) {
             sl[Lds::PX] = xn;
             sl[Lds::PU] = un;
             sl[Lds::PMP] = mupn;
@@ -1607,8 +1626,14 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 
     // -------------------- reference update and warm start --------------------
     // the subproblem's solution: the fresh iterate of the last step
-    const R xh = sl[Lds::PX], uh = sl[Lds::PU], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
-    const R ph = sl[Lds::PPH];
+    if constexpr (!LEAN) {
+        fxh = sl[Lds::PX];
+        fuh = sl[Lds::PU];
+        fmup = sl[Lds::PMP];
+        fmum = sl[Lds::PMM];
+        fph = sl[Lds::PPH];
+    }
+    const R xh = fxh, uh = fuh, mup = fmup, mum = fmum, ph = fph;
     double st[1] = {0.0};
     if (isx) {
         st[0] = fabs(double(xh));
@@ -1635,7 +1660,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 // ------------------------------------------------------------------------------------------
 
 // WPE: minimum waves per SIMD the register allocation must allow (1: no constraint).
-template <typename R, int MAXT, int WPE, bool SD = false, int NUC = NU>
+template <typename R, int MAXT, int WPE, bool SD = false, int NUC = NU, bool LEAN = false>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE)))
 subproblem_kernel(Args<R> a)
 {
@@ -1658,7 +1683,7 @@ subproblem_kernel(Args<R> a)
     }
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
-    subproblem_body<R, MAXT, (WPE >= 6), SD, NUC>(a, b, smem_raw);
+    subproblem_body<R, MAXT, (WPE >= 6), SD, NUC, LEAN>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
@@ -1718,18 +1743,21 @@ __global__ void order_scatter(Args<R> a)
 int qp_block_threads(int kmax) { return (kmax + 3) / 4 * 64; }
 
 // dynamic LDS bytes of the subproblem kernel variant `maxt` running k_max nodes
-static size_t qp_smem_bytes_at(int maxt, int kmax, size_t rsize)
+template <bool LEAN>
+static size_t qp_stage_bytes(int maxt, size_t rsize)
+{
+    if (rsize == 4)
+        return maxt == 192 ? QpLds<float, 192, LEAN>::BYTES
+             : maxt == 320 ? QpLds<float, 320, LEAN>::BYTES
+             : maxt == 512 ? QpLds<float, 512, LEAN>::BYTES : QpLds<float, 1024, LEAN>::BYTES;
+    return maxt == 192 ? QpLds<double, 192, LEAN>::BYTES
+         : maxt == 320 ? QpLds<double, 320, LEAN>::BYTES
+         : maxt == 512 ? QpLds<double, 512, LEAN>::BYTES : QpLds<double, 1024, LEAN>::BYTES;
+}
+static size_t qp_smem_bytes_at(int maxt, int kmax, size_t rsize, bool lean = false)
 {
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
-    size_t stage;
-    if (rsize == 4)
-        stage = maxt == 192 ? QpLds<float, 192>::BYTES
-              : maxt == 320 ? QpLds<float, 320>::BYTES
-              : maxt == 512 ? QpLds<float, 512>::BYTES : QpLds<float, 1024>::BYTES;
-    else
-        stage = maxt == 192 ? QpLds<double, 192>::BYTES
-              : maxt == 320 ? QpLds<double, 320>::BYTES
-              : maxt == 512 ? QpLds<double, 512>::BYTES : QpLds<double, 1024>::BYTES;
+    const size_t stage = lean ? qp_stage_bytes<true>(maxt, rsize) : qp_stage_bytes<false>(maxt, rsize);
     const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
     return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
 }
@@ -1764,9 +1792,33 @@ static void launch_prepare(int maxt, int B, int threads, size_t smem, hipStream_
 
 // Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
 // to that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
+template <typename R, int MAXT, int NUC, bool LEAN>
+static void launch_subproblem_v(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
+                                const Args<R> &a)
+{
+    if constexpr (sizeof(R) == 4) {
+        if (occupancy == 6) {
+            subproblem_kernel<R, MAXT, 6, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            return;
+        }
+        if (occupancy == 5) {
+            subproblem_kernel<R, MAXT, 5, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
+            return;
+        }
+        if constexpr (MAXT < 1024) {
+            if (occupancy == 4) {
+                subproblem_kernel<R, MAXT, 4, false, NUC, LEAN>
+                    <<<dim3(B), dim3(threads), smem, stream>>>(a);
+                return;
+            }
+        }
+    }
+    subproblem_kernel<R, MAXT, 1, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
+}
+// smem must be the dynamic LDS of the variant launched (qp_smem_bytes_at with `lean`)
 template <typename R, int MAXT, int NUC = NU>
 static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
-                              const Args<R> &a)
+                              const Args<R> &a, bool lean)
 {
     if (NUC == NU && a.scalar_dilation) {
         // one variant: FP32 bounded to six waves per SIMD (with the priority rotation), FP64
@@ -1775,23 +1827,10 @@ static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hi
             <<<dim3(B), dim3(threads), smem, stream>>>(a);
         return;
     }
-    if constexpr (sizeof(R) == 4) {
-        if (occupancy == 6) {
-            subproblem_kernel<R, MAXT, 6, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
-            return;
-        }
-        if (occupancy == 5) {
-            subproblem_kernel<R, MAXT, 5, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
-            return;
-        }
-        if constexpr (MAXT < 1024) {
-            if (occupancy == 4) {
-                subproblem_kernel<R, MAXT, 4, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
-                return;
-            }
-        }
-    }
-    subproblem_kernel<R, MAXT, 1, false, NUC><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    if (lean)
+        launch_subproblem_v<R, MAXT, NUC, true>(occupancy, B, threads, smem, stream, a);
+    else
+        launch_subproblem_v<R, MAXT, NUC, false>(occupancy, B, threads, smem, stream, a);
 }
 
 template <typename R, int NUC = NU>
@@ -1887,7 +1926,11 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const long nd = (long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS;
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
-    const size_t smem = qp_smem_bytes(cfg.kmax, sizeof(R));
+    // the lean variant where the node-wise sets are off and no stopping test can fire
+    const bool lean = !cfg.scalar_dilation && cfg.node_projections == 0 &&
+                      (!cfg.early_exit || cfg.pipg_check_every > cfg.pipg_iters_max);
+    const size_t smem = qp_smem_bytes_at(maxt, cfg.kmax, sizeof(R), lean);
+    const size_t smem_full = qp_smem_bytes(cfg.kmax, sizeof(R));
     // power iteration in FP64 unless the FP32 variant is selected (FP32 path only)
     const bool pw32 = sizeof(R) == 4 && cfg.power_fp32;
     const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R), pw32 ? 4 : 8);
@@ -1895,8 +1938,8 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.use_order = cfg.ordered ? 1 : 0;
     a.split = 0;
     const bool bucketed = cfg.bucketed && cfg.ordered && cfg.kmax > 12;
-    const size_t smem20 = qp_smem_bytes(20, sizeof(R));
-    const size_t smem12 = qp_smem_bytes_at(192, 12, sizeof(R));
+    const size_t smem20 = qp_smem_bytes_at(320, 20, sizeof(R), lean);
+    const size_t smem12 = qp_smem_bytes_at(192, 12, sizeof(R), lean);
     if (persistent || cfg.ordered) {
         const unsigned nb = (unsigned)((cfg.B + 255) / 256);
         order_histogram<R><<<dim3(nb), dim3(256), 0, stream>>>(a);
@@ -1924,11 +1967,11 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if ((e = mark(2, true)) != hipSuccess) return e;
         if (persistent) {
             if (maxt == 320)
-                subproblem_persistent<R, 320, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 320, NUC><<<dim3(pgrid), dim3(qthreads), smem_full, stream>>>(a);
             else if (maxt == 512)
-                subproblem_persistent<R, 512, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 512, NUC><<<dim3(pgrid), dim3(qthreads), smem_full, stream>>>(a);
             else
-                subproblem_persistent<R, 1024, NUC><<<dim3(pgrid), dim3(qthreads), smem, stream>>>(a);
+                subproblem_persistent<R, 1024, NUC><<<dim3(pgrid), dim3(qthreads), smem_full, stream>>>(a);
         } else if (bucketed) {
             // the launches touch disjoint instances; on two streams they run side by side
             hipStream_t s2 = cfg.aux_stream ? cfg.aux_stream : stream;
@@ -1940,19 +1983,19 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
             // 320-lane kernel holds four with two idle waves each), 12 < K <= 20 in 320-lane
             // ones, the rest in the k_max-sized kernel
             a.split = 3;
-            launch_subproblem<R, 192, NUC>(cfg.occupancy, cfg.B, qp_block_threads(12), smem12, s2, a);
+            launch_subproblem<R, 192, NUC>(cfg.occupancy, cfg.B, qp_block_threads(12), smem12, s2, a, lean);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 2;
             if (cfg.kmax > 20) {
-                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a);
+                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qp_block_threads(20), smem20, s2, a, lean);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
                 a.split = 1;
                 if (maxt == 512)
-                    launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                    launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
                 else
-                    launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                    launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
             } else {
-                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+                launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
             a.split = 0;
@@ -1961,11 +2004,11 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
                 if ((e = hipStreamWaitEvent(stream, cfg.ev_join, 0)) != hipSuccess) return e;
             }
         } else if (maxt == 320) {
-            launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 320, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
         } else if (maxt == 512) {
-            launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 512, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
         } else {
-            launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a);
+            launch_subproblem<R, 1024, NUC>(cfg.occupancy, cfg.B, qthreads, smem, stream, a, lean);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(2, false)) != hipSuccess) return e;

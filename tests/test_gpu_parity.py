@@ -375,6 +375,25 @@ def test_dispatch_modes_match_plain_launches(mode, occupancy):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,k_max", [("f32", 30), ("f32", 20), ("f64", 30)])
+def test_lean_variant_matches_the_general_kernel(dtype, k_max):
+    # without node-wise sets and with no stopping test that can fire, the library launches the
+    # lean subproblem kernel (no projection or stopping-test code); with a stopping test at the
+    # last PIPG step it launches the general one, which must then compute the same thing bit
+    # for bit (SCP tolerances at zero so that neither run stops early)
+    print("case: lean vs general kernel, %s, k_max %d" % (dtype, k_max), flush=True)
+    base = dict(scp_iters_max=4, pipg_iters_max=300, scp_tol=0.0, feas_tol=0.0)
+    inst = I.make_instances("C2", B=48)
+    inst["K"] = np.minimum(inst["K"], k_max).astype(np.int32)
+    lean = _gpu(I.solver_settings("C2", early_exit=0, **base), inst, dtype, k_max=k_max)
+    full = _gpu(I.solver_settings("C2", early_exit=1, pipg_check_every=300, **base), inst, dtype,
+                k_max=k_max)
+    ran = lean["status"] == 1
+    assert ran.sum() >= 40 and np.all(lean["pipg_iters"][ran] == 4 * 300)
+    for k in lean:
+        np.testing.assert_array_equal(lean[k], full[k], err_msg=k)
+
+
 @pytest.mark.parametrize("occupancy", [0, 5, 6])
 def test_bucketed_short_instances_match_plain_launches(occupancy):
     # K-bucketed launches with k_max <= 20: K <= 12 in the 192-lane kernel, the rest in the
