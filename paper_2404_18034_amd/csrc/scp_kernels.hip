@@ -710,6 +710,21 @@ struct ColStore<float> {
         o[1] = p[3];
     }
 };
+// the same column kept in registers (the preparation kernel's FP32 thrust-only form)
+template <typename R>
+struct ColRegs {
+    R *unused;
+    R c[16];
+    __device__ __forceinline__ void put(int q, R v) { c[q] = v; }
+    __device__ __forceinline__ void get_lo(R (&o)[8]) const
+    {
+        for (int q = 0; q < 8; ++q) o[q] = c[q];
+    }
+    __device__ __forceinline__ void get_hi(R (&o)[8]) const
+    {
+        for (int q = 0; q < 8; ++q) o[q] = c[8 + q];
+    }
+};
 template <>
 struct ColStore<double> {
     static constexpr int LDS_STRIDE = 0;
@@ -989,7 +1004,11 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     // -------------------- load the subproblem's blocks --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
     R rowA[NX], rowBm[NUC], rowBp[NUC], rowBq[NUC];
-    ColStore<R> colA{reinterpret_cast<R *>(smem_raw + Lds::BYTES) + t * ColStore<R>::LDS_STRIDE};
+    // FP32 with thrust only: the column in registers (76 VGPRs, no LDS for it, so three 8-wave
+    // workgroups share a CU); otherwise in LDS as in the subproblem kernel
+    constexpr bool COLREG = sizeof(R) == 4 && NUC == NU;
+    using ColT = std::conditional_t<COLREG, ColRegs<R>, ColStore<R>>;
+    ColT colA{reinterpret_cast<R *>(smem_raw + Lds::BYTES) + t * ColStore<R>::LDS_STRIDE};
     // colA: column i of A^-_k (transposed product); row*: row i of [A^-_k | B^-_k | B^+_k]
     // (forward product); rowBq: row i of B^+_{k-1} (control part of the transposed product)
     for (int q = 0; q < NX; ++q) {
@@ -1019,19 +1038,6 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             rowBqXB[s] = (bq && qb < NUC) ? blk[(long)(k - 1) * BLK + (NX + NUC + qb) * CST + i]
                                           : R(0);
         }
-    }
-
-    // FP64 iteration over FP32 blocks with the thrust-only layout: the row coefficients are
-    // widened once (exactly) and kept in FP64 registers; the column of A^-_k is widened term
-    // by term from LDS.  Otherwise (the torque layout: its register budget) every term widens.
-    constexpr bool WIDEN = sizeof(R) < sizeof(P) && NUC == NU;
-    using RW = std::conditional_t<WIDEN, P, R>;
-    RW rowAw[NX], rowBmw[NUC], rowBpw[NUC], rowBqw[NUC];
-    for (int q = 0; q < NX; ++q) rowAw[q] = RW(rowA[q]);
-    for (int q = 0; q < NUC; ++q) {
-        rowBmw[q] = RW(rowBm[q]);
-        rowBpw[q] = RW(rowBp[q]);
-        rowBqw[q] = RW(rowBq[q]);
     }
 
     // -------------------- customized power iteration --------------------
@@ -1066,11 +1072,11 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     double sstar = sigma;
     const int nw = (blockDim.x + 63) >> 6;
     for (int it = 1; it <= a.power_iters_max; ++it) {
-        if constexpr (sizeof(R) < sizeof(P) && !WIDEN) {
-            keep_narrow(rowAw);
-            keep_narrow(rowBmw);
-            keep_narrow(rowBpw);
-            keep_narrow(rowBqw);
+        if constexpr (sizeof(R) < sizeof(P)) {
+            keep_narrow(rowA);
+            keep_narrow(rowBm);
+            keep_narrow(rowBp);
+            keep_narrow(rowBq);
             if constexpr (NUC == NU_MAX) {
                 keep_narrow(rowBmXA);
                 keep_narrow(rowBqXA);
@@ -1082,16 +1088,16 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
         if (wact) {
             // A^-_k z_k - z_{k+1} + B^-_k u_k + B^+_k u_{k+1} + (mu+ - mu-), divided by sigma
             const P zxn = sl[Lds::Z + 16], zun = sl[Lds::U + 16];
-            P r = pw_dot<RW, P, 0, 1, NX>(rowAw, zx, P(0));
+            P r = pw_dot<R, P, 0, 1, NX>(rowA, zx, P(0));
             r -= zxn;
             if constexpr (NUC == NU) {
-                r = pw_dot<RW, P, 0, 4, NU>(rowBmw, zu, r);
-                r = pw_dot<RW, P, 0, 4, NU>(rowBpw, zun, r);
+                r = pw_dot<R, P, 0, 4, NU>(rowBm, zu, r);
+                r = pw_dot<R, P, 0, 4, NU>(rowBp, zun, r);
             } else {
-                r = pw_dot<RW, P, 4, 1, 4>(rowBmw, zu, r);
-                r = pw_dot<RW, P, 8, 1, 3>(rowBmw + 4, zu, r);
-                r = pw_dot<RW, P, 4, 1, 4>(rowBpw, zun, r);
-                r = pw_dot<RW, P, 8, 1, 3>(rowBpw + 4, zun, r);
+                r = pw_dot<R, P, 4, 1, 4>(rowBm, zu, r);
+                r = pw_dot<R, P, 8, 1, 3>(rowBm + 4, zu, r);
+                r = pw_dot<R, P, 4, 1, 4>(rowBp, zun, r);
+                r = pw_dot<R, P, 8, 1, 3>(rowBp + 4, zun, r);
             }
             r += dmu;
             if constexpr (sizeof(P) == 8) {
@@ -1128,7 +1134,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             // u part: sum over rows i of B^-_k[i][q] phi_k[i] + B^+_{k-1}[i][q] phi_{k-1}[i]
             if constexpr (NUC == NU) {
                 P gq[NU];
-                for (int q = 0; q < NU; ++q) gq[q] = P(rowBmw[q]) * ph + P(rowBqw[q]) * phm;
+                for (int q = 0; q < NU; ++q) gq[q] = P(rowBm[q]) * ph + P(rowBq[q]) * phm;
                 const P zq = row_reduce_scatter4<P>(gq, i);
                 zu = node ? zq : P(0);
             } else {
@@ -1169,9 +1175,11 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     }
 }
 
-// FP32: registers bounded for five waves per SIMD (four 5-wave workgroups per CU)
+// FP32: registers bounded for six waves per SIMD with thrust only (three 8-wave workgroups per
+// CU), five with the torque
 template <typename R, typename P, int MAXT, int NUC = NU>
-__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
+__global__ void __launch_bounds__(MAXT)
+    __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (NUC == NU ? 6 : 5) : 1)))
 prepare_kernel(Args<R> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1764,7 +1772,7 @@ static size_t qp_smem_bytes_at(int maxt, int kmax, size_t rsize, bool lean = fal
 size_t qp_smem_bytes(int kmax, size_t rsize) { return qp_smem_bytes_at(qp_maxt(kmax), kmax, rsize); }
 // dynamic LDS bytes of the preparation kernel (rsize: the working precision, psize: that of
 // the power iteration)
-static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
+static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize, int nu)
 {
     const int maxt = qp_maxt(kmax);
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
@@ -1775,6 +1783,7 @@ static size_t prep_smem_bytes(int kmax, size_t rsize, size_t psize)
                                     : (maxt == 320 ? PrepLds<double, 320>::BYTES
                                                    : (maxt == 512 ? PrepLds<double, 512>::BYTES
                                                                   : PrepLds<double, 1024>::BYTES));
+    if (rsize == 4 && nu == NU) return stage;  // the column in registers
     return stage + rsize * KR * 16 * col;
 }
 
@@ -1933,7 +1942,7 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const size_t smem_full = qp_smem_bytes(cfg.kmax, sizeof(R));
     // power iteration in FP64 unless the FP32 variant is selected (FP32 path only)
     const bool pw32 = sizeof(R) == 4 && cfg.power_fp32;
-    const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R), pw32 ? 4 : 8);
+    const size_t psmem = prep_smem_bytes(cfg.kmax, sizeof(R), pw32 ? 4 : 8, NUC);
     const bool persistent = cfg.persistent_blocks > 0;
     a.use_order = cfg.ordered ? 1 : 0;
     a.split = 0;
