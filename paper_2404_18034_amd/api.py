@@ -280,8 +280,15 @@ class BatchSolver:
         self._check(load().scp_batch_mode(self.handle, ctypes.byref(m), ctypes.byref(o)))
         return m.value, o.value
 
+    def _on_device(self, name, v):
+        if v.device.type != "cuda" or v.device.index != self.device:
+            raise ScpError(2, "%s must be on cuda:%d" % (name, self.device))
+
     def _check_problem(self, prob):
         B = int(prob["x0"].shape[0])
+        for k in ("x0", "xf", "params", "K", "x_init", "u_init"):
+            if prob.get(k) is not None:
+                self._on_device(k, prob[k])
         for k, shape in (("x0", (B, NX)), ("xf", (B, NXF)), ("params", (B, NP))):
             v = prob[k]
             if tuple(v.shape) != shape or v.dtype != self.dtype or not v.is_contiguous():
@@ -311,6 +318,7 @@ class BatchSolver:
                                ("pipg_iters", (), t.int32), ("defect_inf", (), t.float64),
                                ("ctcs_viol", (), t.float64), ("objective", (), t.float64)):
             v = sol[k]
+            self._on_device(k, v)
             if (v.dim() != 1 + len(tail) or v.shape[0] < B or tuple(v.shape[1:]) != tail
                     or v.dtype != dtype or not v.is_contiguous()):
                 raise ScpError(2, "solution array %s must be a contiguous %s tensor of shape "
