@@ -798,6 +798,64 @@ __device__ __forceinline__ unsigned long long max_bits(double v)
 {
     return (unsigned long long)__double_as_longlong(v);
 }
+// Maximum over a wave of non-negative values, as its bit pattern, uniform over the wave.  FP32:
+// unsigned maxima of the patterns (monotone for non-negative values) over the row by DPP
+// (every lane of a row ends with the row's), then row 0 into row 1 and row 2 into row 3
+// (row_bcast:15), rows 0-1 into rows 2-3 (row_bcast:31): lane 63 holds the wave's.  FP64:
+// the row maxima, then the four rows' through scalar registers.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ unsigned int wave_max_bits(float v)
+{
+    unsigned u = __float_as_uint(v), r;
+    // each DPP step reads the previous step's result: two wait states between them
+    asm("s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_readlane_b32 %1, %0, 63"
+        : "+v"(u), "=s"(r));
+    return r;
+}
+// max(|a|, |b|, |c|): one instruction in FP32 (the operands are finite)
+__device__ __forceinline__ float absmax3(float a, float b, float c)
+{
+    float r;
+    asm("v_max3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ double absmax3(double a, double b, double c)
+{
+    return fmax(fmax(fabs(a), fabs(b)), fabs(c));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ unsigned long long wave_max_bits(double v)
+{
+    v = row_max<double>(v);
+    return max_bits(fmax(fmax(lane_value(v, 0), lane_value(v, 16)),
+                         fmax(lane_value(v, 32), lane_value(v, 48))));
+}
+__device__ __forceinline__ unsigned int uniform(unsigned int v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ unsigned long long uniform(unsigned long long v)
+{
+    return (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32 |
+           (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v);
+}
 template <typename R>
 __device__ __forceinline__ double from_max_bits(unsigned int b) { return double(__uint_as_float(b)); }
 template <typename R>
@@ -1211,7 +1269,7 @@ prepare_kernel(Args<R> a)
 // out, which takes the FP32 kernel from 95 to 79 VGPRs and its LDS from 59 to 48 KB at
 // K = 30, three workgroups per CU instead of two.
 template <typename R, int MAXT, bool FAIR = false, bool SD = false, int NUC = NU,
-          bool LEAN = false>
+          int LEAN = 0>
 __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
                                                 unsigned char *smem_raw)
 {
@@ -1227,7 +1285,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     const bool wact = ((t >> 6) << 2) < K;
 
     // LDS: the PIPG exchange arrays at fixed offsets, the reduction scratch, the column slots
-    using Lds = QpLds<R, MAXT, LEAN>;
+    using Lds = QpLds<R, MAXT, (LEAN > 0)>;
     const int KR = blockDim.x >> 4;  // rows of this workgroup (a multiple of 4)
     double *red = reinterpret_cast<double *>(smem_raw + Lds::BYTES);  // [16 waves * 8]
     // stopping-test maxima: two sets of six bit patterns (32-bit for FP32, 64-bit for FP64)
@@ -1387,7 +1445,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     __syncthreads();
 
     const int jmax = a.pipg_iters_max;
-    const int check = LEAN ? 0 : (a.early_exit ? a.pipg_check_every : 0);
+    const int check = LEAN == 1 ? 0 : (a.early_exit ? a.pipg_check_every : 0);
     const int pmask = LEAN ? 0 : a.node_projections;
     // state set of this lane: 1 dry mass (lane 0), 2 glide-slope cone (lanes 1-3),
     // 3 tilt disk (lanes 9-10), 4 rate ball (lanes 11-13); groups are masked by pmask
@@ -1587,24 +1645,25 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         // the other set is cleared for the next one.
         if (test) {
             const bool ucopy = uread;
-            const R xh = sl[Lds::PX], mup = sl[Lds::PMP], mum = sl[Lds::PMM];
-            const R uh = ucopy ? sl[Lds::PU] : R(0), unr = ucopy ? un : R(0);
-            const R ph = sl[Lds::PPH];
-            R m[6];
-            m[0] = fmax(fmax(fabs(xn), fabs(unr)), fmax(fabs(mupn), fabs(mumn)));
-            m[1] = fmax(fmax(fabs(xh), fabs(uh)), fmax(fabs(mup), fabs(mum)));
-            m[2] = fmax(fmax(fabs(xn - xh), fabs(unr - uh)), fmax(fabs(mupn - mup), fabs(mumn - mum)));
-            m[3] = fabs(phn);
-            m[4] = fabs(ph);
-            m[5] = fabs(phn - ph);
-            for (int q = 0; q < 6; ++q) m[q] = row_max<R>(m[q]);
-            if (i == 0)
-                for (int q = 0; q < 6; ++q) atomicMax(&chk[8 * cset + q], max_bits(m[q]));
+            const R xh = LEAN ? fxh : sl[Lds::PX], mup = LEAN ? fmup : sl[Lds::PMP];
+            const R mum = LEAN ? fmum : sl[Lds::PMM];
+            const R uh = ucopy ? (LEAN ? fuh : sl[Lds::PU]) : R(0), unr = ucopy ? un : R(0);
+            const R ph = LEAN ? fph : sl[Lds::PPH];
+            // the test takes the larger of the norms at j+1 and j, so each lane contributes
+            // the larger of its two magnitudes; one norm at a time (fewer live registers)
+            for (int q = 0; q < 4; ++q) {
+                const R m = q == 0 ? absmax3(absmax3(absmax3(xn, unr, mupn), mumn, xh), uh,
+                                             absmax3(mup, mum, R(0)))
+                          : q == 1 ? absmax3(absmax3(xn - xh, unr - uh, mupn - mup), mumn - mum, R(0))
+                          : q == 2 ? absmax3(phn, ph, R(0)) : fabs(phn - ph);
+                const auto w = wave_max_bits(m);
+                if ((t & 63) == 0) atomicMax(&chk[8 * cset + q], w);
+            }
             if (t == 0)
-                for (int q = 0; q < 6; ++q) chk[8 * (cset ^ 1) + q] = 0;
+                for (int q = 0; q < 4; ++q) chk[8 * (cset ^ 1) + q] = 0;
         }
         if constexpr (LEAN) {
-            if (it == jmax) {
+            if (test || before_test || it == jmax) {
                 fxh = xn;
                 fuh = un;
                 fmup = mupn;
@@ -1622,12 +1681,13 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
         __syncthreads();
         iters = it;
         if (test) {
-            double n[6];
-            for (int q = 0; q < 6; ++q) n[q] = from_max_bits<R>(chk[8 * cset + q]);
+            // the workgroup's norms are uniform: scalar registers
+            double n[4];
+            for (int q = 0; q < 4; ++q) n[q] = from_max_bits<R>(uniform(chk[8 * cset + q]));
             since = 0;
             cset ^= 1;
-            if (n[2] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[0], n[1]) &&
-                n[5] <= a.pipg_eps_abs + a.pipg_eps_rel * fmax(n[3], n[4]))
+            if (n[1] <= a.pipg_eps_abs + a.pipg_eps_rel * n[0] &&
+                n[3] <= a.pipg_eps_abs + a.pipg_eps_rel * n[2])
                 break;
         }
     }
@@ -1668,7 +1728,7 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
 // ------------------------------------------------------------------------------------------
 
 // WPE: minimum waves per SIMD the register allocation must allow (1: no constraint).
-template <typename R, int MAXT, int WPE, bool SD = false, int NUC = NU, bool LEAN = false>
+template <typename R, int MAXT, int WPE, bool SD = false, int NUC = NU, int LEAN = 0>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE)))
 subproblem_kernel(Args<R> a)
 {
@@ -1801,7 +1861,7 @@ static void launch_prepare(int maxt, int B, int threads, size_t smem, hipStream_
 
 // Subproblem launch with the register-budget variant: occupancy 4, 5 or 6 bounds the kernel
 // to that many waves per SIMD (FP32 only; FP64 always uses the compiler's choice).
-template <typename R, int MAXT, int NUC, bool LEAN>
+template <typename R, int MAXT, int NUC, int LEAN>
 static void launch_subproblem_v(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
                                 const Args<R> &a)
 {
@@ -1824,10 +1884,12 @@ static void launch_subproblem_v(int occupancy, int B, int threads, size_t smem, 
     }
     subproblem_kernel<R, MAXT, 1, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
-// smem must be the dynamic LDS of the variant launched (qp_smem_bytes_at with `lean`)
+// smem must be the dynamic LDS of the variant launched (qp_smem_bytes_at with `lean` > 0);
+// lean: 0 the general kernel, 1 the lean one without a stopping test, 2 with it (FP32,
+// thrust and dilation only)
 template <typename R, int MAXT, int NUC = NU>
 static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hipStream_t stream,
-                              const Args<R> &a, bool lean)
+                              const Args<R> &a, int lean)
 {
     if (NUC == NU && a.scalar_dilation) {
         // one variant: FP32 bounded to six waves per SIMD (with the priority rotation), FP64
@@ -1836,10 +1898,16 @@ static void launch_subproblem(int occupancy, int B, int threads, size_t smem, hi
             <<<dim3(B), dim3(threads), smem, stream>>>(a);
         return;
     }
+    if constexpr (sizeof(R) == 4 && NUC == NU) {
+        if (lean == 2) {
+            launch_subproblem_v<R, MAXT, NUC, 2>(occupancy, B, threads, smem, stream, a);
+            return;
+        }
+    }
     if (lean)
-        launch_subproblem_v<R, MAXT, NUC, true>(occupancy, B, threads, smem, stream, a);
+        launch_subproblem_v<R, MAXT, NUC, 1>(occupancy, B, threads, smem, stream, a);
     else
-        launch_subproblem_v<R, MAXT, NUC, false>(occupancy, B, threads, smem, stream, a);
+        launch_subproblem_v<R, MAXT, NUC, 0>(occupancy, B, threads, smem, stream, a);
 }
 
 template <typename R, int NUC = NU>
@@ -1935,10 +2003,12 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const long nd = (long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS;
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
-    // the lean variant where the node-wise sets are off and no stopping test can fire
-    const bool lean = !cfg.scalar_dilation && cfg.node_projections == 0 &&
-                      (!cfg.early_exit || cfg.pipg_check_every > cfg.pipg_iters_max);
-    const size_t smem = qp_smem_bytes_at(maxt, cfg.kmax, sizeof(R), lean);
+    // the lean variants where the node-wise sets are off: no stopping test can fire
+    // (variant 1), or where a test can fire, FP32 with thrust and dilation (variant 2)
+    const bool no_test = !cfg.early_exit || cfg.pipg_check_every > cfg.pipg_iters_max;
+    const int lean = (cfg.scalar_dilation || cfg.node_projections != 0) ? 0
+                   : no_test ? 1 : (sizeof(R) == 4 && NUC == NU) ? 2 : 0;
+    const size_t smem = qp_smem_bytes_at(maxt, cfg.kmax, sizeof(R), lean > 0);
     const size_t smem_full = qp_smem_bytes(cfg.kmax, sizeof(R));
     // power iteration in FP64 unless the FP32 variant is selected (FP32 path only)
     const bool pw32 = sizeof(R) == 4 && cfg.power_fp32;
@@ -1947,8 +2017,8 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.use_order = cfg.ordered ? 1 : 0;
     a.split = 0;
     const bool bucketed = cfg.bucketed && cfg.ordered && cfg.kmax > 12;
-    const size_t smem20 = qp_smem_bytes_at(320, 20, sizeof(R), lean);
-    const size_t smem12 = qp_smem_bytes_at(192, 12, sizeof(R), lean);
+    const size_t smem20 = qp_smem_bytes_at(320, 20, sizeof(R), lean > 0);
+    const size_t smem12 = qp_smem_bytes_at(192, 12, sizeof(R), lean > 0);
     if (persistent || cfg.ordered) {
         const unsigned nb = (unsigned)((cfg.B + 255) / 256);
         order_histogram<R><<<dim3(nb), dim3(256), 0, stream>>>(a);

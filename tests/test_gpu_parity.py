@@ -375,21 +375,34 @@ def test_dispatch_modes_match_plain_launches(mode, occupancy):
     s.close()
 
 
-@pytest.mark.parametrize("dtype,k_max", [("f32", 30), ("f32", 20), ("f64", 30)])
-def test_lean_variant_matches_the_general_kernel(dtype, k_max):
-    # without node-wise sets and with no stopping test that can fire, the library launches the
-    # lean subproblem kernel (no projection or stopping-test code); with a stopping test at the
-    # last PIPG step it launches the general one, which must then compute the same thing bit
-    # for bit (SCP tolerances at zero so that neither run stops early)
-    print("case: lean vs general kernel, %s, k_max %d" % (dtype, k_max), flush=True)
-    base = dict(scp_iters_max=4, pipg_iters_max=300, scp_tol=0.0, feas_tol=0.0)
+@pytest.mark.parametrize("dtype,k_max,test", [("f32", 30, 0), ("f32", 20, 0), ("f64", 30, 0),
+                                               ("f32", 30, 1), ("f32", 20, 1), ("f32", 12, 1),
+                                               ("f64", 20, 1)])
+def test_lean_variant_matches_the_general_kernel(dtype, k_max, test):
+    # without node-wise sets plain launches run a lean subproblem kernel (projection code
+    # compiled out; in FP32 the stopping test keeps the previous iterate in registers, FP64 is
+    # lean only without a test); the persistent grid (mode 3) runs the general kernel body,
+    # which must compute the same bit for bit.  Without a test: fixed work, SCP tolerances at
+    # zero so that no instance stops early.  With one: every ten steps, so that PIPG stops at
+    # different steps across instances and subproblems
+    print("case: lean vs general kernel, %s, k_max %d, test %d" % (dtype, k_max, test), flush=True)
+    if test:
+        cfg = I.solver_settings("C2", scp_iters_max=5, pipg_iters_max=1000, pipg_check_every=10)
+    else:
+        cfg = I.solver_settings("C2", early_exit=0, scp_iters_max=4, pipg_iters_max=300,
+                                scp_tol=0.0, feas_tol=0.0)
     inst = I.make_instances("C2", B=48)
     inst["K"] = np.minimum(inst["K"], k_max).astype(np.int32)
-    lean = _gpu(I.solver_settings("C2", early_exit=0, **base), inst, dtype, k_max=k_max)
-    full = _gpu(I.solver_settings("C2", early_exit=1, pipg_check_every=300, **base), inst, dtype,
-                k_max=k_max)
-    ran = lean["status"] == 1
-    assert ran.sum() >= 40 and np.all(lean["pipg_iters"][ran] == 4 * 300)
+    lean = _gpu(dict(cfg, mode=0), inst, dtype, k_max=k_max)
+    full = _gpu(dict(cfg, mode=3), inst, dtype, k_max=k_max)
+    if test:
+        # (the oracle on these instances: 40, 48 and 48 of them stop early at k_max 30, 20
+        # and 12, with 36 to 40 distinct totals)
+        assert np.all(lean["pipg_iters"] % 10 == 0) and len(np.unique(lean["pipg_iters"])) > 20
+        assert np.sum(lean["pipg_iters"] < 1000 * lean["scp_iters"]) >= 32
+    else:
+        ran = lean["status"] == 1
+        assert ran.sum() >= 40 and np.all(lean["pipg_iters"][ran] == 4 * 300)
     for k in lean:
         np.testing.assert_array_equal(lean[k], full[k], err_msg=k)
 
