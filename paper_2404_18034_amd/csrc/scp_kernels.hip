@@ -798,32 +798,69 @@ __device__ __forceinline__ unsigned long long max_bits(double v)
 {
     return (unsigned long long)__double_as_longlong(v);
 }
-// Maximum over a wave of non-negative values, as its bit pattern, uniform over the wave.  FP32:
-// unsigned maxima of the patterns (monotone for non-negative values) over the row by DPP
-// (every lane of a row ends with the row's), then row 0 into row 1 and row 2 into row 3
-// (row_bcast:15), rows 0-1 into rows 2-3 (row_bcast:31): lane 63 holds the wave's.  FP64:
-// the row maxima, then the four rows' through scalar registers.  Every lane of the wave must
-// be active.
-__device__ __forceinline__ unsigned int wave_max_bits(float v)
+// Maximum over a wave of non-negative values, as its bit pattern.  FP32: unsigned maxima of
+// the patterns (monotone for non-negative values) over the row by DPP (every lane of a row ends
+// with the row's), then row 0 into row 1 and row 2 into row 3 (row_bcast:15), rows 0-1 into
+// rows 2-3 (row_bcast:31): lane 63 holds the wave's.  FP64: the row maxima, then the four
+// rows' through scalar registers (uniform).  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_value(double v, int l)
 {
-    unsigned u = __float_as_uint(v), r;
-    // each DPP step reads the previous step's result: two wait states between them
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ unsigned long long wave_max_bits(double v)
+{
+    v = row_max<double>(v);
+    return max_bits(fmax(fmax(lane_value(v, 0), lane_value(v, 16)),
+                         fmax(lane_value(v, 32), lane_value(v, 48))));
+}
+// Four such maxima at once, added to dst[0..3] (LDS, bit patterns) by atomic maxima from the
+// wave's lane 63 (`leader`).  The four DPP chains are interleaved: three instructions separate
+// each result from its next read, more than the two wait states a DPP read needs.  The atomics
+// complete before the block ends (the barrier after them must see them).
+__device__ __forceinline__ void wave_max_to_lds(float m0, float m1, float m2, float m3,
+                                                unsigned int *dst, bool leader)
+{
+    unsigned u0 = __float_as_uint(m0), u1 = __float_as_uint(m1), u2 = __float_as_uint(m2),
+             u3 = __float_as_uint(m3);
+#define SCP_DPP_MAX4(CTRL, MASK)                                                            \
+    "v_max_u32_dpp %0, %0, %0 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t"               \
+    "v_max_u32_dpp %1, %1, %1 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t"               \
+    "v_max_u32_dpp %2, %2, %2 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t"               \
+    "v_max_u32_dpp %3, %3, %3 " CTRL " row_mask:" MASK " bank_mask:0xf\n\t"
     asm("s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_max_u32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_readlane_b32 %1, %0, 63"
-        : "+v"(u), "=s"(r));
-    return r;
+        SCP_DPP_MAX4("quad_perm:[1,0,3,2]", "0xf")
+        SCP_DPP_MAX4("quad_perm:[2,3,0,1]", "0xf")
+        SCP_DPP_MAX4("row_half_mirror", "0xf")
+        SCP_DPP_MAX4("row_mirror", "0xf")
+        SCP_DPP_MAX4("row_bcast:15", "0xa")
+        SCP_DPP_MAX4("row_bcast:31", "0xc")
+        : "+v"(u0), "+v"(u1), "+v"(u2), "+v"(u3));
+#undef SCP_DPP_MAX4
+    if (leader) {
+        // the low 32 bits of a generic pointer into LDS are its LDS address
+        const unsigned a = (unsigned)(uintptr_t)dst;
+        asm volatile("ds_max_u32 %0, %1\n\t"
+                     "ds_max_u32 %0, %2 offset:4\n\t"
+                     "ds_max_u32 %0, %3 offset:8\n\t"
+                     "ds_max_u32 %0, %4 offset:12\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     :
+                     : "v"(a), "v"(u0), "v"(u1), "v"(u2), "v"(u3)
+                     : "memory");
+    }
+}
+__device__ __forceinline__ void wave_max_to_lds(double m0, double m1, double m2, double m3,
+                                                unsigned long long *dst, bool)
+{
+    const unsigned long long w0 = wave_max_bits(m0), w1 = wave_max_bits(m1),
+                             w2 = wave_max_bits(m2), w3 = wave_max_bits(m3);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&dst[0], w0);
+        atomicMax(&dst[1], w1);
+        atomicMax(&dst[2], w2);
+        atomicMax(&dst[3], w3);
+    }
 }
 // max(|a|, |b|, |c|): one instruction in FP32 (the operands are finite)
 __device__ __forceinline__ float absmax3(float a, float b, float c)
@@ -835,17 +872,6 @@ __device__ __forceinline__ float absmax3(float a, float b, float c)
 __device__ __forceinline__ double absmax3(double a, double b, double c)
 {
     return fmax(fmax(fabs(a), fabs(b)), fabs(c));
-}
-__device__ __forceinline__ double lane_value(double v, int l)
-{
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ unsigned long long wave_max_bits(double v)
-{
-    v = row_max<double>(v);
-    return max_bits(fmax(fmax(lane_value(v, 0), lane_value(v, 16)),
-                         fmax(lane_value(v, 32), lane_value(v, 48))));
 }
 __device__ __forceinline__ unsigned int uniform(unsigned int v)
 {
@@ -1650,15 +1676,11 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
             const R uh = ucopy ? (LEAN ? fuh : sl[Lds::PU]) : R(0), unr = ucopy ? un : R(0);
             const R ph = LEAN ? fph : sl[Lds::PPH];
             // the test takes the larger of the norms at j+1 and j, so each lane contributes
-            // the larger of its two magnitudes; one norm at a time (fewer live registers)
-            for (int q = 0; q < 4; ++q) {
-                const R m = q == 0 ? absmax3(absmax3(absmax3(xn, unr, mupn), mumn, xh), uh,
-                                             absmax3(mup, mum, R(0)))
-                          : q == 1 ? absmax3(absmax3(xn - xh, unr - uh, mupn - mup), mumn - mum, R(0))
-                          : q == 2 ? absmax3(phn, ph, R(0)) : fabs(phn - ph);
-                const auto w = wave_max_bits(m);
-                if ((t & 63) == 0) atomicMax(&chk[8 * cset + q], w);
-            }
+            // the larger of its two magnitudes
+            const R m0 = absmax3(absmax3(absmax3(xn, unr, mupn), mumn, xh), uh, absmax3(mup, mum, R(0)));
+            const R m1 = absmax3(absmax3(xn - xh, unr - uh, mupn - mup), mumn - mum, R(0));
+            const R m2 = absmax3(phn, ph, R(0)), m3 = fabs(phn - ph);
+            wave_max_to_lds(m0, m1, m2, m3, &chk[8 * cset], (t & 63) == 63);
             if (t == 0)
                 for (int q = 0; q < 4; ++q) chk[8 * (cset ^ 1) + q] = 0;
         }
@@ -1751,7 +1773,8 @@ subproblem_kernel(Args<R> a)
     }
     const int b = a.use_order ? __builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
     // with four 5-wave workgroups per CU (WPE >= 6) the priority rotation keeps them abreast
-    subproblem_body<R, MAXT, (WPE >= 6), SD, NUC, LEAN>(a, b, smem_raw);
+    // (not in the lean variant with the stopping test: measured slower there)
+    subproblem_body<R, MAXT, (WPE >= 6 && LEAN != 2), SD, NUC, LEAN>(a, b, smem_raw);
 }
 
 // Persistent form: a fixed grid whose workgroups pop instances from a queue (one int32
