@@ -7,6 +7,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace scp {
 
 constexpr int NX = 15;
@@ -16,6 +18,22 @@ constexpr int NP = 24;
 constexpr int NXF = 13;
 constexpr int IY = 14;
 constexpr double NORM_EPS = 1e-4;  // below this a norm's derivative is taken as 0
+
+// Quotient and square root as the model takes them: in FP32 the hardware reciprocal and square
+// root (v_rcp_f32, v_sqrt_f32, about 1 ulp each, one instruction instead of a correctly
+// rounded sequence), in every other type the correctly rounded operations.
+__device__ __forceinline__ float mdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float msqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+template <typename T>
+__device__ __forceinline__ T mdiv(const T &a, const T &b)
+{
+    return a / b;
+}
+template <typename T>
+__device__ __forceinline__ T msqrt(const T &v)
+{
+    return sqrt(v);
+}
 
 // Vehicle data used inside the model, with the trigonometric constants folded once.
 template <typename R>
@@ -37,15 +55,21 @@ __device__ __forceinline__ Vehicle<R> load_vehicle(const R *p)
     for (int i = 0; i < 3; ++i) {
         v.g[i] = p[3 + i];
         v.J[i] = p[6 + i];
-        v.Jinv[i] = R(1) / p[6 + i];
+        v.Jinv[i] = mdiv(R(1), p[6 + i]);
         v.rT[i] = p[9 + i];
     }
     v.T_min = p[12];
     v.T_max = p[13];
-    // trigonometric constants in double, then rounded to R
-    v.sec_delta = R(1.0 / cos(double(p[14])));
-    v.tan_gamma = R(tan(double(p[15])));
-    v.tilt_c = R(1.0 - cos(double(p[16])));
+    // trigonometric constants: in FP32 directly (a few ulp), otherwise in double, rounded to R
+    if constexpr (std::is_same<R, float>::value) {
+        v.sec_delta = mdiv(1.0f, cosf(p[14]));
+        v.tan_gamma = tanf(p[15]);
+        v.tilt_c = 1.0f - cosf(p[16]);
+    } else {
+        v.sec_delta = R(1.0 / cos(double(p[14])));
+        v.tan_gamma = R(tan(double(p[15])));
+        v.tilt_c = R(1.0 - cos(double(p[16])));
+    }
     v.w_max2 = p[17] * p[17];
     v.has_vmax = isfinite(double(p[22]));
     v.v_max2 = v.has_vmax ? p[22] * p[22] : R(0);
@@ -81,9 +105,9 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     const R a0 = C00 * T0 + C01 * T1 + C02 * T2;
     const R a1 = C10 * T0 + C11 * T1 + C12 * T2;
     const R a2 = C20 * T0 + C21 * T1 + C22 * T2;
-    const R im = R(1) / m;
+    const R im = mdiv(R(1), m);
 
-    const R Tn = sqrt(T0 * T0 + T1 * T1 + T2 * T2);
+    const R Tn = msqrt(T0 * T0 + T1 * T1 + T2 * T2);
     const R Jw0 = V.J[0] * w0, Jw1 = V.J[1] * w1, Jw2 = V.J[2] * w2;
 
     R F[NX];
@@ -108,7 +132,7 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
 
     // path constraints g (mass, glide slope, tilt, rate, gimbal, T_max, T_min, speed; the
     // speed row is the constant -1 without a speed bound)
-    const R lat = sqrt(x[2] * x[2] + x[3] * x[3]);
+    const R lat = msqrt(x[2] * x[2] + x[3] * x[3]);
     R g[9];
     g[0] = V.m_dry - m;
     g[1] = V.tan_gamma * lat - x[1];
@@ -156,7 +180,7 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
     const R da2 = dC20 * T0 + dC21 * T1 + dC22 * T2 + C20 * dT0 + C21 * dT1 + C22 * dT2;
     // the derivative of a norm is taken as 0 below NORM_EPS (the thrust projection can put T
     // exactly at the apex of the gimbal cone; its reconstruction carries rounding noise)
-    const R dTn = Tn > R(NORM_EPS) ? (T0 * dT0 + T1 * dT1 + T2 * dT2) / Tn : R(0);
+    const R dTn = Tn > R(NORM_EPS) ? mdiv(T0 * dT0 + T1 * dT1 + T2 * dT2, Tn) : R(0);
     const R dim = -dm * im * im;
 
     R dF[NX];
@@ -182,7 +206,8 @@ __device__ __forceinline__ void f_jvp(const Vehicle<R> &V, const R *x, const R *
         for (int i = 0; i < 3; ++i) dF[11 + i] += V.Jinv[i] * du[3 + i];
     R dg[9];
     dg[0] = -dm;
-    dg[1] = (lat > R(NORM_EPS) ? V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]) / lat : R(0)) - dx[1];
+    dg[1] = (lat > R(NORM_EPS) ? mdiv(V.tan_gamma * (x[2] * dx[2] + x[3] * dx[3]), lat) : R(0)) -
+            dx[1];
     dg[2] = R(4) * (q2 * dq2 + q3 * dq3);
     dg[3] = R(2) * (w0 * dw0 + w1 * dw1 + w2 * dw2);
     dg[4] = dTn - dT0 * V.sec_delta;

@@ -38,6 +38,7 @@ struct Args {
     double power_eps_abs, power_eps_rel, power_buff;
     double w_cost, w_prox, w_ep, omega, rho;
     double px[NX], pu[NU_MAX];
+    double ipx[NX];  // 1 / px
     const R *x0, *xf, *params;
     const R *x_init, *u_init;  // optional first reference ([B][kmax][NX], [B][kmax][NUC])
     const int32_t *K;
@@ -182,7 +183,8 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const R h6 = h / R(6);
     const double hd = double(h), hhd = double(hh), h6d = double(h6);
 
-    double xs[NX], accx[NX];
+    // the stage input of the state is only taken in R: it is formed in double and rounded once
+    double accx[NX];
     R xin[NX], cs[NX], accc[NX], fx[NX], fc[NX], u[NUC], du[NUC];
     double fy;
 
@@ -195,7 +197,8 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
                 u[i] = lm * ua[i] + lp * ub[i];
                 du[i] = (i == uj) ? (plus ? lp : lm) : R(0);
             }
-            for (int i = 0; i < NX; ++i) xin[i] = R(st == 0 ? x[i] : xs[i]);
+            if (st == 0)
+                for (int i = 0; i < NX; ++i) xin[i] = R(x[i]);
             const R *cin = st == 0 ? col : cs;
             f_jvp<R, true, NUC>(V, xin, u, cin, du, fx, fy, fc);
             fx[IY] = R(0);  // y is advanced with the double-precision fy below
@@ -212,8 +215,8 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
             if (st < 3) {
                 const R hs = st == 2 ? h : hh;
                 const double hsd = st == 2 ? hd : hhd;
-                for (int i = 0; i < IY; ++i) xs[i] = x[i] + hsd * double(fx[i]);
-                xs[IY] = x[IY] + hsd * fy;
+                for (int i = 0; i < IY; ++i) xin[i] = R(x[i] + hsd * double(fx[i]));
+                xin[IY] = R(x[IY] + hsd * fy);
                 for (int i = 0; i < NX; ++i) cs[i] = col[i] + hs * fc[i];
             }
         }
@@ -227,12 +230,12 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     if (need_blocks) {
         R *dst = a.blocks + ib * BLK + c * CST;
         const double pc = c < NX ? a.px[c] : a.pu[(c - NX) % NUC];
-        for (int i = 0; i < NX; ++i) dst[i] = R(double(col[i]) * pc / a.px[i]);
+        for (int i = 0; i < NX; ++i) dst[i] = R(double(col[i]) * pc * a.ipx[i]);
         dst[NX] = R(0);
     }
     if (c == 0) {
         R *w = a.what + ib * DST;
-        for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) / a.px[i]);
+        for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) * a.ipx[i]);
         w[NX] = R(0);
         a.dy[ib] = x[IY] - double(xk[IY]);
     }
@@ -1962,7 +1965,10 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     a.w_ep = cfg.w_ep;
     a.omega = cfg.omega;
     a.rho = cfg.rho;
-    for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
+    for (int i = 0; i < NX; ++i) {
+        a.px[i] = cfg.px[i];
+        a.ipx[i] = 1.0 / cfg.px[i];
+    }
     for (int i = 0; i < NU_MAX; ++i) a.pu[i] = i < NUC ? cfg.pu[i] : 1.0;
     a.x0 = static_cast<const R *>(prob.x0);
     a.x_init = static_cast<const R *>(prob.x_init);
@@ -2142,7 +2148,10 @@ static hipError_t discretize_at_typed(const Config &cfg, const void *x, const vo
     a.B = cfg.B;
     a.kmax = cfg.kmax;
     a.rk4_substeps = cfg.rk4_substeps;
-    for (int i = 0; i < NX; ++i) a.px[i] = cfg.px[i];
+    for (int i = 0; i < NX; ++i) {
+        a.px[i] = cfg.px[i];
+        a.ipx[i] = 1.0 / cfg.px[i];
+    }
     for (int i = 0; i < NU_MAX; ++i) a.pu[i] = i < NU ? cfg.pu[i] : 1.0;
     a.params = static_cast<const R *>(prob.params);
     a.K = prob.K;
@@ -2167,8 +2176,8 @@ hipError_t launch_discretize_at(const Config &cfg, const void *x, const void *u,
 }
 
 // ------------------------------------------------------------------------------------------
-// Multi-start selection (the paper's Conclusion: several initial guesses per problem, solved
-// in parallel, the converged trajectory of lowest cost kept).  One 64-lane workgroup per
+// Multi-start selection (named as future work in the paper's Conclusion): each problem is run
+// from several starts and, of the starts that converge, the one of lowest cost is kept.  One 64-lane workgroup per
 // problem: every lane scans the problem's starts (the same loads, so every lane reaches the
 // same choice without an exchange), lane 0 writes the choice and the scalar outputs, and the
 // workgroup copies the chosen trajectory.
