@@ -18,8 +18,10 @@
 //                   alpha_mdot and T_max (the only entries of theta the discretization sees;
 //                   x0 and m_wet enter through the initial boundary value alone).
 //   tangent_kernel  alternative to the reverse sweep (settings.grad_rk4_tangent): the RK4 run
-//                   on two-direction dual numbers gives the tangents of the blocks and defect
-//                   along (alpha_mdot, T_max), contracted with the adjoints in grad_kernel.
+//                   on one-direction dual numbers along alpha_mdot, with two quadratures for
+//                   T_max, gives the tangents of the blocks and defect along (alpha_mdot,
+//                   T_max) in the working precision, contracted with the adjoints in
+//                   grad_kernel.
 // Every projection is differentiated on the branch the forward evaluation takes; a kink is
 // given the derivative of that branch (the derivative of max(0, .) at 0 is that of the
 // clamped side).
@@ -108,12 +110,50 @@ __device__ __forceinline__ Vehicle<Dual<double, N>> lift_vehicle(const Vehicle<d
 }
 
 // ------------------------------------------------------------------------------------------
-// Tangents of the discretization with respect to (alpha_mdot, T_max), in double.
+// Tangents of the discretization with respect to (alpha_mdot, T_max), in the working precision.
+//
+// alpha_mdot enters the mass rate, so it reaches the whole state and every column: the RK4
+// run of (x, column) is carried on one-direction dual numbers along it.  T_max enters only the
+// CTCS integrand (the row ||T|| - T_max), which no other component reads, so its tangents
+// vanish except in the y entries of the state and of the column, and those obey quadratures:
+//     d/dt (dy/dT_max)      = s d([g]_+^2)/dT_max            = -2 s [g]_+
+//     d/dt (dcol_y/dT_max)  = d/dT_max of the y row of the column's slope
+//                           = -2 ds [g]_+ - 2 s 1{g > 0} dTn,
+// with g = ||T|| - T_max, s the dilation, (dT, ds) the column's control direction and dTn the
+// derivative of ||T|| along dT; they run with the same RK4 weights.
 // ------------------------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
+// Vehicle data on one-direction dual numbers, seeded on alpha_mdot.
+template <typename T>
+__device__ __forceinline__ Vehicle<Dual<T, 1>> lift_alpha(const Vehicle<T> &W)
 {
-    using D = Dual<double, 2>;
+    using D = Dual<T, 1>;
+    Vehicle<D> V;
+    V.m_dry = D(double(W.m_dry));
+    V.alpha = seed<T, 1>(W.alpha, 0, T(1));
+    for (int q = 0; q < 3; ++q) {
+        V.g[q] = D(double(W.g[q]));
+        V.Jinv[q] = D(double(W.Jinv[q]));
+        V.J[q] = D(double(W.J[q]));
+        V.rT[q] = D(double(W.rT[q]));
+    }
+    V.T_min = D(double(W.T_min));
+    V.T_max = D(double(W.T_max));
+    V.sec_delta = D(double(W.sec_delta));
+    V.tan_gamma = D(double(W.tan_gamma));
+    V.tilt_c = D(double(W.tilt_c));
+    V.w_max2 = D(double(W.w_max2));
+    V.v_max2 = D(double(W.v_max2));
+    V.has_vmax = W.has_vmax;
+    V.g_max2 = D(double(W.g_max2));
+    V.has_gmax = W.has_gmax;
+    return V;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64)
+tangent_kernel(GradArgs<R> a)
+{
+    using D = Dual<R, 1>;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long per_b = (long)(a.kmax - 1) * COLS;
     const int b = (int)(gid / per_b);
@@ -123,10 +163,8 @@ __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
     const int K = a.K[b];
     if (k >= K - 1) return;
 
-    double pd[NP];
-    for (int q = 0; q < NP; ++q) pd[q] = double(a.params[(long)b * NP + q]);
-    const Vehicle<double> W = load_vehicle<double>(pd);
-    const Vehicle<D> V = lift_vehicle<2>(W, true);
+    const Vehicle<R> W = load_vehicle<R>(a.params + (long)b * NP);
+    const Vehicle<D> V = lift_alpha<R>(W);
 
     const R *xk = a.xbar + ((long)b * a.kmax + k) * NX;
     const R *uk = a.ubar + ((long)b * a.kmax + k) * NU;
@@ -135,51 +173,71 @@ __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
         x[i] = D(double(xk[i]));
         col[i] = D((c < NX && i == c) ? 1.0 : 0.0);
     }
-    double ua[NU], ub[NU];
+    R ua[NU], ub[NU];
     for (int i = 0; i < NU; ++i) {
-        ua[i] = double(uk[i]);
-        ub[i] = double(uk[NU + i]);
+        ua[i] = uk[i];
+        ub[i] = uk[NU + i];
     }
     const int uj = c < NX ? -1 : (c - NX) % NU;
     const bool plus = c >= NX + NU;
-    const double dtau = 1.0 / double(K - 1);
+    const R dtau = R(1.0 / double(K - 1));
     const int nsub = a.rk4_substeps;
-    const double h = dtau / nsub, hh = 0.5 * h, h6 = h / 6.0;
+    const R h = dtau / R(nsub), hh = R(0.5) * h, h6 = h / R(6);
 
-    D xs[NX], cs[NX], accx[NX], accc[NX], fx[NX], fc[NX], u[NU], du[NU];
+    R yT = R(0), cyT = R(0);  // tangents along T_max of y and of the column's y entry
+    D xn[NX], cn[NX], xin[NX], cin[NX], fx[NX], fc[NX];
     double fy;
     for (int n = 0; n < nsub; ++n) {
-        const double sig = n * h;
+        const R sig = R(n) * h;
+        R yTn = yT, cyTn = cyT;
         for (int st = 0; st < 4; ++st) {
-            const double sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
-            const double lp = sg / dtau, lm = 1.0 - lp;
+            const R sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
+            const R lp = sg / dtau, lm = R(1) - lp;
+            R u[NU], du[NU];
+            D uD[NU], duD[NU];
             for (int i = 0; i < NU; ++i) {
-                u[i] = D(lm * ua[i] + lp * ub[i]);
-                du[i] = D(i == uj ? (plus ? lp : lm) : 0.0);
+                u[i] = lm * ua[i] + lp * ub[i];
+                du[i] = i == uj ? (plus ? lp : lm) : R(0);
+                uD[i] = D(double(u[i]));
+                duD[i] = D(double(du[i]));
             }
-            f_jvp<D, true>(V, st == 0 ? x : xs, u, st == 0 ? col : cs, du, fx, fy, fc);
-            const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+            f_jvp<D, true>(V, st == 0 ? x : xin, uD, st == 0 ? col : cin, duD, fx, fy, fc);
+            // the T_max quadratures (the model's thrust norm and its derivative, same forms)
+            const R Tn = msqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            const R g5 = Tn - W.T_max, gp5 = g5 > R(0) ? g5 : R(0);
+            const R dTn = Tn > R(NORM_EPS) ? mdiv(u[0] * du[0] + u[1] * du[1] + u[2] * du[2], Tn)
+                                           : R(0);
+            const R s = u[NU - 1], ds = du[NU - 1];
+            const R ky = R(-2) * s * gp5;
+            const R kc = R(-2) * (ds * gp5 + (g5 > R(0) ? s * dTn : R(0)));
+            // RK4: the next value accumulates h/6 (k1 + 2 k2 + 2 k3 + k4)
+            const R w = (st == 0 || st == 3) ? h6 : R(2) * h6;
+            const D wd = D(double(w));
             for (int i = 0; i < NX; ++i) {
                 if (st == 0) {
-                    accx[i] = fx[i];
-                    accc[i] = fc[i];
+                    xn[i] = x[i] + wd * fx[i];
+                    cn[i] = col[i] + wd * fc[i];
                 } else {
-                    accx[i] += D(wgt) * fx[i];
-                    accc[i] += D(wgt) * fc[i];
+                    xn[i] += wd * fx[i];
+                    cn[i] += wd * fc[i];
                 }
             }
+            yTn += w * ky;
+            cyTn += w * kc;
             if (st < 3) {
-                const D hs = D(st == 2 ? h : hh);
+                const D hs = D(double(st == 2 ? h : hh));
                 for (int i = 0; i < NX; ++i) {
-                    xs[i] = x[i] + hs * fx[i];
-                    cs[i] = col[i] + hs * fc[i];
+                    xin[i] = x[i] + hs * fx[i];
+                    cin[i] = col[i] + hs * fc[i];
                 }
             }
         }
         for (int i = 0; i < NX; ++i) {
-            x[i] += D(h6) * accx[i];
-            col[i] += D(h6) * accc[i];
+            x[i] = xn[i];
+            col[i] = cn[i];
         }
+        yT = yTn;
+        cyT = cyTn;
     }
 
     const long ib = (long)b * (a.kmax - 1) + k;
@@ -187,16 +245,16 @@ __global__ void __launch_bounds__(64) tangent_kernel(GradArgs<R> a)
     R *d0 = a.dblk + (ib * 2) * BLK + c * CST;
     R *d1 = d0 + BLK;
     for (int i = 0; i < NX; ++i) {
-        d0[i] = R(col[i].d[0] * pc / a.px[i]);
-        d1[i] = R(col[i].d[1] * pc / a.px[i]);
+        d0[i] = R(double(col[i].d[0]) * pc / a.px[i]);
+        d1[i] = i == IY ? R(double(cyT) * pc / a.px[IY]) : R(0);
     }
     d0[NX] = d1[NX] = R(0);
     if (c == 0) {
         R *w0 = a.dwhat + (ib * 2) * DST;
         R *w1 = w0 + DST;
         for (int i = 0; i < NX; ++i) {
-            w0[i] = R(x[i].d[0] / a.px[i]);
-            w1[i] = R(x[i].d[1] / a.px[i]);
+            w0[i] = R(double(x[i].d[0]) / a.px[i]);
+            w1[i] = i == IY ? R(double(yT) / a.px[IY]) : R(0);
         }
         w0[NX] = w1[NX] = R(0);
     }

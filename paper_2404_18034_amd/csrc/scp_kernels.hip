@@ -1135,8 +1135,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     // neighbouring rows pass through this lane's LDS slots.  Two barriers per step.  The
     // iterate and the products are in P (FP64 by default: the blocks are widened term by
     // term); the squared norm is summed over each row in P and over the rows in FP64; sigma
-    // and the stopping test are FP64.  In the FP32 variant 1/sigma is rounded once per step
-    // and multiplied.
+    // and the stopping test are FP64.  1/sigma is formed once per step and multiplied.
     const int KR = (kmax + 3) / 4 * 4;
     const bool thlane = dual && i == IY;
     P zx = isx ? P(1) : P(0), zu = uval ? P(1) : P(0);
@@ -1187,14 +1186,10 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
                 r = pw_dot<R, P, 8, 1, 3>(rowBp + 4, zun, r);
             }
             r += dmu;
-            if constexpr (sizeof(P) == 8) {
-                ph = dual ? r / sigma : 0.0;
-                thv = thlane ? (zxn - zx) / sigma : 0.0;
-            } else {
-                const P isg = P(1.0 / sigma);
-                ph = dual ? r * isg : P(0);
-                thv = thlane ? (zxn - zx) * isg : P(0);
-            }
+            // 1/sigma once per step (uniform), rounded to P
+            const P isg = P(1.0 / sigma);
+            ph = dual ? r * isg : P(0);
+            thv = thlane ? (zxn - zx) * isg : P(0);
         }
         sl[Lds::P + 16] = ph;
         sl[Lds::T + 16] = thv;
