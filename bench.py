@@ -55,6 +55,7 @@ def pipg_flops_per_iter(K, n_u=4):
 
 KERNEL_SOURCES = ("paper_2404_18034_amd/csrc/scp_kernels.hip",
                   "paper_2404_18034_amd/csrc/scp_common.hpp",
+                  "paper_2404_18034_amd/csrc/scp_dpp.hpp",
                   "paper_2404_18034_amd/csrc/lander_model.hpp")
 # hardware-counter summaries of the subproblem kernel's HBM traffic, per workload
 TRAFFIC_FILES = {"C1": os.path.join(ROOT, "profiles", "subproblem_kernel_traffic_mc1024.txt"),

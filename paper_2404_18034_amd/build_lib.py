@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscp_batch.so")
 SOURCES = ["scp_kernels.hip", "scp_grad.hip", "scp_api.cpp"]
-HEADERS = ["scp_kernels.hpp", "scp_common.hpp", "lander_model.hpp", "dual.hpp"]
+HEADERS = ["scp_kernels.hpp", "scp_common.hpp", "scp_dpp.hpp", "lander_model.hpp", "dual.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
