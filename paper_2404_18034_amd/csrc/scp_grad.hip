@@ -27,12 +27,28 @@
 // clamped side).
 #include <math.h>
 
+#include <utility>
+
 #include "dual.hpp"
 #include "lander_model.hpp"
 #include "scp_common.hpp"
+#include "scp_dpp.hpp"
 #include "scp_kernels.hpp"
 
 namespace scp {
+
+// acc[q] += w * (value of lane q of this row), q < N: the broadcast form of an outer-product
+// accumulation (every lane of the row must take part)
+template <typename R, int... Q>
+__device__ __forceinline__ void bcast_axpy_impl(R *acc, R w, R v, std::integer_sequence<int, Q...>)
+{
+    ((acc[Q] = acc[Q] + w * rowb<Q>(v)), ...);
+}
+template <typename R, int N>
+__device__ __forceinline__ void bcast_axpy(R *acc, R w, R v)
+{
+    bcast_axpy_impl<R>(acc, w, v, std::make_integer_sequence<int, N>{});
+}
 
 // Offsets of one saved PIPG iterate (x~, u~, nu+, nu-, varphi, vartheta) in LDS and tape.
 struct StateLayout {
@@ -705,8 +721,7 @@ size_t grad_smem_bytes_r(int kmax, size_t rs)
 {
     const StateLayout L = state_layout(kmax);
     return 128 * sizeof(double) +
-           rs * ((size_t)L.len + 4 * 16 * kmax + 4 * NU * kmax + 128 * (kmax - 1) +
-                 DST * (kmax - 1) + kmax);
+           rs * ((size_t)L.len + 4 * 16 * kmax + 4 * NU * kmax + DST * (kmax - 1) + kmax);
 }
 
 template <typename R, int MAXT>
@@ -735,8 +750,7 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     R *UH = UP + kmax * NU;                               // [kmax][4]  fresh u^
     R *UB = UH + kmax * NU;                               // [kmax][4]  reference (original)
     R *UHB = UB + kmax * NU;                              // [kmax][4]  adjoint of u^
-    R *BC = UHB + kmax * NU;                              // [kmax-1][8][16] B^-, B^+ columns
-    R *RB = BC + (kmax - 1) * 128;                        // [kmax-1][16] adjoint of r
+    R *RB = UHB + kmax * NU;                              // [kmax-1][16] adjoint of r
     R *PB = RB + (kmax - 1) * DST;                        // [kmax] adjoint of the theta step
 
     const bool node = k < K;
@@ -757,9 +771,6 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
             S[L.MP + k * DST + i] = dual ? a.mup[ro] : R(0);
             S[L.MM + k * DST + i] = dual ? a.mum[ro] : R(0);
             S[L.PH + k * DST + i] = dual ? a.phi[ro] : R(0);
-            for (int c = 0; c < 8; ++c)
-                BC[(k * 8 + c) * 16 + i] =
-                    dual ? a.blocks[ib * BLK + (NX + c) * CST + i] : R(0);
         }
         if (i == IY) S[L.TH + k] = k < M ? a.th[(long)b * (kmax - 1) + k] : R(0);
     }
@@ -771,6 +782,19 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     for (int q = 0; q < NU; ++q) {
         rowBm[q] = dual ? a.blocks[ib * BLK + (NX + q) * CST + i] : R(0);
         rowBp[q] = dual ? a.blocks[ib * BLK + (NX + NU + q) * CST + i] : R(0);
+    }
+    // transposed control products: lane i supplies row i of B^-_k and of B^+_{k-1} with the
+    // components in the exchange order of row_reduce_scatter4i, which leaves the row sum of
+    // component q on lane q
+    R rowBmX[NU], rowBqX[NU];
+    {
+        const bool bq = node && k > 0 && i < NX;
+        const long ibq = (long)b * (kmax - 1) + (bq ? k - 1 : 0);
+        for (int s = 0; s < NU; ++s) {
+            const int q = xpermi(i, s);
+            rowBmX[s] = dual ? a.blocks[ib * BLK + (NX + q) * CST + i] : R(0);
+            rowBqX[s] = bq ? a.blocks[ibq * BLK + (NX + NU + q) * CST + i] : R(0);
+        }
     }
     const R wk = dual ? a.what[ib * DST + i] : R(0);
     R epsk = R(0);
@@ -823,28 +847,32 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     R a_mu = R(0), b_mu = R(0), mupn = R(0), mumn = R(0), phn = R(0), thp = R(0), thn = R(0);
 
     // projected gradient step on the primal variables: XP/UP (pre-projection), XH/UH
+    // (the row products below run on every lane of a row, with zeros where a lane holds no
+    // variable: a DPP exchange reads lanes that a branch would have switched off)
     auto primal = [&]() {
+        // phi_k of this lane's dynamics row and phi_{k-1} of the row above
+        const R vph = dual ? S[L.PH + k * DST + i] : R(0);
+        const R vphm = (node && k > 0 && i < NX) ? S[L.PH + (k - 1) * DST + i] : R(0);
+        // x: wprox x~ + cost + (A^-_k)^T phi_k, by row broadcasts of phi_k
+        const R xt = isx ? S[L.X + k * 16 + i] : R(0);
+        R g = rowdot15<R>(colA, vph, wprox * xt + cost);
+        // u: (B^-_k)^T phi_k + (B^+_{k-1})^T phi_{k-1}, reduced onto lane q
+        R gq[NU];
+        for (int s = 0; s < NU; ++s) gq[s] = rowBmX[s] * vph + rowBqX[s] * vphm;
+        const R gu = row_reduce_scatter4i<R>(gq);
         if (isx) {
-            R g = wprox * S[L.X + k * 16 + i] + cost;
-            if (k < M)
-                for (int q = 0; q < NX; ++q) g += colA[q] * S[L.PH + k * DST + q];
-            if (k > 0) g -= S[L.PH + (k - 1) * DST + i];
+            if (k > 0) g -= vphm;
             if (i == IY) {
                 if (k < M) g -= S[L.TH + k];
                 if (k > 0) g += S[L.TH + k - 1];
             }
-            const R xp = S[L.X + k * 16 + i] - alpha * g;
+            const R xp = xt - alpha * g;
             XP[k * 16 + i] = xp;
             XH[k * 16 + i] = fixed ? fixv : xp;
         }
         if (isu) {
-            R g = wprox * S[L.U + k * NU + i];
-            if (k < M)
-                for (int q = 0; q < NX; ++q) g += BC[(k * 8 + i) * 16 + q] * S[L.PH + k * DST + q];
-            if (k > 0)
-                for (int q = 0; q < NX; ++q)
-                    g += BC[((k - 1) * 8 + NU + i) * 16 + q] * S[L.PH + (k - 1) * DST + q];
-            UP[k * NU + i] = S[L.U + k * NU + i] - alpha * g;
+            const R ut = S[L.U + k * NU + i];
+            UP[k * NU + i] = ut - alpha * (wprox * ut + gu);
         }
         __syncthreads();
         if (node && i == 0 && (sets.mask & 15))
@@ -855,7 +883,18 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     };
 
     // dual step (needs XH, UH)
+    // extrapolated primal values 2 z^ - z~: this node's x (lane i), its u and node k+1's u
+    // (lanes q < 4)
+    auto vx_own = [&]() { return isx ? R(2) * XH[k * 16 + i] - S[L.X + k * 16 + i] : R(0); };
+    auto vu_own = [&]() { return isu ? R(2) * UH[k * NU + i] - S[L.U + k * NU + i] : R(0); };
+    auto vu_next = [&]() {
+        return (dual && i < NU) ? R(2) * UH[(k + 1) * NU + i] - S[L.U + (k + 1) * NU + i] : R(0);
+    };
     auto dual_step = [&]() {
+        // A^-_k, B^-_k, B^+_k times the extrapolated values, by row broadcasts
+        R r = rowdot15<R>(rowA, vx_own(), R(0));
+        r = rowdot_part<R, 0, NU>(rowBm, vu_own(), r);
+        r = rowdot_part<R, 0, NU>(rowBp, vu_next(), r);
         if (!dual) return;
         const R vph = S[L.PH + k * DST + i];
         const R np = S[L.MP + k * DST + i], nm = S[L.MM + k * DST + i];
@@ -863,13 +902,7 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
         b_mu = nm - alpha * (wep - vph);
         mupn = a_mu > R(0) ? a_mu : R(0);
         mumn = b_mu > R(0) ? b_mu : R(0);
-        R r = R(0);
-        for (int q = 0; q < NX; ++q) r += rowA[q] * (R(2) * XH[k * 16 + q] - S[L.X + k * 16 + q]);
         r -= R(2) * XH[(k + 1) * 16 + i] - S[L.X + (k + 1) * 16 + i];
-        for (int q = 0; q < NU; ++q) {
-            r += rowBm[q] * (R(2) * UH[k * NU + q] - S[L.U + k * NU + q]);
-            r += rowBp[q] * (R(2) * UH[(k + 1) * NU + q] - S[L.U + (k + 1) * NU + q]);
-        }
         r += (R(2) * mupn - np) - (R(2) * mumn - nm) + wk;
         phn = vph + beta * r;
         if (i == IY) {
@@ -976,11 +1009,15 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
                 }
             }
             __syncthreads();
+            // (A^-_k)^T rb_k and (B^-_k)^T rb_k + (B^+_{k-1})^T rb_{k-1}, by row broadcasts
+            const R rbm = (node && k > 0 && i < NX) ? RB[(k - 1) * DST + i] : R(0);
+            const R vbA = rowdot15<R>(colA, rb, R(0));
+            R gq[NU];
+            for (int s = 0; s < NU; ++s) gq[s] = rowBmX[s] * rb + rowBqX[s] * rbm;
+            const R vub = row_reduce_scatter4i<R>(gq);
             if (isx) {
-                R vb = R(0);
-                if (k < M)
-                    for (int q = 0; q < NX; ++q) vb += colA[q] * RB[k * DST + q];
-                if (k > 0) vb -= RB[(k - 1) * DST + i];
+                R vb = vbA;
+                if (k > 0) vb -= rbm;
                 if (i == IY) vb += beta * ((k > 0 ? PB[k - 1] : R(0)) - (k < M ? PB[k] : R(0)));
                 R xb_ = hxb + R(2) * vb;
                 nbx -= vb;
@@ -991,26 +1028,19 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
                 XHB[k * 16 + i] = xb_;
             }
             if (isu) {
-                R vub = R(0);
-                if (k < M)
-                    for (int q = 0; q < NX; ++q) vub += BC[(k * 8 + i) * 16 + q] * RB[k * DST + q];
-                if (k > 0)
-                    for (int q = 0; q < NX; ++q)
-                        vub += BC[((k - 1) * 8 + NU + i) * 16 + q] * RB[(k - 1) * DST + q];
                 UHB[k * NU + i] = hub + R(2) * vub;
                 nbu -= vub;
             }
+            // derivative of the blocks: rb_k times the extrapolated values (zero rb off the
+            // dynamics rows)
+            bcast_axpy<R, NX>(accA, rb, vx_own());
+            bcast_axpy<R, NU>(accBm, rb, vu_own());
+            bcast_axpy<R, NU>(accBp, rb, vu_next());
             if (dual) {
                 const R mpb = hmpb + R(2) * rb, mmb = hmmb - R(2) * rb;
                 nbmp -= rb;
                 nbmm += rb;
                 accW += rb;
-                for (int q = 0; q < NX; ++q)
-                    accA[q] += rb * (R(2) * XH[k * 16 + q] - S[L.X + k * 16 + q]);
-                for (int q = 0; q < NU; ++q) {
-                    accBm[q] += rb * (R(2) * UH[k * NU + q] - S[L.U + k * NU + q]);
-                    accBp[q] += rb * (R(2) * UH[(k + 1) * NU + q] - S[L.U + (k + 1) * NU + q]);
-                }
                 const R ab = a_mu > R(0) ? mpb : R(0), bb = b_mu > R(0) ? mmb : R(0);
                 nbmp += ab;
                 nbph -= alpha * ab;
@@ -1028,22 +1058,22 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
             // gradient step: x^pre = x~ - alpha g(x~, varphi, vartheta), likewise u
             if (isx) nbx += XHB[k * 16 + i] * (R(1) - alpha * wprox);
             if (isu) nbu += UHB[k * NU + i] * (R(1) - alpha * wprox);
+            {
+                // -alpha times the adjoints of this node's x^, u^ and of node k+1's u^
+                const R gxo = isx ? -alpha * XHB[k * 16 + i] : R(0);
+                const R guo = isu ? -alpha * UHB[k * NU + i] : R(0);
+                const R gun = (dual && i < NU) ? -alpha * UHB[(k + 1) * NU + i] : R(0);
+                const R ph = dual ? S[L.PH + k * DST + i] : R(0);
+                R s = dual ? alpha * XHB[(k + 1) * 16 + i] : R(0);
+                s = rowdot15<R>(rowA, gxo, s);
+                s = rowdot_part<R, 0, NU>(rowBm, guo, s);
+                s = rowdot_part<R, 0, NU>(rowBp, gun, s);
+                bcast_axpy<R, NX>(accA, ph, gxo);
+                bcast_axpy<R, NU>(accBm, ph, guo);
+                bcast_axpy<R, NU>(accBp, ph, gun);
+                if (dual) nbph += s;
+            }
             if (dual) {
-                const R ph = S[L.PH + k * DST + i];
-                R s = alpha * XHB[(k + 1) * 16 + i];
-                for (int q = 0; q < NX; ++q) {
-                    const R gq = -alpha * XHB[k * 16 + q];
-                    s += rowA[q] * gq;
-                    accA[q] += ph * gq;
-                }
-                for (int q = 0; q < NU; ++q) {
-                    const R g0 = -alpha * UHB[k * NU + q];
-                    const R g1 = -alpha * UHB[(k + 1) * NU + q];
-                    s += rowBm[q] * g0 + rowBp[q] * g1;
-                    accBm[q] += ph * g0;
-                    accBp[q] += ph * g1;
-                }
-                nbph += s;
                 if (i == IY) nbth += alpha * (XHB[k * 16 + IY] - XHB[(k + 1) * 16 + IY]);
             }
             tbx = nbx;
