@@ -721,7 +721,7 @@ size_t grad_smem_bytes_r(int kmax, size_t rs)
 {
     const StateLayout L = state_layout(kmax);
     return 128 * sizeof(double) +
-           rs * ((size_t)L.len + 4 * 16 * kmax + 4 * NU * kmax + DST * (kmax - 1) + kmax);
+           rs * ((size_t)2 * L.len + 4 * 16 * kmax + 4 * NU * kmax + DST * (kmax - 1) + kmax);
 }
 
 template <typename R, int MAXT>
@@ -741,7 +741,9 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     const StateLayout L = state_layout(kmax);
 
     double *red = reinterpret_cast<double *>(smem_raw);  // [16 waves * 8]
+    // the extrapolated iterate S lives in two buffers (each extrapolation writes the other)
     R *S = reinterpret_cast<R *>(red + 128);             // current extrapolated iterate
+    R *const S1 = S;
     R *XP = S + L.len;                                    // [kmax][16] x^ before projection
     R *XH = XP + kmax * 16;                               // [kmax][16] fresh x^
     R *XB = XH + kmax * 16;                               // [kmax][16] reference (original)
@@ -752,6 +754,7 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     R *UHB = UB + kmax * NU;                              // [kmax][4]  adjoint of u^
     R *RB = UHB + kmax * NU;                              // [kmax-1][16] adjoint of r
     R *PB = RB + (kmax - 1) * DST;                        // [kmax] adjoint of the theta step
+    R *const S2 = PB + kmax;                              // [L.len] second buffer of S
 
     const bool node = k < K;
     const bool isx = node && i < NX;
@@ -761,6 +764,7 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     const long ib = (long)b * (kmax - 1) + (dual ? k : 0);
 
     // -------------------- load the recorded starting point and the QP --------------------
+    for (int q = t; q < L.len; q += blockDim.x) S2[q] = R(0);
     if (k < kmax) {
         XB[k * 16 + i] = isx ? a.xbar[((long)b * kmax + k) * NX + i] : R(0);
         if (i < NU) UB[k * NU + i] = isu ? a.ubar[((long)b * kmax + k) * NU + i] : R(0);
@@ -872,13 +876,19 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
         }
         if (isu) {
             const R ut = S[L.U + k * NU + i];
-            UP[k * NU + i] = ut - alpha * (wprox * ut + gu);
+            const R up = ut - alpha * (wprox * ut + gu);
+            UP[k * NU + i] = up;
+            // the paper's set: the s box is the only control projection, taken in place
+            if (!sets.mask) UH[k * NU + i] = i == 3 ? fmin(fmax(up, slo), shi) : up;
         }
-        __syncthreads();
-        if (node && i == 0 && (sets.mask & 15))
-            xproj_fwd<R>(sets, XP + k * 16, XB + k * 16, pxr, fixed_node, k == K - 1 && k > 0,
-                         XH + k * 16);
-        if (node && i == 1) uproj_fwd<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UH + k * NU);
+        if (sets.mask) {
+            __syncthreads();
+            if (node && i == 0 && (sets.mask & 15))
+                xproj_fwd<R>(sets, XP + k * 16, XB + k * 16, pxr, fixed_node,
+                             k == K - 1 && k > 0, XH + k * 16);
+            if (node && i == 1)
+                uproj_fwd<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UH + k * NU);
+        }
         __syncthreads();
     };
 
@@ -914,17 +924,20 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
     };
 
     // extrapolation: S <- (1 - rho) S + rho (fresh iterate)
+    // into the other buffer, so that no lane still reading this step's S is overtaken; the
+    // entries no lane writes (no variable) are zero in both buffers
     auto extrapolate = [&]() {
-        __syncthreads();
-        if (isx) S[L.X + k * 16 + i] = omr * S[L.X + k * 16 + i] + rho * XH[k * 16 + i];
-        if (isu) S[L.U + k * NU + i] = omr * S[L.U + k * NU + i] + rho * UH[k * NU + i];
+        R *const Sn = S == S1 ? S2 : S1;
+        if (isx) Sn[L.X + k * 16 + i] = omr * S[L.X + k * 16 + i] + rho * XH[k * 16 + i];
+        if (isu) Sn[L.U + k * NU + i] = omr * S[L.U + k * NU + i] + rho * UH[k * NU + i];
         if (dual) {
-            S[L.MP + k * DST + i] = omr * S[L.MP + k * DST + i] + rho * mupn;
-            S[L.MM + k * DST + i] = omr * S[L.MM + k * DST + i] + rho * mumn;
-            S[L.PH + k * DST + i] = omr * S[L.PH + k * DST + i] + rho * phn;
-            if (i == IY) S[L.TH + k] = omr * S[L.TH + k] + rho * thn;
+            Sn[L.MP + k * DST + i] = omr * S[L.MP + k * DST + i] + rho * mupn;
+            Sn[L.MM + k * DST + i] = omr * S[L.MM + k * DST + i] + rho * mumn;
+            Sn[L.PH + k * DST + i] = omr * S[L.PH + k * DST + i] + rho * phn;
+            if (i == IY) Sn[L.TH + k] = omr * S[L.TH + k] + rho * thn;
         }
         __syncthreads();
+        S = Sn;
     };
 
     R *tape = a.tape + (long)b * (a.n_ckpt + a.ckpt) * L.len;
@@ -1028,7 +1041,11 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
                 XHB[k * 16 + i] = xb_;
             }
             if (isu) {
-                UHB[k * NU + i] = hub + R(2) * vub;
+                R ub_ = hub + R(2) * vub;
+                // the paper's set: the s box's derivative, taken in place (zero where it clamps)
+                if (!sets.mask && i == 3 && !(UP[k * NU + 3] >= slo && UP[k * NU + 3] <= shi))
+                    ub_ = R(0);
+                UHB[k * NU + i] = ub_;
                 nbu -= vub;
             }
             // derivative of the blocks: rb_k times the extrapolated values (zero rb off the
@@ -1047,13 +1064,16 @@ __global__ void __launch_bounds__(MAXT) grad_kernel(GradArgs<R> a)
                 nbmm += bb;
                 nbph += alpha * bb;
             }
-            __syncthreads();
-            // projections
-            if (node && i == 0 && (sets.mask & 15))
-                xproj_vjp<R>(sets, XP + k * 16, XB + k * 16, pxr, XH + k * 16,
-                             k == K - 1 && k > 0, XHB + k * 16);
-            if (node && i == 1)
-                accT += uproj_vjp<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi, UHB + k * NU);
+            // projections (the node-wise sets; with the paper's set only the s box, above)
+            if (sets.mask) {
+                __syncthreads();
+                if (node && i == 0 && (sets.mask & 15))
+                    xproj_vjp<R>(sets, XP + k * 16, XB + k * 16, pxr, XH + k * 16,
+                                 k == K - 1 && k > 0, XHB + k * 16);
+                if (node && i == 1)
+                    accT += uproj_vjp<R>(sets, UP + k * NU, UB + k * NU, pur, slo, shi,
+                                         UHB + k * NU);
+            }
             __syncthreads();
             // gradient step: x^pre = x~ - alpha g(x~, varphi, vartheta), likewise u
             if (isx) nbx += XHB[k * 16 + i] * (R(1) - alpha * wprox);
