@@ -178,3 +178,29 @@ def test_truncated_map_reproduces_last_iteration_and_is_smooth():
             d.append((oracle.truncated_map(cfg, x0, xf, p, K, theta + e, last, 200)
                       - oracle.truncated_map(cfg, x0, xf, p, K, theta - e, last, 200)) / (2 * h))
         np.testing.assert_allclose(d[0], d[1], rtol=1e-3, atol=1e-6)
+
+
+def test_prox_linear_iteration_creeps_instead_of_settling():
+    # Why the differentiated unit is the last SCP iteration and not an implicit adjoint of
+    # the whole solve (section "Sequential Convex Programming"): run on far past the paper's
+    # tolerances (PIPG to 1e-13 with up to 20,000 steps per subproblem), the scaled SCP step
+    # of a paper Monte Carlo run settles at a constant nonzero value while the trajectory
+    # stays dynamically feasible and drifts steadily (final mass up, flight time down), so the
+    # iteration has no isolated fixed point for the implicit function theorem to use.
+    inst = I.make_instances("F1", B=1)
+    base = dict(pipg_iters_max=20000, pipg_check_every=10, scp_tol=1e-12, feas_tol=1e-12,
+                pipg_eps_abs=1e-13, pipg_eps_rel=1e-13, early_exit=0)
+    out = {}
+    for n in (24, 36):
+        cfg = I.solver_settings("F1", scp_iters_max=n, **base)
+        out[n] = oracle.solve(cfg, inst["x0"], inst["xf"], inst["params"], inst["K"])
+    a, b = out[24], out[36]
+    print("\nstep %.3e %.3e, defect %.1e %.1e, m_f %+.2e, t_f %+.2e over 12 iterations" % (
+        a["step"][0], b["step"][0], a["defect_inf"][0], b["defect_inf"][0],
+        b["m_f"][0] - a["m_f"][0], b["t_f"][0] - a["t_f"][0]))
+    for r in (a, b):
+        assert r["defect_inf"][0] < 1e-7
+        assert r["step"][0] > 1e-5
+    assert abs(b["step"][0] - a["step"][0]) <= 0.05 * a["step"][0]
+    assert b["m_f"][0] - a["m_f"][0] > 5e-6
+    assert b["t_f"][0] - a["t_f"][0] < -1e-4
