@@ -1209,10 +1209,12 @@ static hipError_t launch_grad_typed(const Config &cfg, int nsteps, int ckpt, con
     }
     const int threads = qp_block_threads(cfg.kmax);
     const size_t smem = grad_smem_bytes_r(cfg.kmax, sizeof(R));
-    // the workgroup-size bound sets the register budget: a 320-lane bound (k_max <= 20) leaves
-    // room for the kernel's per-lane state without spilling
+    // the workgroup-size bound sets the register budget: the 320- and 512-lane bounds (k_max <=
+    // 20, <= 32) leave room for the kernel's per-lane state without spilling (FP32)
     if (threads <= 320)
         grad_kernel<R, 320><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
+    else if (threads <= 512)
+        grad_kernel<R, 512><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
     else if (threads <= 640)
         grad_kernel<R, 640><<<dim3(cfg.B), dim3(threads), smem, stream>>>(a);
     else

@@ -253,3 +253,17 @@ def test_rk4_reverse_sweep_matches_forward_tangents():
     print("reverse vs tangent: max rel diff %.3e" % _rel_err(J_rev, J_tan).max())
     assert _rel_err(J_rev, J_tan).max() <= 1e-10
     assert np.any(np.abs(J_rev[:, :, 17]) > 0)
+
+
+@pytest.mark.parametrize("dtype,K", [("f64", 30), ("f32", 30), ("f32", 40), ("f32", 48)])
+def test_grad_larger_node_counts(dtype, K):
+    # the workgroup-size variants of the gradient kernel beyond k_max 20: 512 lanes (K = 30),
+    # 640 (K = 40) and 1,024 (K = 48); FP64 to the finite-difference bar, FP32 to 1e-3
+    print("case: gradient, %s, K %d" % (dtype, K), flush=True)
+    cfg = I.solver_settings("C3", scp_iters_max=5, pipg_iters_max=400)
+    inst = I.make_instances("C3", B=3)
+    inst["K"][:] = K
+    if dtype == "f64":
+        _run(cfg, inst, list(range(3)), "f64", 1e-5, 1e-11)
+    else:
+        _run(cfg, inst, list(range(3)), "f32", 1e-3, 1e-4)
