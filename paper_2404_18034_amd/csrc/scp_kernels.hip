@@ -135,23 +135,30 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
 }
 
 // ------------------------------------------------------------------------------------------
-// Discretization: lane (b, k, c) integrates x and column c of [Phi_x | Phi_u- | Phi_u+] over
-// interval k with rk4_substeps RK4 steps; every lane of an interval integrates the same x
-// (identical instruction stream, so identical bits).
+// Discretization over interval k with rk4_substeps RK4 steps, in two kinds of workgroup.
+// Column workgroups (the first `col_blocks`): lane (b, k, c) integrates x and column c of
+// [Phi_x | Phi_u- | Phi_u+] in the working precision R and writes the prescaled column.
+// State workgroups (the rest): lane (b, k) integrates x alone with the state accumulated in
+// double (the model still in R), which keeps the propagated endpoint -- and so the defect
+// w^_k and the CTCS increment it writes -- free of R-rounding accumulated over the RK4
+// stages.  In FP32 the columns thus linearize along an FP32 copy of the state (a relative
+// difference of order 1e-7 in the linearization point), and the column lanes carry no FP64
+// arithmetic.  Every lane of an interval's columns integrates the same x (identical
+// instruction stream, so identical bits).
 // ------------------------------------------------------------------------------------------
 template <typename R, int NUC = NU>
-__global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blocks)
+__global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int col_blocks)
 {
     constexpr int COLS = Blk<NUC>::COLS, BLK = Blk<NUC>::SIZE;
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long per_b = (long)(a.kmax - 1) * COLS;
+    const bool column = (int)blockIdx.x < col_blocks;  // uniform over the workgroup
+    const long gid = (long)(column ? blockIdx.x : blockIdx.x - col_blocks) * blockDim.x + threadIdx.x;
+    const long per_b = (long)(a.kmax - 1) * (column ? COLS : 1);
     const int b = (int)(gid / per_b);
     if (b >= a.B) return;
-    const int rem = (int)(gid % per_b), k = rem / COLS, c = rem % COLS;
+    const int rem = (int)(gid % per_b), k = column ? rem / COLS : rem, c = column ? rem % COLS : 0;
     if (a.status[b] >= 0) return;
     const int K = a.K[b];
     if (k >= K - 1) return;
-    if (!need_blocks && c != 0) return;
 
     const R *p = a.params + (long)b * NP;
     const Vehicle<R> V = load_vehicle<R>(p);
@@ -159,16 +166,6 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const R *xk1 = xk + NX;
     const R *uk = a.u + ((long)b * a.kmax + k) * NUC;
     const R *uk1 = uk + NUC;
-
-    // the state is accumulated in double (the model and the variational columns run in R),
-    // which keeps the propagated endpoint -- and so the defect w^_k -- free of R-rounding
-    // accumulated over the RK4 stages
-    double x[NX];
-    R col[NX];
-    for (int i = 0; i < NX; ++i) {
-        x[i] = double(xk[i]);
-        col[i] = (c < NX && i == c) ? R(1) : R(0);
-    }
     R ua[NUC], ub[NUC];
     for (int i = 0; i < NUC; ++i) {
         ua[i] = uk[i];
@@ -179,68 +176,91 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int need_blo
     const bool plus = c >= NX + NUC;
 
     const R dtau = R(1.0 / double(K - 1));
+    const R km1 = R(K - 1);
     const int nsub = a.rk4_substeps;
     const R h = dtau / R(nsub);
     const R hh = R(0.5) * h;
     const R h6 = h / R(6);
-    const double hd = double(h), hhd = double(hh), h6d = double(h6);
-
-    // the stage input of the state is only taken in R: it is formed in double and rounded once
-    double accx[NX];
-    R xin[NX], cs[NX], accc[NX], fx[NX], fc[NX], u[NUC], du[NUC];
+    const long ib = (long)b * (a.kmax - 1) + k;
+    R u[NUC], du[NUC], fx[NX], fc[NX];
     double fy;
 
-    for (int n = 0; n < nsub; ++n) {
-        const R sig = R(n) * h;
-        for (int st = 0; st < 4; ++st) {
-            const R sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
-            const R lp = sg / dtau, lm = R(1) - lp;
-            for (int i = 0; i < NUC; ++i) {
-                u[i] = lm * ua[i] + lp * ub[i];
-                du[i] = (i == uj) ? (plus ? lp : lm) : R(0);
-            }
-            if (st == 0)
-                for (int i = 0; i < NX; ++i) xin[i] = R(x[i]);
-            const R *cin = st == 0 ? col : cs;
-            f_jvp<R, true, NUC>(V, xin, u, cin, du, fx, fy, fc);
-            fx[IY] = R(0);  // y is advanced with the double-precision fy below
-            if (st == 0) {
-                for (int i = 0; i < IY; ++i) accx[i] = double(fx[i]);
-                accx[IY] = fy;
-                for (int i = 0; i < NX; ++i) accc[i] = fc[i];
-            } else {
-                const R wgt = st == 3 ? R(1) : R(2);
-                for (int i = 0; i < IY; ++i) accx[i] += double(wgt) * double(fx[i]);
-                accx[IY] += double(wgt) * fy;
-                for (int i = 0; i < NX; ++i) accc[i] += wgt * fc[i];
-            }
-            if (st < 3) {
-                const R hs = st == 2 ? h : hh;
-                const double hsd = st == 2 ? hd : hhd;
-                for (int i = 0; i < IY; ++i) xin[i] = R(x[i] + hsd * double(fx[i]));
-                xin[IY] = R(x[IY] + hsd * fy);
-                for (int i = 0; i < NX; ++i) cs[i] = col[i] + hs * fc[i];
-            }
-        }
+    if (column) {
+        R x[NX], col[NX], xin[NX], cs[NX], accx[NX], accc[NX];
         for (int i = 0; i < NX; ++i) {
-            x[i] = x[i] + h6d * accx[i];
-            col[i] = col[i] + h6 * accc[i];
+            x[i] = xk[i];
+            col[i] = (c < NX && i == c) ? R(1) : R(0);
         }
-    }
-
-    const long ib = (long)b * (a.kmax - 1) + k;
-    if (need_blocks) {
+        for (int n = 0; n < nsub; ++n) {
+            const R sig = R(n) * h;
+            for (int st = 0; st < 4; ++st) {
+                const R sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
+                const R lp = sg * km1, lm = R(1) - lp;
+                for (int i = 0; i < NUC; ++i) {
+                    u[i] = lm * ua[i] + lp * ub[i];
+                    du[i] = (i == uj) ? (plus ? lp : lm) : R(0);
+                }
+                f_jvp<R, true, NUC>(V, st == 0 ? x : xin, u, st == 0 ? col : cs, du, fx, fy, fc);
+                const R wgt = (st == 0 || st == 3) ? R(1) : R(2);
+                for (int i = 0; i < NX; ++i) {
+                    accx[i] = st == 0 ? fx[i] : accx[i] + wgt * fx[i];
+                    accc[i] = st == 0 ? fc[i] : accc[i] + wgt * fc[i];
+                }
+                if (st < 3) {
+                    const R hs = st == 2 ? h : hh;
+                    for (int i = 0; i < NX; ++i) {
+                        xin[i] = x[i] + hs * fx[i];
+                        cs[i] = col[i] + hs * fc[i];
+                    }
+                }
+            }
+            for (int i = 0; i < NX; ++i) {
+                x[i] = x[i] + h6 * accx[i];
+                col[i] = col[i] + h6 * accc[i];
+            }
+        }
         R *dst = a.blocks + ib * BLK + c * CST;
         const double pc = c < NX ? a.px[c] : a.pu[(c - NX) % NUC];
         for (int i = 0; i < NX; ++i) dst[i] = R(double(col[i]) * pc * a.ipx[i]);
         dst[NX] = R(0);
+        return;
     }
-    if (c == 0) {
-        R *w = a.what + ib * DST;
-        for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) * a.ipx[i]);
-        w[NX] = R(0);
-        a.dy[ib] = x[IY] - double(xk[IY]);
+
+    // state lane: the stage input is only taken in R (formed in double, rounded once)
+    double x[NX], accx[NX];
+    R xin[NX];
+    for (int i = 0; i < NX; ++i) x[i] = double(xk[i]);
+    const double hd = double(h), hhd = double(hh), h6d = double(h6);
+    for (int n = 0; n < nsub; ++n) {
+        const R sig = R(n) * h;
+        for (int st = 0; st < 4; ++st) {
+            const R sg = st == 0 ? sig : (st == 3 ? sig + h : sig + hh);
+            const R lp = sg * km1, lm = R(1) - lp;
+            for (int i = 0; i < NUC; ++i) u[i] = lm * ua[i] + lp * ub[i];
+            if (st == 0)
+                for (int i = 0; i < NX; ++i) xin[i] = R(x[i]);
+            f_jvp<R, false, NUC>(V, xin, u, xin, u, fx, fy, fc);
+            fx[IY] = R(0);  // y is advanced with the double-precision fy below
+            if (st == 0) {
+                for (int i = 0; i < IY; ++i) accx[i] = double(fx[i]);
+                accx[IY] = fy;
+            } else {
+                const double wgt = st == 3 ? 1.0 : 2.0;
+                for (int i = 0; i < IY; ++i) accx[i] += wgt * double(fx[i]);
+                accx[IY] += wgt * fy;
+            }
+            if (st < 3) {
+                const double hsd = st == 2 ? hd : hhd;
+                for (int i = 0; i < IY; ++i) xin[i] = R(x[i] + hsd * double(fx[i]));
+                xin[IY] = R(x[IY] + hsd * fy);
+            }
+        }
+        for (int i = 0; i < NX; ++i) x[i] = x[i] + h6d * accx[i];
     }
+    R *w = a.what + ib * DST;
+    for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) * a.ipx[i]);
+    w[NX] = R(0);
+    a.dy[ib] = x[IY] - double(xk[IY]);
 }
 
 // Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
@@ -1629,7 +1649,9 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(0, false)) != hipSuccess) return e;
     }
-    const long nd = (long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS;
+    // discretization grid: column workgroups (when the blocks are needed), then state ones
+    const unsigned dcol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS + 127) / 128);
+    const unsigned dstate = (unsigned)(((long)cfg.B * (cfg.kmax - 1) + 127) / 128);
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
     // the lean variants where the node-wise sets are off: no stopping test can fire
@@ -1658,10 +1680,10 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
     const unsigned pgrid = (unsigned)(cfg.persistent_blocks < cfg.B ? cfg.persistent_blocks : cfg.B);
     for (int j = 1; j <= cfg.scp_iters_max + 1; ++j) {
         a.j = j;
-        const int need_blocks = j <= cfg.scp_iters_max ? 1 : 0;
+        // the last launch only tests the final reference: no blocks
+        const unsigned ncol = j <= cfg.scp_iters_max ? dcol : 0;
         if ((e = mark(1, true)) != hipSuccess) return e;
-        discretize_kernel<R, NUC><<<dim3((unsigned)((nd + 127) / 128)), dim3(128), 0, stream>>>(
-            a, need_blocks);
+        discretize_kernel<R, NUC><<<dim3(ncol + dstate), dim3(128), 0, stream>>>(a, (int)ncol);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mark(1, false)) != hipSuccess) return e;
         if ((e = mark(3, true)) != hipSuccess) return e;
@@ -1761,8 +1783,9 @@ static hipError_t discretize_at_typed(const Config &cfg, const void *x, const vo
     a.blocks = static_cast<R *>(ws.blocks);
     a.what = static_cast<R *>(ws.what);
     a.dy = ws.dy;
-    const long nd = (long)cfg.B * (cfg.kmax - 1) * COLS;
-    discretize_kernel<R><<<dim3((unsigned)((nd + 127) / 128)), dim3(128), 0, stream>>>(a, 1);
+    const unsigned ncol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * COLS + 127) / 128);
+    const unsigned nstate = (unsigned)(((long)cfg.B * (cfg.kmax - 1) + 127) / 128);
+    discretize_kernel<R><<<dim3(ncol + nstate), dim3(128), 0, stream>>>(a, (int)ncol);
     return hipGetLastError();
 }
 
