@@ -5,8 +5,8 @@
 //                      state and on one column of the variational equations (section
 //                      "Gradient of Discretized Dynamics"), then the prescaling of that
 //                      column (subsection "Convex Subproblem with Prescaling and
-//                      Preconditioning"); lane 0 of each interval also writes the scaled
-//                      defect w^_k and the CTCS increment.
+//                      Preconditioning"); separate state lanes, one per interval, write the
+//                      scaled defect w^_k and the CTCS increment.
 //   prepare_kernel     one workgroup per instance, one 16-lane row per node: convergence
 //                      test of the current reference and the customized power iteration
 //                      (FP64), which sets the PIPG step sizes.
