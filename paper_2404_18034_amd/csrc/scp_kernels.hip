@@ -369,6 +369,26 @@ struct ColStore<double> {
     }
 };
 
+// FP64 subproblem kernel of 512 lanes (K = 21..32): the column in LDS, transposed ([16][MAXT]:
+// entry q of every lane's column in one row, so that an entry is read by consecutive lanes
+// from consecutive 8-byte words, free of bank conflicts), which frees its 32 VGPRs for a
+// second workgroup per CU (the smaller workgroups keep it in registers: measured faster)
+template <int MAXT>
+struct ColLdsT {
+    double *slot;  // this lane's word of row 0
+    __device__ __forceinline__ void put(int q, double v) { slot[q * MAXT] = v; }
+    __device__ __forceinline__ void get_lo(double (&o)[8]) const
+    {
+        for (int q = 0; q < 8; ++q) o[q] = slot[q * MAXT];
+    }
+    __device__ __forceinline__ void get_hi(double (&o)[8]) const
+    {
+        for (int q = 0; q < 8; ++q) o[q] = slot[(8 + q) * MAXT];
+    }
+};
+template <typename R, int MAXT>
+constexpr bool col_in_lds_t = sizeof(R) == 8 && MAXT == 512;
+
 // Exchange arrays of the PIPG iteration for a workgroup of at most MAXT lanes, one value per
 // lane (row stride 16), so that every access of the iteration is this lane's slot or a slot
 // of the row above or below, at a compile-time offset from a per-lane address register:
@@ -940,7 +960,9 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // stopping-test maxima: two sets of six bit patterns (32-bit for FP32, 64-bit for FP64)
     using Bits = decltype(max_bits(R(0)));
     Bits *chk = reinterpret_cast<Bits *>(red + 128);               // [2][8]
-    R *myCol = reinterpret_cast<R *>(red + 144) + t * ColStore<R>::LDS_STRIDE;  // FP32: [KR * 16][20]
+    // the column of A^-: FP32 [KR * 16][20]; FP64 at 512 lanes [16][MAXT]
+    R *myCol = reinterpret_cast<R *>(red + 144) +
+               (col_in_lds_t<R, MAXT> ? t : t * ColStore<R>::LDS_STRIDE);
     // SD: partial sums of the fresh dilation values, one per wave (the reduction scratch is
     // idle during PIPG)
     R *sdil = reinterpret_cast<R *>(red);  // [KR / 4]
@@ -961,7 +983,8 @@ __device__ __forceinline__ void subproblem_body(const Args<R> &a, const int b,
     // -------------------- load the subproblem into registers --------------------
     const R *blk = a.blocks + (long)b * (kmax - 1) * BLK;
     R rowA[NX], rowBm[NUC], rowBp[NUC];
-    ColStore<R> colA{myCol};
+    using ColT = std::conditional_t<col_in_lds_t<R, MAXT>, ColLdsT<MAXT>, ColStore<R>>;
+    ColT colA{myCol};
     // colA: column i of [A^-_k ; e_y^T] (transposed product: entry 15 is the coefficient of
     // -theta_k in the y lane's gradient); row*: row i of [A^-_k | B^-_k | B^+_k] (forward
     // product; on lane 15 the CTCS row)
@@ -1472,8 +1495,10 @@ static size_t qp_smem_bytes_at(int maxt, int kmax, size_t rsize, bool lean = fal
 {
     const size_t KR = (size_t)(kmax + 3) / 4 * 4;
     const size_t stage = lean ? qp_stage_bytes<true>(maxt, rsize) : qp_stage_bytes<false>(maxt, rsize);
-    const size_t col = rsize == 4 ? ColStore<float>::LDS_STRIDE : ColStore<double>::LDS_STRIDE;
-    return stage + sizeof(double) * 144 + rsize * KR * 16 * col;
+    // the column of A^-: FP32 [KR * 16][20]; FP64 [16][maxt] at 512 lanes, else registers
+    const size_t col = rsize == 4 ? sizeof(float) * KR * 16 * ColStore<float>::LDS_STRIDE
+                                  : (maxt == 512 ? sizeof(double) * 16 * (size_t)maxt : 0);
+    return stage + sizeof(double) * 144 + col;
 }
 size_t qp_smem_bytes(int kmax, size_t rsize) { return qp_smem_bytes_at(qp_maxt(kmax), kmax, rsize); }
 // dynamic LDS bytes of the preparation kernel (rsize: the working precision, psize: that of
@@ -1528,7 +1553,11 @@ static void launch_subproblem_v(int occupancy, int B, int threads, size_t smem, 
             }
         }
     }
-    subproblem_kernel<R, MAXT, 1, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
+    // FP64, thrust only, 512 lanes, lean without a test: bounded for four waves per SIMD (128
+    // VGPRs, a few spills; the column sits in LDS), two 8-wave workgroups per CU at K = 30
+    // where the compiler's 138 VGPRs hold one
+    constexpr int W64 = (sizeof(R) == 8 && LEAN == 1 && MAXT == 512 && NUC == NU) ? 4 : 1;
+    subproblem_kernel<R, MAXT, W64, false, NUC, LEAN><<<dim3(B), dim3(threads), smem, stream>>>(a);
 }
 // smem must be the dynamic LDS of the variant launched (qp_smem_bytes_at with `lean` > 0);
 // lean: 0 the general kernel, 1 the lean one without a stopping test, 2 with it (FP32,
