@@ -780,16 +780,19 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
     // neighbouring rows pass through this lane's LDS slots.  Two barriers per step.  The
     // iterate and the products are in P (FP64 by default: the blocks are widened term by
     // term); the squared norm is summed over each row in P and over the rows in FP64; sigma
-    // and the stopping test are FP64.  1/sigma is formed once per step and multiplied.
+    // and the stopping test are FP64.  Each step takes sqrt and 1/sqrt of the squared norm from
+    // the hardware reciprocal square root refined by two Newton steps (a few ulp, about a third
+    // of the instructions of a correctly rounded square root and division); 1/sigma multiplies.
     const int KR = (kmax + 3) / 4 * 4;
     const bool thlane = dual && i == IY;
     P zx = isx ? P(1) : P(0), zu = uval ? P(1) : P(0);
     P dmu = P(0);  // mu+ - mu- of this dynamics row
-    double sigma;
+    double sigma, isig;
     {
         double acc[1] = {(isx ? 1.0 : 0.0) + ((node && i < NUC) ? 1.0 : 0.0) + (dual ? 2.0 : 0.0)};
         block_reduce<1, false>(acc, red);
         sigma = sqrt(acc[0]);
+        isig = 1.0 / sigma;
     }
     sl[Lds::Z] = zx;
     sl[Lds::U] = zu;
@@ -832,7 +835,7 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
             }
             r += dmu;
             // 1/sigma once per step (uniform), rounded to P
-            const P isg = P(1.0 / sigma);
+            const P isg = P(isig);
             ph = dual ? r * isg : P(0);
             thv = thlane ? (zxn - zx) * isg : P(0);
         }
@@ -886,11 +889,16 @@ __device__ __forceinline__ void prepare_body(const Args<R> &a, const int b, unsi
         __syncthreads();
         double s2 = red[0];
         for (int w = 1; w < nw; ++w) s2 += red[w];
-        sstar = sqrt(s2);
+        // s2 > 0: the dynamics rows hold -I on x_{k+1}, so H^T is injective and z' != 0
+        double y = __builtin_amdgcn_rsq(s2);  // approximate; two Newton steps reach rounding level
+        for (int nwt = 0; nwt < 2; ++nwt) y = fma(0.5 * y, fma(-s2 * y, y, 1.0), y);
+        sstar = s2 * y;
         if (fabs(sstar - sigma) <= a.power_eps_abs + a.power_eps_rel * fmax(sstar, sigma))
             break;
-        else if (it < a.power_iters_max)
+        else if (it < a.power_iters_max) {
             sigma = sstar;
+            isig = y;
+        }
     }
     sigma = (1.0 + a.power_buff) * sstar;
     if (t == 0) {
