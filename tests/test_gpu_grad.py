@@ -194,6 +194,24 @@ def test_record_matches_oracle_last_iteration():
     s.close()
 
 
+def test_record_f32_sigma_near_oracle():
+    """FP32 path: the recorded power-iteration estimate of the last subproblem (iterate and
+    products in FP64 over the FP32 blocks; square root and reciprocal by a refined reciprocal
+    square root) against the FP64 oracle's.  The FP32 reference and blocks differ from the
+    oracle's by FP32 rounding (about 1e-6 relative), so sigma agrees to 1e-5 relative."""
+    import torch
+    cfg = I.solver_settings("C3", scp_iters_max=3, pipg_iters_max=300)
+    inst = I.make_instances("C3", B=6)
+    s = api.BatchSolver(cfg, dtype="f32", k_max=20, max_batch=6)
+    prob = s.to_device(inst)
+    sol, last = s.solve_record_into(prob, s.alloc_solution(6), s.alloc_lastiter(6))
+    torch.cuda.synchronize()
+    lasts = _oracle_last(cfg, inst, range(6))
+    for b, L in enumerate(lasts):
+        assert float(last["sigma"][b]) == pytest.approx(L["sigma"], rel=1e-5), b
+    s.close()
+
+
 def test_autograd_function_matches_grad_entry_point():
     import torch
     cfg = I.solver_settings("C3", scp_iters_max=4, pipg_iters_max=300)
