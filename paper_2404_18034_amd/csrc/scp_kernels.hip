@@ -6,7 +6,8 @@
 //                      "Gradient of Discretized Dynamics"), then the prescaling of that
 //                      column (subsection "Convex Subproblem with Prescaling and
 //                      Preconditioning"); separate state lanes, one per interval, write the
-//                      scaled defect w^_k and the CTCS increment.
+//                      scaled defect w^_k, the CTCS increment and the y column of A^- (e_y:
+//                      no entry of f reads y, so that column is not integrated).
 //   prepare_kernel     one workgroup per instance, one 16-lane row per node: convergence
 //                      test of the current reference and the customized power iteration
 //                      (FP64), which sets the PIPG step sizes.
@@ -149,13 +150,17 @@ __global__ void __launch_bounds__(256) init_kernel(Args<R> a)
 template <typename R, int NUC = NU>
 __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int col_blocks)
 {
-    constexpr int COLS = Blk<NUC>::COLS, BLK = Blk<NUC>::SIZE;
+    constexpr int BLK = Blk<NUC>::SIZE;
+    // integrated columns: all but the y column of A^- (no entry of f reads y, so that column
+    // of the transition matrix stays e_y; the state lane writes it)
+    constexpr int ICOLS = Blk<NUC>::COLS - 1;
     const bool column = (int)blockIdx.x < col_blocks;  // uniform over the workgroup
     const long gid = (long)(column ? blockIdx.x : blockIdx.x - col_blocks) * blockDim.x + threadIdx.x;
-    const long per_b = (long)(a.kmax - 1) * (column ? COLS : 1);
+    const long per_b = (long)(a.kmax - 1) * (column ? ICOLS : 1);
     const int b = (int)(gid / per_b);
     if (b >= a.B) return;
-    const int rem = (int)(gid % per_b), k = column ? rem / COLS : rem, c = column ? rem % COLS : 0;
+    const int rem = (int)(gid % per_b), k = column ? rem / ICOLS : rem;
+    const int ci = column ? rem % ICOLS : 0, c = ci < IY ? ci : ci + 1;
     if (a.status[b] >= 0) return;
     const int K = a.K[b];
     if (k >= K - 1) return;
@@ -261,6 +266,10 @@ __global__ void __launch_bounds__(128) discretize_kernel(Args<R> a, int col_bloc
     for (int i = 0; i < NX; ++i) w[i] = R((x[i] - double(xk1[i])) * a.ipx[i]);
     w[NX] = R(0);
     a.dy[ib] = x[IY] - double(xk[IY]);
+    // the y column of the prescaled A^-: e_y, scaled as the integrated columns are
+    R *ycol = a.blocks + ib * BLK + IY * CST;
+    for (int i = 0; i < NX; ++i) ycol[i] = R(double(i == IY ? R(1) : R(0)) * a.px[IY] * a.ipx[i]);
+    ycol[NX] = R(0);
 }
 
 // Square root and reciprocal of the generic (FP64) projection: IEEE arithmetic.  The FP32
@@ -1687,7 +1696,7 @@ static hipError_t launch_typed(const Config &cfg, const Problem &prob, const Sol
         if ((e = mark(0, false)) != hipSuccess) return e;
     }
     // discretization grid: column workgroups (when the blocks are needed), then state ones
-    const unsigned dcol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * Blk<NUC>::COLS + 127) / 128);
+    const unsigned dcol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * (Blk<NUC>::COLS - 1) + 127) / 128);
     const unsigned dstate = (unsigned)(((long)cfg.B * (cfg.kmax - 1) + 127) / 128);
     const int qthreads = qp_block_threads(cfg.kmax);
     const int maxt = qp_maxt(cfg.kmax);
@@ -1820,7 +1829,7 @@ static hipError_t discretize_at_typed(const Config &cfg, const void *x, const vo
     a.blocks = static_cast<R *>(ws.blocks);
     a.what = static_cast<R *>(ws.what);
     a.dy = ws.dy;
-    const unsigned ncol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * COLS + 127) / 128);
+    const unsigned ncol = (unsigned)(((long)cfg.B * (cfg.kmax - 1) * (COLS - 1) + 127) / 128);
     const unsigned nstate = (unsigned)(((long)cfg.B * (cfg.kmax - 1) + 127) / 128);
     discretize_kernel<R><<<dim3(ncol + nstate), dim3(128), 0, stream>>>(a, (int)ncol);
     return hipGetLastError();
